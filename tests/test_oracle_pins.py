@@ -1,0 +1,391 @@
+"""Pins of the FP64 oracle against facts fixed by the thesis and by
+mathematics, independent of the oracle's own code.
+
+Each test names the passage it follows.  A plausible slip in the oracle (a
+dropped term, a wrong sign or index, a transposed operand, a wrong tie rule,
+a missed bound) fails at least one of them:
+
+* footprint enumeration in exact rational arithmetic from the rect interval
+  (-1/(2 beta), 1/(2 beta)] and the support interval (-S/2, S/2]
+  (Section 2.1.4 helper functions; Section 2.3.4)  -> index, tie, tap, bounds;
+* delta kernel at integer cells (NN interpolation, Section 2.4.1)
+  -> scatter addressing, polarisation layout;
+* the equivalence theorem (Section 2.4.2): NN onto the beta-oversampled grid
+  followed by a discrete convolution equals direct gridding  -> tap selection
+  and orientation, separable and W-projection, conjugation for w < 0;
+* component analysis (Section 2.3.2): with one common fractional offset the
+  inverse DFT of the grid equals the direct Fourier sum times l_co
+  -> the whole map, against an independent Fourier sum;
+* Hermitian mirror, linearity, adjoint identity  -> degrid vs grid.
+"""
+from fractions import Fraction
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Geometry
+from paper_2111_04141_amd import workload as W
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------------------
+# index rule
+# ---------------------------------------------------------------------------
+
+def _brute_axis(x: float, n: int, beta: int, S: int):
+    """Footprint of a record at cell position x, by enumeration over cells.
+
+    The record's position on the beta-oversampled grid is P = beta*x, formed
+    in FP64 (exact for a power-of-two beta; otherwise the one rounding the
+    index rule makes) and then taken exactly as a rational.  Nearest pixel:
+    the q with rect_beta((q - P)/beta) = 1, i.e. -1/2 < q - P <= 1/2.
+    Footprint: cells k with offset d = k - q/beta in (-S/2, S/2]; the tap of
+    cell k sits at table index beta*S/2 + beta*d.
+    """
+    P = Fraction(float(x) * beta)
+    q = None
+    for cand in range(math.floor(P) - 2, math.floor(P) + 3):
+        if -Fraction(1, 2) < cand - P <= Fraction(1, 2):
+            assert q is None
+            q = cand
+    assert q is not None
+    X = Fraction(x)
+    cells, taps = [], []
+    for k in range(math.floor(X) - S - 3, math.floor(X) + S + 4):
+        d = k - Fraction(q, beta)
+        if -Fraction(S, 2) < d <= Fraction(S, 2):
+            cells.append(k)
+            taps.append(int(beta * S // 2 + beta * d))
+    valid = cells[0] >= 0 and cells[-1] <= n - 1
+    return q, cells, taps, valid
+
+
+@pytest.mark.parametrize("beta,S", [(8, 7), (4, 8), (2, 1), (1, 6), (3, 4), (16, 5)])
+def test_index_rule_matches_rect_enumeration(beta, S):
+    n = 64
+    rng = _rng(11)
+    xs = list(rng.uniform(-4, n + 4, 300))
+    # exact ties of the nearest-pixel rule (x = (q + 1/2)/beta) and grid edges
+    xs += [(q + 0.5) / beta for q in range(0, n * beta, 37)]
+    xs += [S / 2 - 0.5, S / 2, S / 2 + 0.25, n - S / 2, n - S / 2 - 0.5, 0.0, n / 2]
+    scale = 1.0
+    # coord chosen so that coord*scale + n/2 == x exactly
+    uvw = np.array([[x - n // 2, 0.0, 0.0] for x in xs])
+    g = Geometry(nu=n, nv=n, beta=beta, scale_u=scale, scale_v=scale, support=S)
+    ix = oracle.index(g, uvw)
+    for r, x in enumerate(xs):
+        xr = (x - n // 2) * scale + n // 2
+        q, cells, taps, valid = _brute_axis(xr, n, beta, S)
+        assert len(cells) == S
+        assert ix["k_lo_u"][r] == cells[0], (x, q)
+        assert ix["o_u"][r] + 1 == taps[0]
+        assert all(t - taps[0] == i * beta for i, t in enumerate(taps))
+        vv = _brute_axis(n / 2, n, beta, S)[3]
+        assert bool(ix["valid"][r]) == (valid and vv)
+    assert ix["nskipped"] == int((ix["valid"] == 0).sum())
+
+
+def test_index_worked_example_and_tie():
+    """S = 7, beta = 8, x = 100: q = 800, cells 97..103, first tap 4 (the
+    centre tap 28 lands on cell 100), o = 3.  x = 100 + 1/16 is an exact tie
+    of the nearest-pixel rule: the half-open rect sends it up to q = 801."""
+    g = Geometry(nu=1024, nv=1024, beta=8, scale_u=1.0, scale_v=1.0, support=7)
+    uvw = np.array([[100.0 - 512, 0.0, 0.0], [100.0625 - 512, 0.0, 0.0]])
+    ix = oracle.index(g, uvw)
+    assert ix["k_lo_u"][0] == 97 and ix["o_u"][0] == 3
+    # q = 801 -> k_lo = floor((801 - 28)/8) + 1 = 97, t0 = 776 - 801 + 28 = 3
+    assert ix["k_lo_u"][1] == 97 and ix["o_u"][1] == 2
+    assert ix["k_lo_v"][0] == 512 - 3 and ix["o_v"][0] == 3
+
+
+def test_index_nonfinite_and_out_of_bounds_are_skipped():
+    g = Geometry(nu=32, nv=32, beta=4, scale_u=1.0, scale_v=1.0, support=6)
+    uvw = np.array([[0, 0, 0], [np.nan, 0, 0], [0, np.inf, 0], [0, 0, np.nan],
+                    [-13.0, 0, 0], [-12.9, 0, 0], [12.9, 0, 0], [13.0, 0, 0], [1e300, 0, 0]])
+    ix = oracle.index(g, uvw)
+    # x = 16 + u; footprint needs q/4 - 3 < k_lo and k_lo + 5 <= 31
+    want = []
+    for row in uvw:
+        if not np.all(np.isfinite(row)):
+            want.append(0)
+            continue
+        _, cells, _, ok = _brute_axis(float(row[0]) + 16, 32, 4, 6)
+        want.append(int(ok))
+    assert list(ix["valid"]) == want
+    assert ix["nskipped"] == want.count(0)
+    G, sk = oracle.grid(g, W.pswf_taps(6, 4), uvw, np.ones((len(uvw), 1)))
+    assert sk == want.count(0)
+
+
+def test_wproj_plane_rule():
+    """plane = round-half-up(|w| * inv_dw), clamped to the last plane;
+    w < 0 selects the conjugate table."""
+    sup = [2, 4, 6]
+    g = Geometry(nu=32, nv=32, beta=2, scale_u=1.0, scale_v=1.0, kind="wproj",
+                 plane_support=sup, plane_offset=[0, 25, 106], inv_dw=0.5)
+    ws = [0.0, 0.99, 1.0, 1.01, -1.0, 2.99, 3.0, 100.0, -100.0]
+    uvw = np.array([[0.0, 0.0, w] for w in ws])
+    ix = oracle.index(g, uvw)
+    assert list(ix["plane"]) == [0, 0, 1, 1, 1, 1, 2, 2, 2]
+
+
+# ---------------------------------------------------------------------------
+# delta kernel: NN interpolation at integer cells
+# ---------------------------------------------------------------------------
+
+def test_delta_kernel_is_cell_sum():
+    """S = 1 with the table [0, 1, 0] at beta = 2 is nearest-neighbour
+    interpolation; records at integer cells land exactly on their cell."""
+    n, npol = 48, 4
+    rng = _rng(3)
+    nrec = 2000
+    ku = rng.integers(0, n, nrec)
+    kv = rng.integers(0, n, nrec)
+    uvw = np.stack([ku - n // 2, kv - n // 2, np.zeros(nrec)], 1).astype(np.float64)
+    vis = (rng.integers(-8, 9, (nrec, npol)) + 1j * rng.integers(-8, 9, (nrec, npol)))
+    g = Geometry(nu=n, nv=n, beta=2, scale_u=1.0, scale_v=1.0, support=1)
+    G, sk = oracle.grid(g, np.array([0.0, 1.0, 0.0]), uvw, vis)
+    assert sk == 0
+    want = np.zeros((npol, n, n), np.complex128)
+    for p in range(npol):
+        np.add.at(want[p], (kv, ku), vis[:, p])
+    assert np.array_equal(G, want)
+    # and the adjoint reads the cell back
+    V, _ = oracle.degrid(g, np.array([0.0, 1.0, 0.0]), uvw, want)
+    assert np.array_equal(V, want[:, kv, ku].T)
+
+
+# ---------------------------------------------------------------------------
+# equivalence theorem (Section 2.4.2)
+# ---------------------------------------------------------------------------
+
+def _nn_then_convolve(n, beta, uvw_cells, vis, kernel_of_record, S_of_record):
+    """Algorithm "Equivalent Algorithm for Convolutional Gridding with GCF
+    Oversampling": (1) NN-interpolate every record to the beta-oversampled
+    grid (rect interval (-1/(2beta), 1/(2beta)]), kept per kernel class;
+    (2) convolve each class's oversampled grid with its kernel C sampled every
+    1/beta and keep the samples at integer cells.  C(d) for an offset d in
+    cells is table[beta*S/2 + beta*d] on (-S/2, S/2] and 0 elsewhere."""
+    npol = vis.shape[1]
+    out = np.zeros((npol, n, n), np.complex128)
+    classes = {}
+    for r in range(uvw_cells.shape[0]):
+        X = [Fraction(float(uvw_cells[r, 0])), Fraction(float(uvw_cells[r, 1]))]
+        q = [math.floor(c * beta + Fraction(1, 2)) for c in X]
+        # check the rect condition independently of the floor formula
+        for c, qq in zip(X, q):
+            assert -Fraction(1, 2 * beta) < Fraction(qq, beta) - c <= Fraction(1, 2 * beta)
+        key = kernel_of_record(r)
+        nn = classes.setdefault(key, {})
+        nn[(q[0], q[1])] = nn.get((q[0], q[1]), 0) + vis[r]
+    for key, nn in classes.items():
+        table, S = key[0], key[1]
+        K = _KERNELS[table]
+        conj = key[2]
+        for (qu, qv), val in nn.items():
+            for kv in range(n):
+                dv = Fraction(kv) - Fraction(qv, beta)
+                if not (-Fraction(S, 2) < dv <= Fraction(S, 2)):
+                    continue
+                tv = int(beta * S // 2 + beta * dv)
+                for ku in range(n):
+                    du = Fraction(ku) - Fraction(qu, beta)
+                    if not (-Fraction(S, 2) < du <= Fraction(S, 2)):
+                        continue
+                    tu = int(beta * S // 2 + beta * du)
+                    c = K(tu, tv)
+                    if conj:
+                        c = np.conj(c)
+                    out[:, kv, ku] += c * val
+    return out
+
+
+_KERNELS = {}
+
+
+def test_equivalence_theorem_separable_exact():
+    """Dyadic taps and small-integer visibilities make every product and sum
+    exact in FP64, so the two algorithms must agree bit for bit."""
+    n, beta, S, npol = 24, 4, 5, 2
+    rng = _rng(5)
+    taps = rng.integers(1, 16, beta * S + 1) / 16.0
+    _KERNELS["sep"] = lambda tu, tv: taps[tu] * taps[tv]
+    nrec = 60
+    pos = rng.uniform(S / 2 + 1, n - S / 2 - 1, (nrec, 2))
+    # include exact ties of the NN rule
+    pos[:6, 0] = (np.arange(6) + 40 + 0.5) / beta
+    uvw = np.concatenate([pos - n // 2, np.zeros((nrec, 1))], 1)
+    vis = rng.integers(-4, 5, (nrec, npol)) + 1j * rng.integers(-4, 5, (nrec, npol))
+    g = Geometry(nu=n, nv=n, beta=beta, scale_u=1.0, scale_v=1.0, support=S)
+    G, sk = oracle.grid(g, taps, uvw, vis)
+    assert sk == 0
+    want = _nn_then_convolve(n, beta, pos, vis, lambda r: ("sep", S, False), None)
+    assert np.array_equal(G, want)
+
+
+def test_equivalence_theorem_wproj_exact():
+    n, beta, npol = 20, 2, 3
+    rng = _rng(6)
+    sup = [2, 4, 6]
+    planes = []
+    for p, S in enumerate(sup):
+        m = beta * S + 1
+        planes.append((rng.integers(-8, 9, (m, m)) + 1j * rng.integers(-8, 9, (m, m))) / 8.0)
+    offs = np.cumsum([0] + [pl.size for pl in planes[:-1]])
+    taps = np.concatenate([pl.ravel() for pl in planes])
+    for p in range(3):
+        _KERNELS[f"w{p}"] = (lambda pl: (lambda tu, tv: pl[tv, tu]))(planes[p])
+    nrec = 40
+    pos = rng.uniform(4, n - 4, (nrec, 2))
+    w = rng.uniform(-3.2, 3.2, nrec)
+    uvw = np.concatenate([pos - n // 2, w[:, None]], 1)
+    inv_dw = 0.8
+    plane = np.minimum(2, np.floor(np.abs(w) * inv_dw + 0.5)).astype(int)
+    vis = rng.integers(-4, 5, (nrec, npol)) + 1j * rng.integers(-4, 5, (nrec, npol))
+    g = Geometry(nu=n, nv=n, beta=beta, scale_u=1.0, scale_v=1.0, kind="wproj",
+                 plane_support=sup, plane_offset=offs, inv_dw=inv_dw)
+    G, sk = oracle.grid(g, taps, uvw, vis)
+    assert sk == 0
+    want = _nn_then_convolve(n, beta, pos, vis,
+                             lambda r: (f"w{plane[r]}", sup[plane[r]], bool(w[r] < 0)), None)
+    assert np.array_equal(G, want)
+
+
+# ---------------------------------------------------------------------------
+# component analysis: equal fractional offsets are gridded without aliasing
+# ---------------------------------------------------------------------------
+
+def _inverse_dft_of_grid(G, n):
+    """image[y, x] = sum_k G[kv, ku] exp(+j2pi((ku-n/2) l + (kv-n/2) m)),
+    l = (x - n/2)/n (the same sign and origin as the direct sum)."""
+    k = np.arange(n) - n // 2
+    l = (np.arange(n) - n // 2) / n
+    E = np.exp(2j * np.pi * np.outer(l, k))       # [x, ku]
+    return E @ G @ E.T                             # [y, x]
+
+
+def _direct_sum(pos, F, n):
+    l = (np.arange(n) - n // 2) / n
+    Eu = np.exp(2j * np.pi * np.outer(pos[:, 0], l))  # [r, x]
+    Ev = np.exp(2j * np.pi * np.outer(pos[:, 1], l))  # [r, y]
+    return (Ev * F[:, None]).T @ Eu
+
+
+@pytest.mark.parametrize("kind", ["separable", "wproj"])
+def test_equal_offset_exactness_against_direct_sum(kind):
+    """All records at k + delta with a common delta: the inverse DFT of the
+    grid equals the direct Fourier sum times l_co(delta, x) =
+    sum_m C(m - delta) exp(+j2pi (m - delta) . x) (component analysis)."""
+    n, beta = 32, 4
+    rng = _rng(7)
+    nrec = 200
+    du, dv = 3 / beta - 0.5, -1 / beta   # multiples of 1/beta in [-1/2, 1/2)
+    ku = rng.integers(6, n - 6, nrec)
+    kv = rng.integers(6, n - 6, nrec)
+    pos = np.stack([ku + du, kv + dv], 1) - n // 2      # cells from the centre
+    F = rng.standard_normal(nrec) + 1j * rng.standard_normal(nrec)
+    if kind == "separable":
+        S = 7 if beta % 2 == 0 else 6
+        taps = W.pswf_taps(S, beta)
+        g = Geometry(nu=n, nv=n, beta=beta, scale_u=1.0, scale_v=1.0, support=S)
+        C2 = np.outer(taps, taps)                        # [tv, tu]
+        uvw = np.concatenate([pos, np.zeros((nrec, 1))], 1)
+    else:
+        S = 6
+        m = beta * S + 1
+        Kt = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+        taps = Kt.ravel()
+        g = Geometry(nu=n, nv=n, beta=beta, scale_u=1.0, scale_v=1.0, kind="wproj",
+                     plane_support=[S], plane_offset=[0], inv_dw=1.0)
+        C2 = Kt
+        uvw = np.concatenate([pos, np.full((nrec, 1), 0.25)], 1)
+    G, sk = oracle.grid(g, taps, uvw, F)
+    assert sk == 0
+    img = _inverse_dft_of_grid(G[0], n)
+    dft = _direct_sum(pos, F, n)
+    # l_co(delta, x): sum over the footprint offsets m - delta in (-S/2, S/2]
+    l = (np.arange(n) - n // 2) / n
+    offs_u = [Fraction(mm) - Fraction(du).limit_denominator(64) for mm in range(-S - 1, S + 2)]
+    offs_u = [o for o in offs_u if -Fraction(S, 2) < o <= Fraction(S, 2)]
+    offs_v = [Fraction(mm) - Fraction(dv).limit_denominator(64) for mm in range(-S - 1, S + 2)]
+    offs_v = [o for o in offs_v if -Fraction(S, 2) < o <= Fraction(S, 2)]
+    lco = np.zeros((n, n), np.complex128)
+    for ov in offs_v:
+        tv = int(beta * S // 2 + beta * ov)
+        for ou in offs_u:
+            tu = int(beta * S // 2 + beta * ou)
+            lco += C2[tv, tu] * np.outer(np.exp(2j * np.pi * float(ov) * l),
+                                         np.exp(2j * np.pi * float(ou) * l))
+    want = dft * lco
+    err = np.linalg.norm(img - want) / np.linalg.norm(want)
+    assert err < 1e-12, err
+
+
+# ---------------------------------------------------------------------------
+# invariants: Hermitian mirror, linearity, adjoint
+# ---------------------------------------------------------------------------
+
+def test_hermitian_mirror():
+    """For a symmetric real kernel whose end taps are zero, gridding
+    {(-xi, conj V)} gives the conjugate of the grid of {(xi, V)} reflected
+    through the centre cell.  Positions are dyadic and away from NN ties, so
+    n/2 +- u is exact and the nearest pixels mirror exactly."""
+    n, beta, S = 64, 8, 7
+    taps = W.pswf_taps(S, beta)
+    assert np.array_equal(taps, taps[::-1]) and taps[0] == 0
+    rng = _rng(8)
+    nrec = 300
+    u = (rng.integers(-20 * 2 ** 10, 20 * 2 ** 10, (nrec, 2)) + 0.3) / 2 ** 10
+    uvw = np.concatenate([u, np.zeros((nrec, 1))], 1)
+    vis = rng.standard_normal((nrec, 4)) + 1j * rng.standard_normal((nrec, 4))
+    g = Geometry(nu=n, nv=n, beta=beta, scale_u=1.0, scale_v=1.0, support=S)
+    G1, _ = oracle.grid(g, taps, uvw, vis)
+    G2, _ = oracle.grid(g, taps, -uvw, np.conj(vis))
+    refl = np.conj(G1[:, ::-1, ::-1])[:, :-1, :-1]     # cell k -> n - k, k >= 1
+    assert np.array_equal(G2[:, 1:, 1:], refl)
+
+
+def test_linearity_and_adjoint_separable_and_wproj():
+    rng = _rng(9)
+    n = 40
+    cases = []
+    S = 7
+    cases.append((Geometry(nu=n, nv=n, beta=8, scale_u=0.9, scale_v=1.1, support=S),
+                  W.pswf_taps(S, 8)))
+    bank = W.wproj_bank(4, 8, 14, 4, w_absmax=30.0, fov_rad=0.2)
+    cases.append((Geometry(nu=n, nv=n, beta=4, scale_u=1.0, scale_v=1.0, kind="wproj",
+                           plane_support=bank.supports, plane_offset=bank.offsets,
+                           inv_dw=bank.inv_dw), bank.taps))
+    for g, taps in cases:
+        nrec = 150
+        uvw = np.concatenate([rng.uniform(-12, 12, (nrec, 2)), rng.uniform(-40, 40, (nrec, 1))], 1)
+        x = rng.standard_normal((nrec, 4)) + 1j * rng.standard_normal((nrec, 4))
+        y = rng.standard_normal((nrec, 4)) + 1j * rng.standard_normal((nrec, 4))
+        a, b = 0.7 - 0.2j, -1.3 + 0.5j
+        Gx, _ = oracle.grid(g, taps, uvw, x)
+        Gy, _ = oracle.grid(g, taps, uvw, y)
+        Gxy, _ = oracle.grid(g, taps, uvw, a * x + b * y)
+        assert np.allclose(Gxy, a * Gx + b * Gy, rtol=0, atol=1e-12 * np.abs(Gxy).max())
+        Z = rng.standard_normal((4, n, n)) + 1j * rng.standard_normal((4, n, n))
+        Vz, _ = oracle.degrid(g, taps, uvw, Z)
+        lhs = np.vdot(Z, Gx)            # <G x, Z>
+        rhs = np.vdot(Vz, x)            # <x, G^H Z>  (vdot conjugates the first)
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_window_equals_full_grid_slice():
+    g = Geometry(nu=50, nv=50, beta=8, scale_u=1.0, scale_v=1.0, support=7)
+    rng = _rng(10)
+    uvw = np.concatenate([rng.uniform(-20, 20, (200, 2)), np.zeros((200, 1))], 1)
+    vis = rng.standard_normal((200, 4)) + 1j * rng.standard_normal((200, 4))
+    taps = W.pswf_taps(7, 8)
+    G, _ = oracle.grid(g, taps, uvw, vis)
+    Gw, _ = oracle.grid(g, taps, uvw, vis, window=(11, 17, 9, 13))
+    assert np.array_equal(Gw, G[:, 17:30, 11:20])
