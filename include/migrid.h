@@ -1,0 +1,166 @@
+/*
+ * migrid — convolutional gridding and degridding on AMD Instinct MI355X
+ * (gfx950).  C ABI.
+ *
+ * The operation (Muscat, "High-Performance Gridding For Radio
+ * Interferometric Image Synthesis", 2021):
+ *   records xi_p carry values F(xi_p) at continuous (u, v[, w]) positions;
+ *   the Gridding Step convolves every record with an oversampled, lookup-
+ *   table kernel and samples the result on an N x N uv-grid (Algorithm
+ *   "General Convolutional Gridding", Section 2.3; oversampled kernel,
+ *   Section 2.3.6 and the studied algorithm of Section 2.4.5).  Every
+ *   polarisation of a record is gridded with the same weights (Section 1.1).
+ *   Degridding is the adjoint map (the forward/backward operator pair of the
+ *   major-cycle residual, Section 1.6), which the thesis names as future work
+ *   (Chapter 8).
+ *
+ * Index rule (identical in every entry point, computed in FP64):
+ *   x = coord * scale + n/2            cells, origin at the centre pixel
+ *                                      (Section 2.1.2)
+ *   q = floor(x * beta + 1/2)          nearest pixel of the beta-oversampled
+ *                                      grid; rect is 1 on (-1/(2beta),
+ *                                      1/(2beta)] (Section 2.1.4), so ties go up
+ *   k_lo = floor((q - beta*S/2)/beta) + 1, footprint cells k_lo .. k_lo+S-1
+ *                                      (offsets in (-S/2, S/2], Section 2.3.4)
+ *   t0 = k_lo*beta - q + beta*S/2      in [1, beta]; cell k_lo+i takes table
+ *                                      entry t0 + i*beta; o = t0 - 1
+ *   W-projection plane: p = min(P-1, floor(|w| * inv_dw + 1/2)), support
+ *   S_p, conjugated table for w < 0 (Section 1.3: gbar_{-w} = conj(gbar_w)).
+ *   A record is skipped (and counted) unless uvw is finite and its whole
+ *   footprint lies inside the grid (Bounded Records Assumption, Section
+ *   2.3.1).  Each argument of the rule is formed in FP64 without fused
+ *   multiply-add, so indices are reproducible bit for bit.
+ *
+ * Layouts:
+ *   uvw      [nrec][3], F32 or F64, wavelengths
+ *   vis      [nrec][npol] complex64 (re, im float pairs), npol in 1..4
+ *   grid     [npol][nv][nu] complex64, u fastest, cell (nu/2, nv/2) is u=v=0
+ *   separable taps: beta*S + 1 real values; entry t at offset
+ *            (t - beta*S/2)/beta cells; the 2-D weight is T[tu] * T[tv]
+ *   W-projection taps: planes concatenated; plane p is (beta*S_p+1)^2
+ *            complex values, row-major [tv][tu], starting at element
+ *            plane_offset[p]
+ *   tap dtype: F32, F16 or BF16 (a complex tap is a pair of that type);
+ *            arithmetic is always FP32.
+ *
+ * Ownership and streams:
+ *   All array arguments are DEVICE pointers unless stated; the caller owns
+ *   them and they must stay alive until the work queued on `stream` ends.
+ *   Calls are asynchronous on `stream`.  Argument errors are returned
+ *   synchronously before anything is queued; launch errors are returned as
+ *   MG_EDEVICE.  The last error's text is available from mg_last_error()
+ *   (thread-local).
+ *
+ * Accumulation: grid entry points ADD into `grid`; degrid entry points
+ * OVERWRITE `vis_out` (skipped records get 0).
+ */
+#ifndef MIGRID_H
+#define MIGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MG_OK = 0,
+    MG_EINVAL = -1,        /* bad argument (checked on the host, nothing queued) */
+    MG_ENOMEM = -2,        /* device allocation failed / over the serving budget */
+    MG_EDEVICE = -3,       /* a HIP call or kernel launch failed */
+    MG_EUNSUPPORTED = -4,  /* valid request this build does not handle */
+    MG_EBUSY = -5          /* serving: no free slot */
+} mg_status;
+
+typedef enum { MG_F32 = 0, MG_F64 = 1, MG_F16 = 2, MG_BF16 = 3 } mg_dtype;
+
+typedef enum { MG_KERNEL_SEPARABLE = 0, MG_KERNEL_WPROJ = 1 } mg_kernel_kind;
+
+/* Grid geometry.  scale_* = cells per wavelength (= N x pixel size in rad,
+ * the N*dl = 1 normalisation of Section 2.1.2).  nu, nv in [1, 65535]. */
+typedef struct {
+    int32_t nu, nv;
+    int32_t npol;        /* 1..4 */
+    int32_t beta;        /* oversampling factor >= 1, beta*S even */
+    double scale_u, scale_v;
+} mg_grid_desc;
+
+/* Kernel bank.  plane_support / plane_offset are HOST arrays read during the
+ * call (copied by plans).  taps is a DEVICE pointer. */
+typedef struct {
+    mg_kernel_kind kind;
+    mg_dtype tap_dtype;            /* MG_F32, MG_F16 or MG_BF16 */
+    int32_t support;               /* separable: S (1..64) */
+    int32_t nplanes;               /* W-projection: number of planes (1..255) */
+    const int32_t *plane_support;  /* W-projection: S_p per plane (1..64) */
+    const int64_t *plane_offset;   /* W-projection: first complex tap of plane p */
+    double inv_dw;                 /* W-projection: 1 / plane spacing in w */
+    const void *taps;              /* device: the table(s) */
+    int64_t ntaps;                 /* elements in taps (real for separable,
+                                      complex for W-projection) */
+} mg_kernel_desc;
+
+/* Text of the status code. */
+const char *mg_status_str(mg_status s);
+
+/* Text of the last error set on this thread ("" if none). */
+const char *mg_last_error(void);
+
+/* Per-record integer indices of the index rule above, in input order
+ * (parity and debugging).  Outputs are device arrays of nrec entries:
+ * k_lo_u, k_lo_v, o_u, o_v, plane (-1 for a separable kernel), valid (0/1).
+ * *d_nskipped (device, may be NULL) is INCREMENTED by the skipped count. */
+mg_status mg_compute_indices(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                             const void *uvw, mg_dtype uvw_dtype,
+                             int32_t *k_lo_u, int32_t *k_lo_v, int32_t *o_u, int32_t *o_v,
+                             int32_t *plane, uint8_t *valid, int64_t *d_nskipped,
+                             hipStream_t stream);
+
+/* ---- plans: index + sort once, grid / degrid many times (major cycles) ----
+ *
+ * mg_plan_create runs the index rule over all records and sorts the valid
+ * ones by (plane, cell) on `stream` (the thesis's sorted record order,
+ * Section 3.2.4), and prepares the kernel bank.  The plan owns device memory
+ * it allocates itself (freed by mg_plan_destroy); it keeps no pointer to
+ * uvw, and copies the tap table, so neither needs to outlive the create
+ * call's stream work.  A plan is immutable after creation and may be used
+ * from several streams once the creating stream's work has completed. */
+typedef struct mg_plan mg_plan;
+
+mg_status mg_plan_create(mg_plan **plan, const mg_grid_desc *g, const mg_kernel_desc *k,
+                         int64_t nrec, const void *uvw, mg_dtype uvw_dtype, hipStream_t stream);
+
+/* grid += G vis.  vis: [nrec][npol] complex64 in the create call's record
+ * order; grid: [npol][nv][nu] complex64. */
+mg_status mg_plan_grid(const mg_plan *plan, const void *vis, void *grid, hipStream_t stream);
+
+/* vis_out = G^H grid (overwritten; skipped records get 0). */
+mg_status mg_plan_degrid(const mg_plan *plan, const void *grid, void *vis_out,
+                         hipStream_t stream);
+
+/* Number of skipped records (waits for the plan's creation work). */
+mg_status mg_plan_nskipped(const mg_plan *plan, int64_t *nskipped);
+
+/* Device bytes the plan holds. */
+mg_status mg_plan_bytes(const mg_plan *plan, size_t *bytes);
+
+mg_status mg_plan_destroy(mg_plan *plan);
+
+/* ---- one-shot calls: index + sort + grid (or degrid) in one go ----
+ * Scratch is allocated and released stream-ordered inside the call.
+ * *d_nskipped (device, may be NULL) is INCREMENTED by the skipped count. */
+mg_status mg_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                  const void *uvw, mg_dtype uvw_dtype, const void *vis, void *grid,
+                  int64_t *d_nskipped, hipStream_t stream);
+
+mg_status mg_degrid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                    const void *uvw, mg_dtype uvw_dtype, const void *grid, void *vis_out,
+                    int64_t *d_nskipped, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIGRID_H */

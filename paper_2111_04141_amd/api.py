@@ -1,0 +1,315 @@
+"""Python binding of libmigrid (include/migrid.h): argument marshalling only.
+
+Every step of gridding and degridding runs in the HIP library; this module
+checks tensor dtypes/devices/shapes, builds the C descriptors and passes raw
+device pointers plus torch's current HIP stream.  There is no CPU fallback:
+if the library is missing the import of the library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import re
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmigrid.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "migrid.h")
+
+MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_EUNSUPPORTED, MG_EBUSY = 0, -1, -2, -3, -4, -5
+MG_F32, MG_F64, MG_F16, MG_BF16 = 0, 1, 2, 3
+MG_KERNEL_SEPARABLE, MG_KERNEL_WPROJ = 0, 1
+
+_TORCH_TO_MG = {torch.float32: MG_F32, torch.float64: MG_F64, torch.float16: MG_F16,
+                torch.bfloat16: MG_BF16}
+
+
+class MigridError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nu", C.c_int32), ("nv", C.c_int32), ("npol", C.c_int32), ("beta", C.c_int32),
+                ("scale_u", C.c_double), ("scale_v", C.c_double)]
+
+
+class KernelDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("tap_dtype", C.c_int32), ("support", C.c_int32),
+                ("nplanes", C.c_int32), ("plane_support", C.POINTER(C.c_int32)),
+                ("plane_offset", C.POINTER(C.c_int64)), ("inv_dw", C.c_double),
+                ("taps", C.c_void_p), ("ntaps", C.c_int64)]
+
+
+_lib = None
+
+
+def header_symbols() -> list:
+    """Names of the functions declared in include/migrid.h."""
+    txt = open(HEADER_PATH).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def lib():
+    """The loaded libmigrid.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2111_04141_amd/build.py "
+                          "(there is no fallback path)")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    gd, kd = C.POINTER(GridDesc), C.POINTER(KernelDesc)
+    L.mg_status_str.argtypes = [i32]
+    L.mg_status_str.restype = C.c_char_p
+    L.mg_last_error.argtypes = []
+    L.mg_last_error.restype = C.c_char_p
+    L.mg_compute_indices.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.mg_plan_create.argtypes = [C.POINTER(vp), gd, kd, i64, vp, i32, vp]
+    L.mg_plan_grid.argtypes = [vp, vp, vp, vp]
+    L.mg_plan_degrid.argtypes = [vp, vp, vp, vp]
+    L.mg_plan_nskipped.argtypes = [vp, C.POINTER(i64)]
+    L.mg_plan_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.mg_plan_destroy.argtypes = [vp]
+    L.mg_grid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
+    L.mg_degrid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
+    for f in ("mg_compute_indices", "mg_plan_create", "mg_plan_grid", "mg_plan_degrid",
+              "mg_plan_nskipped", "mg_plan_bytes", "mg_plan_destroy", "mg_grid", "mg_degrid"):
+        getattr(L, f).restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != MG_OK:
+        L = lib()
+        raise MigridError(status, where, L.mg_last_error().decode() or
+                          L.mg_status_str(status).decode())
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# descriptors
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class GridSpec:
+    """nu x nv grid, npol polarisations, oversampling beta, cells per
+    wavelength scale_u / scale_v (origin at cell (nu/2, nv/2))."""
+    nu: int
+    nv: int
+    npol: int = 4
+    beta: int = 8
+    scale_u: float = 1.0
+    scale_v: float = 1.0
+
+    def desc(self) -> GridDesc:
+        return GridDesc(self.nu, self.nv, self.npol, self.beta, float(self.scale_u),
+                        float(self.scale_v))
+
+
+class KernelBank:
+    """A kernel table resident on the device.
+
+    separable: taps real [beta*S + 1] (float32 / float16 / bfloat16).
+    wproj: taps complex, concatenated planes [sum (beta*S_p+1)^2]; given as a
+    complex64 tensor or as a [..., 2] float16 / bfloat16 tensor.
+    """
+
+    def __init__(self, kind: str, taps: torch.Tensor, support: int = 0,
+                 plane_support: Sequence[int] = (), plane_offset: Sequence[int] = (),
+                 inv_dw: float = 0.0):
+        if kind not in ("separable", "wproj"):
+            raise ValueError("kind must be 'separable' or 'wproj'")
+        if not taps.is_cuda:
+            raise ValueError("taps must be a device tensor")
+        taps = taps.contiguous()
+        if kind == "wproj":
+            if taps.dtype == torch.complex64:
+                tdt, nt = MG_F32, taps.numel()
+            elif taps.dtype in (torch.float16, torch.bfloat16) and taps.shape[-1] == 2:
+                tdt, nt = _TORCH_TO_MG[taps.dtype], taps.numel() // 2
+            else:
+                raise ValueError("wproj taps: complex64, or [..., 2] float16/bfloat16")
+        else:
+            if taps.dtype not in (torch.float32, torch.float16, torch.bfloat16):
+                raise ValueError("separable taps: float32, float16 or bfloat16")
+            tdt, nt = _TORCH_TO_MG[taps.dtype], taps.numel()
+        self.kind = kind
+        self.taps = taps
+        self.tap_dtype = tdt
+        self.ntaps = nt
+        self.support = int(support)
+        self._ps = (C.c_int32 * max(1, len(plane_support)))(*[int(s) for s in plane_support])
+        self._po = (C.c_int64 * max(1, len(plane_offset)))(*[int(o) for o in plane_offset])
+        self.plane_support = [int(s) for s in plane_support]
+        self.plane_offset = [int(o) for o in plane_offset]
+        self.inv_dw = float(inv_dw)
+
+    @property
+    def support_max(self) -> int:
+        return self.support if self.kind == "separable" else max(self.plane_support)
+
+    def desc(self) -> KernelDesc:
+        d = KernelDesc()
+        d.kind = MG_KERNEL_SEPARABLE if self.kind == "separable" else MG_KERNEL_WPROJ
+        d.tap_dtype = self.tap_dtype
+        d.support = self.support
+        d.nplanes = len(self.plane_support)
+        d.plane_support = C.cast(self._ps, C.POINTER(C.c_int32))
+        d.plane_offset = C.cast(self._po, C.POINTER(C.c_int64))
+        d.inv_dw = self.inv_dw
+        d.taps = self.taps.data_ptr()
+        d.ntaps = self.ntaps
+        return d
+
+
+def _check_uvw(uvw: torch.Tensor) -> int:
+    if not uvw.is_cuda or uvw.dim() != 2 or uvw.shape[1] != 3 or not uvw.is_contiguous():
+        raise ValueError("uvw must be a contiguous [nrec, 3] device tensor")
+    if uvw.dtype not in (torch.float32, torch.float64):
+        raise ValueError("uvw must be float32 or float64")
+    return _TORCH_TO_MG[uvw.dtype]
+
+
+def _check_vis(vis: torch.Tensor, nrec: int, npol: int):
+    if (not vis.is_cuda or vis.dtype != torch.complex64 or not vis.is_contiguous()
+            or tuple(vis.shape) != (nrec, npol)):
+        raise ValueError(f"vis must be a contiguous complex64 [{nrec}, {npol}] device tensor")
+
+
+def _check_grid(g: torch.Tensor, spec: GridSpec):
+    if (not g.is_cuda or g.dtype != torch.complex64 or not g.is_contiguous()
+            or tuple(g.shape) != (spec.npol, spec.nv, spec.nu)):
+        raise ValueError(f"grid must be a contiguous complex64 "
+                         f"[{spec.npol}, {spec.nv}, {spec.nu}] device tensor")
+
+
+# ---------------------------------------------------------------------------
+# calls
+# ---------------------------------------------------------------------------
+
+def compute_indices(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor) -> dict:
+    """Per-record integer indices (k_lo_u, k_lo_v, o_u, o_v, plane, valid) and
+    the skipped count, in input order."""
+    dt = _check_uvw(uvw)
+    n = uvw.shape[0]
+    dev = uvw.device
+    out = {k: torch.empty(n, dtype=torch.int32, device=dev)
+           for k in ("k_lo_u", "k_lo_v", "o_u", "o_v", "plane")}
+    out["valid"] = torch.empty(n, dtype=torch.uint8, device=dev)
+    nsk = torch.zeros(1, dtype=torch.int64, device=dev)
+    gd, kd = spec.desc(), bank.desc()
+    _check(lib().mg_compute_indices(C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt,
+                                    *[out[k].data_ptr() for k in ("k_lo_u", "k_lo_v", "o_u",
+                                                                  "o_v", "plane", "valid")],
+                                    nsk.data_ptr(), _stream_ptr(dev)), "mg_compute_indices")
+    out["nskipped"] = nsk
+    return out
+
+
+def grid(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, vis: torch.Tensor,
+         out: Optional[torch.Tensor] = None, nskipped: Optional[torch.Tensor] = None):
+    """One-shot gridding (index + sort + grid): out += G vis."""
+    dt = _check_uvw(uvw)
+    n = uvw.shape[0]
+    _check_vis(vis, n, spec.npol)
+    if out is None:
+        out = torch.zeros(spec.npol, spec.nv, spec.nu, dtype=torch.complex64, device=uvw.device)
+    _check_grid(out, spec)
+    gd, kd = spec.desc(), bank.desc()
+    _check(lib().mg_grid(C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt, vis.data_ptr(),
+                         out.data_ptr(), _ptr(nskipped), _stream_ptr(uvw.device)), "mg_grid")
+    return out
+
+
+def degrid(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, grid_in: torch.Tensor,
+           out: Optional[torch.Tensor] = None, nskipped: Optional[torch.Tensor] = None):
+    """One-shot degridding: returns vis = G^H grid (skipped records get 0)."""
+    dt = _check_uvw(uvw)
+    n = uvw.shape[0]
+    _check_grid(grid_in, spec)
+    if out is None:
+        out = torch.empty(n, spec.npol, dtype=torch.complex64, device=uvw.device)
+    _check_vis(out, n, spec.npol)
+    gd, kd = spec.desc(), bank.desc()
+    _check(lib().mg_degrid(C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt, grid_in.data_ptr(),
+                           out.data_ptr(), _ptr(nskipped), _stream_ptr(uvw.device)), "mg_degrid")
+    return out
+
+
+class Plan:
+    """Index + sort once; grid / degrid many times over the same records."""
+
+    def __init__(self, spec: GridSpec, bank: KernelBank, uvw: torch.Tensor):
+        dt = _check_uvw(uvw)
+        self.spec, self.bank = spec, bank
+        self.nrec = uvw.shape[0]
+        self.device = uvw.device
+        self._h = C.c_void_p()
+        gd, kd = spec.desc(), bank.desc()
+        _check(lib().mg_plan_create(C.byref(self._h), C.byref(gd), C.byref(kd), self.nrec,
+                                    uvw.data_ptr(), dt, _stream_ptr(uvw.device)),
+               "mg_plan_create")
+
+    def grid(self, vis: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        _check_vis(vis, self.nrec, self.spec.npol)
+        if out is None:
+            out = torch.zeros(self.spec.npol, self.spec.nv, self.spec.nu, dtype=torch.complex64,
+                              device=self.device)
+        _check_grid(out, self.spec)
+        _check(lib().mg_plan_grid(self._h, vis.data_ptr(), out.data_ptr(),
+                                  _stream_ptr(self.device)), "mg_plan_grid")
+        return out
+
+    def degrid(self, grid_in: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        _check_grid(grid_in, self.spec)
+        if out is None:
+            out = torch.empty(self.nrec, self.spec.npol, dtype=torch.complex64,
+                              device=self.device)
+        _check_vis(out, self.nrec, self.spec.npol)
+        _check(lib().mg_plan_degrid(self._h, grid_in.data_ptr(), out.data_ptr(),
+                                    _stream_ptr(self.device)), "mg_plan_degrid")
+        return out
+
+    @property
+    def nskipped(self) -> int:
+        v = C.c_int64()
+        _check(lib().mg_plan_nskipped(self._h, C.byref(v)), "mg_plan_nskipped")
+        return int(v.value)
+
+    @property
+    def nbytes(self) -> int:
+        v = C.c_size_t()
+        _check(lib().mg_plan_bytes(self._h, C.byref(v)), "mg_plan_bytes")
+        return int(v.value)
+
+    def close(self):
+        if self._h:
+            lib().mg_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

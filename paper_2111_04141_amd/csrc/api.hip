@@ -1,0 +1,327 @@
+// C ABI of the migrid library: argument checking, plan layout, one-shot calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+struct mg_plan {
+    mg::PlanState st;
+    hipEvent_t ready = nullptr;   // recorded after the build work
+};
+
+namespace mg {
+
+namespace {
+thread_local std::string g_err;
+
+size_t dtype_size(mg_dtype d) {
+    switch (d) {
+    case MG_F32: return 4;
+    case MG_F64: return 8;
+    case MG_F16: return 2;
+    case MG_BF16: return 2;
+    }
+    return 0;
+}
+
+int ilog2(int x) {
+    int l = 0;
+    while ((1 << (l + 1)) <= x) ++l;
+    return l;
+}
+
+int lds_limit_bytes() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return v > 0 ? v : 65536;
+}
+
+// Tile side for a gridder class: the largest of 32, 16, 8 whose LDS region
+// (tile + S_max - 1)^2 x npol x 8 bytes fits the per-workgroup LDS limit.
+int tile_for_class(int cls, int npol, int lds_limit) {
+    if (cls == 3) return 16;
+    const int smax = cls == 0 ? 8 : cls == 1 ? 16 : 32;
+    for (int T : {32, 16, 8}) {
+        size_t bytes = (size_t)(T + smax - 1) * (T + smax - 1) * npol * 8;
+        if (bytes <= (size_t)lds_limit) return T;
+    }
+    return 8;
+}
+
+mg_status check_common(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                       const void *uvw, mg_dtype uvw_dtype) {
+    if (!g || !k) return set_error(MG_EINVAL, "null descriptor");
+    if (g->nu < 1 || g->nv < 1 || g->nu > kMaxN || g->nv > kMaxN)
+        return set_error(MG_EINVAL, "grid size must be in [1, 65535]");
+    if (g->npol < 1 || g->npol > 4) return set_error(MG_EINVAL, "npol must be in 1..4");
+    if (g->beta < 1 || g->beta > kMaxBeta) return set_error(MG_EINVAL, "beta must be in 1..256");
+    if (!std::isfinite(g->scale_u) || !std::isfinite(g->scale_v))
+        return set_error(MG_EINVAL, "scale must be finite");
+    if (nrec < 0 || nrec > 0x7ffffffeLL) return set_error(MG_EINVAL, "nrec must be in [0, 2^31-2]");
+    if (nrec > 0 && !uvw) return set_error(MG_EINVAL, "null uvw");
+    if (uvw_dtype != MG_F32 && uvw_dtype != MG_F64)
+        return set_error(MG_EINVAL, "uvw dtype must be MG_F32 or MG_F64");
+    if (k->tap_dtype != MG_F32 && k->tap_dtype != MG_F16 && k->tap_dtype != MG_BF16)
+        return set_error(MG_EINVAL, "tap dtype must be MG_F32, MG_F16 or MG_BF16");
+    if (!k->taps) return set_error(MG_EINVAL, "null taps");
+    if (k->kind == MG_KERNEL_SEPARABLE) {
+        if (k->support < 1 || k->support > kMaxSupport)
+            return set_error(MG_EINVAL, "support must be in 1..64");
+        if (((int64_t)g->beta * k->support) % 2)
+            return set_error(MG_EINVAL, "beta * support must be even");
+        if (k->ntaps < (int64_t)g->beta * k->support + 1)
+            return set_error(MG_EINVAL, "separable table shorter than beta*S+1");
+    } else if (k->kind == MG_KERNEL_WPROJ) {
+        if (k->nplanes < 1 || k->nplanes > kMaxPlanes)
+            return set_error(MG_EINVAL, "nplanes must be in 1..128");
+        if (!k->plane_support || !k->plane_offset)
+            return set_error(MG_EINVAL, "null plane_support / plane_offset");
+        if (!std::isfinite(k->inv_dw) || k->inv_dw < 0)
+            return set_error(MG_EINVAL, "inv_dw must be finite and >= 0");
+        for (int p = 0; p < k->nplanes; ++p) {
+            const int S = k->plane_support[p];
+            if (S < 1 || S > kMaxSupport) return set_error(MG_EINVAL, "plane support must be in 1..64");
+            if (((int64_t)g->beta * S) % 2) return set_error(MG_EINVAL, "beta * S_p must be even");
+            const int64_t w = (int64_t)g->beta * S + 1;
+            if (k->plane_offset[p] < 0 || k->plane_offset[p] + w * w > k->ntaps)
+                return set_error(MG_EINVAL, "plane table outside the tap array");
+        }
+    } else {
+        return set_error(MG_EINVAL, "unknown kernel kind");
+    }
+    return MG_OK;
+}
+
+DevGeom make_geom(const mg_grid_desc *g, const mg_kernel_desc *k) {
+    DevGeom d;
+    std::memset(&d, 0, sizeof d);
+    d.nu = g->nu;
+    d.nv = g->nv;
+    d.npol = g->npol;
+    d.beta = g->beta;
+    d.scale_u = g->scale_u;
+    d.scale_v = g->scale_v;
+    if (k->kind == MG_KERNEL_WPROJ) {
+        d.nplanes = k->nplanes;
+        d.support = 0;
+        d.inv_dw = k->inv_dw;
+        for (int p = 0; p < k->nplanes; ++p) {
+            d.plane_support[p] = k->plane_support[p];
+            d.plane_offset[p] = k->plane_offset[p];
+        }
+    } else {
+        d.nplanes = 0;
+        d.support = k->support;
+        d.plane_support[0] = k->support;
+        d.plane_offset[0] = 0;
+    }
+    return d;
+}
+
+void free_plan_memory(PlanState &P, hipStream_t s) {
+    void *ptrs[] = {P.taps, P.smeta, P.sperm, P.chunks, P.plane_cfirst, P.d_planes, P.counters};
+    for (void *p : ptrs) {
+        if (!p) continue;
+        if (P.stream_ordered) hipFreeAsync(p, s);
+        else hipFree(p);
+    }
+    P.taps = nullptr;
+    P.smeta = nullptr;
+    P.sperm = nullptr;
+    P.chunks = nullptr;
+    P.plane_cfirst = nullptr;
+    P.d_planes = nullptr;
+    P.counters = nullptr;
+}
+
+// Lays out the plan and runs the build on `stream`.
+mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc *k,
+                       int64_t nrec, const void *uvw, mg_dtype uvw_dtype, hipStream_t stream,
+                       bool stream_ordered) {
+    P.geom = make_geom(g, k);
+    P.kind = k->kind;
+    P.tap_dtype = k->tap_dtype;
+    P.nrec = nrec;
+    P.stream_ordered = stream_ordered;
+    P.alloc_stream = stream;
+    P.nplanes_eff = (k->kind == MG_KERNEL_WPROJ) ? k->nplanes : 1;
+    // chunk size: enough chunks to fill the chip, at most 2048 records
+    int64_t R = nrec / 4096;
+    P.R = (int32_t)std::max<int64_t>(64, std::min<int64_t>(2048, R));
+    const int lds = lds_limit_bytes();
+    P.planes.resize(P.nplanes_eff);
+    int64_t base = 0;
+    for (int p = 0; p < P.nplanes_eff; ++p) {
+        PlaneLayout &L = P.planes[p];
+        L.S = (k->kind == MG_KERNEL_WPROJ) ? k->plane_support[p] : k->support;
+        L.cls = support_class(L.S);
+        L.T = tile_for_class(L.cls, g->npol, lds);
+        L.log2T = ilog2(L.T);
+        L.ntu = (g->nu + L.T - 1) / L.T;
+        L.ntv = (g->nv + L.T - 1) / L.T;
+        L.base = base;
+        base += (int64_t)L.ntu * L.ntv;
+    }
+    P.nbuckets = base;
+    if (base >= 0x7fffffffLL) return set_error(MG_EUNSUPPORTED, "too many (plane, tile) buckets");
+    // private copy of the tap table(s)
+    const size_t esz = dtype_size(k->tap_dtype) * (k->kind == MG_KERNEL_WPROJ ? 2 : 1);
+    P.taps_bytes = esz * (size_t)k->ntaps;
+    hipError_t e = stream_ordered ? hipMallocAsync(&P.taps, P.taps_bytes, stream)
+                                  : hipMalloc(&P.taps, P.taps_bytes);
+    if (e != hipSuccess) return set_error(MG_ENOMEM, "tap table allocation failed");
+    P.bytes += P.taps_bytes;
+    e = hipMemcpyAsync(P.taps, k->taps, P.taps_bytes, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("tap copy: ") + hipGetErrorString(e));
+    return plan_build(P, uvw, uvw_dtype, stream);
+}
+
+__global__ void add_count_kernel(const int64_t *src, int64_t *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst += *src;
+}
+
+}  // namespace
+
+mg_status set_error(mg_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+const char *mg_status_str(mg_status s) {
+    switch (s) {
+    case MG_OK: return "ok";
+    case MG_EINVAL: return "invalid argument";
+    case MG_ENOMEM: return "out of memory";
+    case MG_EDEVICE: return "device error";
+    case MG_EUNSUPPORTED: return "unsupported";
+    case MG_EBUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+const char *mg_last_error(void) { return g_err.c_str(); }
+
+mg_status mg_compute_indices(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                             const void *uvw, mg_dtype uvw_dtype, int32_t *k_lo_u,
+                             int32_t *k_lo_v, int32_t *o_u, int32_t *o_v, int32_t *plane,
+                             uint8_t *valid, int64_t *d_nskipped, hipStream_t stream) {
+    mg_status s = check_common(g, k, nrec, uvw, uvw_dtype);
+    if (s != MG_OK) return s;
+    if (nrec > 0 && (!k_lo_u || !k_lo_v || !o_u || !o_v || !plane || !valid))
+        return set_error(MG_EINVAL, "null output array");
+    return launch_compute_indices(make_geom(g, k), nrec, uvw, uvw_dtype, k_lo_u, k_lo_v, o_u, o_v,
+                                  plane, valid, d_nskipped, stream);
+}
+
+mg_status mg_plan_create(mg_plan **plan, const mg_grid_desc *g, const mg_kernel_desc *k,
+                         int64_t nrec, const void *uvw, mg_dtype uvw_dtype, hipStream_t stream) {
+    if (!plan) return set_error(MG_EINVAL, "null plan output");
+    *plan = nullptr;
+    mg_status s = check_common(g, k, nrec, uvw, uvw_dtype);
+    if (s != MG_OK) return s;
+    mg_plan *p = new (std::nothrow) mg_plan;
+    if (!p) return set_error(MG_ENOMEM, "host allocation failed");
+    s = create_state(p->st, g, k, nrec, uvw, uvw_dtype, stream, false);
+    if (s == MG_OK) {
+        if (hipEventCreateWithFlags(&p->ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(p->ready, stream) != hipSuccess)
+            s = set_error(MG_EDEVICE, "event record failed");
+    }
+    if (s != MG_OK) {
+        hipStreamSynchronize(stream);
+        free_plan_memory(p->st, stream);
+        if (p->ready) hipEventDestroy(p->ready);
+        delete p;
+        return s;
+    }
+    *plan = p;
+    return MG_OK;
+}
+
+mg_status mg_plan_grid(const mg_plan *plan, const void *vis, void *grid, hipStream_t stream) {
+    if (!plan) return set_error(MG_EINVAL, "null plan");
+    if (plan->st.nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
+    if (!grid) return set_error(MG_EINVAL, "null grid");
+    return launch_grid(plan->st, vis, grid, stream);
+}
+
+mg_status mg_plan_degrid(const mg_plan *plan, const void *grid, void *vis_out,
+                         hipStream_t stream) {
+    if (!plan) return set_error(MG_EINVAL, "null plan");
+    if (!grid) return set_error(MG_EINVAL, "null grid");
+    if (plan->st.nrec > 0 && !vis_out) return set_error(MG_EINVAL, "null vis_out");
+    return launch_degrid(plan->st, grid, vis_out, stream);
+}
+
+mg_status mg_plan_nskipped(const mg_plan *plan, int64_t *nskipped) {
+    if (!plan || !nskipped) return set_error(MG_EINVAL, "null argument");
+    if (hipEventSynchronize(plan->ready) != hipSuccess) return set_error(MG_EDEVICE, "event sync failed");
+    int64_t v = 0;
+    if (hipMemcpy(&v, plan->st.counters, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+        return set_error(MG_EDEVICE, "counter copy failed");
+    *nskipped = v;
+    return MG_OK;
+}
+
+mg_status mg_plan_bytes(const mg_plan *plan, size_t *bytes) {
+    if (!plan || !bytes) return set_error(MG_EINVAL, "null argument");
+    *bytes = plan->st.bytes;
+    return MG_OK;
+}
+
+mg_status mg_plan_destroy(mg_plan *plan) {
+    if (!plan) return MG_OK;
+    if (plan->ready) hipEventSynchronize(plan->ready);
+    hipDeviceSynchronize();
+    free_plan_memory(plan->st, nullptr);
+    if (plan->ready) hipEventDestroy(plan->ready);
+    delete plan;
+    return MG_OK;
+}
+
+mg_status mg_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec, const void *uvw,
+                  mg_dtype uvw_dtype, const void *vis, void *grid, int64_t *d_nskipped,
+                  hipStream_t stream) {
+    mg_status s = check_common(g, k, nrec, uvw, uvw_dtype);
+    if (s != MG_OK) return s;
+    if (nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
+    if (!grid) return set_error(MG_EINVAL, "null grid");
+    PlanState P;
+    s = create_state(P, g, k, nrec, uvw, uvw_dtype, stream, true);
+    if (s == MG_OK) s = launch_grid(P, vis, grid, stream);
+    if (s == MG_OK && d_nskipped)
+        hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(64), 0, stream, P.counters, d_nskipped);
+    free_plan_memory(P, stream);
+    return s;
+}
+
+mg_status mg_degrid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                    const void *uvw, mg_dtype uvw_dtype, const void *grid, void *vis_out,
+                    int64_t *d_nskipped, hipStream_t stream) {
+    mg_status s = check_common(g, k, nrec, uvw, uvw_dtype);
+    if (s != MG_OK) return s;
+    if (!grid) return set_error(MG_EINVAL, "null grid");
+    if (nrec > 0 && !vis_out) return set_error(MG_EINVAL, "null vis_out");
+    PlanState P;
+    s = create_state(P, g, k, nrec, uvw, uvw_dtype, stream, true);
+    if (s == MG_OK) s = launch_degrid(P, grid, vis_out, stream);
+    if (s == MG_OK && d_nskipped)
+        hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(64), 0, stream, P.counters, d_nskipped);
+    free_plan_memory(P, stream);
+    return s;
+}
+
+}  // extern "C"

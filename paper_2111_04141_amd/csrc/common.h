@@ -1,0 +1,147 @@
+// Shared definitions of the migrid HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "../../include/migrid.h"
+
+namespace mg {
+
+constexpr int kWave = 64;
+constexpr int kMaxPlanes = 128;
+constexpr int kMaxSupport = 64;
+constexpr int kMaxBeta = 256;
+constexpr int kMaxN = 65535;
+
+// Geometry and kernel description as the device sees it (passed by value).
+struct DevGeom {
+    int32_t nu, nv, npol, beta;
+    double scale_u, scale_v;
+    int32_t nplanes;         // 0 = separable
+    int32_t support;         // separable S
+    double inv_dw;
+    int32_t plane_support[kMaxPlanes];
+    int64_t plane_offset[kMaxPlanes];   // element offset of plane p
+};
+
+// Per-record packed index, 8 bytes:
+//   kuv  = k_lo_u | k_lo_v << 16
+//   info = o_u | o_v << 8 | plane << 16 | conj << 24
+struct RecMeta {
+    uint32_t kuv;
+    uint32_t info;
+};
+
+__host__ __device__ inline uint32_t meta_ku(RecMeta m) { return m.kuv & 0xffffu; }
+__host__ __device__ inline uint32_t meta_kv(RecMeta m) { return m.kuv >> 16; }
+__host__ __device__ inline uint32_t meta_ou(RecMeta m) { return m.info & 0xffu; }
+__host__ __device__ inline uint32_t meta_ov(RecMeta m) { return (m.info >> 8) & 0xffu; }
+__host__ __device__ inline uint32_t meta_plane(RecMeta m) { return (m.info >> 16) & 0xffu; }
+__host__ __device__ inline uint32_t meta_conj(RecMeta m) { return (m.info >> 24) & 1u; }
+
+// One result of the index rule.
+struct RecIndex {
+    int32_t ku, kv, ou, ov, plane, S, conj, valid;
+};
+
+// Floor division of a possibly negative numerator by a positive divisor.
+__device__ inline int64_t floor_div_pos(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) q -= 1;
+    return q;
+}
+
+// One axis of the index rule, in FP64 with every operation rounded as
+// written (no contraction into fused multiply-add), so that the GPU and any
+// other implementation of the same rule agree bit for bit.
+__device__ inline bool index_axis(double coord, double scale, int32_t n, int32_t beta, int32_t S,
+                                  int32_t *k_lo, int32_t *o) {
+#pragma clang fp contract(off)
+    double x = coord * scale;
+    x = x + (double)(n / 2);
+    double xb = x * (double)beta;
+    xb = xb + 0.5;
+    double fq = floor(xb);
+    if (!(fabs(fq) < 4.0e15)) return false;
+    int64_t q = (int64_t)fq;
+    int64_t half = (int64_t)beta * S / 2;
+    int64_t k = floor_div_pos(q - half, beta) + 1;
+    int64_t t0 = k * beta - q + half;
+    bool ok = (k >= 0) && (k + S - 1 <= (int64_t)n - 1);
+    *k_lo = ok ? (int32_t)k : 0;
+    *o = ok ? (int32_t)(t0 - 1) : 0;
+    return ok;
+}
+
+template <typename T>
+__device__ inline RecIndex index_record(const DevGeom &g, T u_, T v_, T w_) {
+#pragma clang fp contract(off)
+    RecIndex r;
+    r.ku = r.kv = r.ou = r.ov = 0;
+    r.plane = -1;
+    r.conj = 0;
+    r.valid = 0;
+    double u = (double)u_, v = (double)v_, w = (double)w_;
+    r.S = g.support;
+    if (!(isfinite(u) && isfinite(v) && isfinite(w))) return r;
+    if (g.nplanes > 0) {
+        double a = fabs(w) * g.inv_dw;
+        a = a + 0.5;
+        double fp = floor(a);
+        int32_t p = (fp >= (double)(g.nplanes - 1)) ? g.nplanes - 1 : (int32_t)fp;
+        r.plane = p;
+        r.conj = (w < 0.0) ? 1 : 0;
+        r.S = g.plane_support[p];
+    }
+    bool okU = index_axis(u, g.scale_u, g.nu, g.beta, r.S, &r.ku, &r.ou);
+    bool okV = index_axis(v, g.scale_v, g.nv, g.beta, r.S, &r.kv, &r.ov);
+    r.valid = (okU && okV) ? 1 : 0;
+    return r;
+}
+
+__device__ inline RecMeta pack_meta(const RecIndex &r) {
+    RecMeta m;
+    m.kuv = (uint32_t)r.ku | ((uint32_t)r.kv << 16);
+    m.info = (uint32_t)r.ou | ((uint32_t)r.ov << 8) | ((uint32_t)(r.plane < 0 ? 0 : r.plane) << 16)
+             | ((uint32_t)r.conj << 24);
+    return m;
+}
+
+// Tap loads: a tap table element of type TapT expanded to FP32.
+template <typename TapT> struct TapTraits;
+template <> struct TapTraits<float> {
+    static __device__ inline float real(const float *p, int64_t i) { return p[i]; }
+    static __device__ inline float2 cplx(const float *p, int64_t i) {
+        return *reinterpret_cast<const float2 *>(p + 2 * i);
+    }
+};
+template <> struct TapTraits<__half> {
+    static __device__ inline float real(const __half *p, int64_t i) { return __half2float(p[i]); }
+    static __device__ inline float2 cplx(const __half *p, int64_t i) {
+        __half2 h = *reinterpret_cast<const __half2 *>(p + 2 * i);
+        return __half22float2(h);
+    }
+};
+template <> struct TapTraits<__hip_bfloat16> {
+    static __device__ inline float real(const __hip_bfloat16 *p, int64_t i) {
+        return __bfloat162float(p[i]);
+    }
+    static __device__ inline float2 cplx(const __hip_bfloat16 *p, int64_t i) {
+        uint32_t bits = *reinterpret_cast<const uint32_t *>(p + 2 * i);
+        float2 f;
+        f.x = __uint_as_float(bits << 16);
+        f.y = __uint_as_float(bits & 0xffff0000u);
+        return f;
+    }
+};
+
+// Uniform (scalar) broadcast helpers.
+__device__ inline uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline float uniform_f32(float x) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x)));
+}
+
+}  // namespace mg

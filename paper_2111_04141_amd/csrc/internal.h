@@ -1,0 +1,83 @@
+// Internal interfaces between the C-ABI layer and the kernel launchers.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace mg {
+
+// Per-plane layout of the record buckets and the kernel each plane runs.
+//   Buckets are (plane, uv tile) pairs, numbered plane-major.  A tile is
+//   T x T cells; a record belongs to the tile holding its footprint's first
+//   cell (k_lo_u, k_lo_v).
+struct PlaneLayout {
+    int32_t S;          // support of the plane
+    int32_t T;          // tile side in cells (16 or 32)
+    int32_t log2T;
+    int32_t ntu, ntv;   // tiles per axis
+    int64_t base;       // first bucket of the plane
+    int32_t cls;        // gridder class (see grid.hip)
+};
+
+// One chunk: up to R records of one bucket, cell-sorted inside the chunk.
+//   bbox: k_lo ranges of the chunk's records relative to the tile origin,
+//   packed umin | umax << 8 | vmin << 16 | vmax << 24.
+struct Chunk {
+    uint32_t start;
+    uint32_t len;
+    uint32_t bucket;
+    uint32_t bbox;
+};
+
+struct PlanState {
+    DevGeom geom{};
+    mg_kernel_kind kind = MG_KERNEL_SEPARABLE;
+    mg_dtype tap_dtype = MG_F32;
+    int32_t nplanes_eff = 1;          // 1 for separable
+    int64_t nrec = 0;
+    int64_t nbuckets = 0;
+    int64_t max_chunks = 0;
+    int32_t R = 1024;                 // records per chunk (max)
+    std::vector<PlaneLayout> planes;  // host copy
+    // device memory
+    void *taps = nullptr;             // plan-owned copy of the table(s)
+    size_t taps_bytes = 0;
+    RecMeta *smeta = nullptr;         // [nrec] sorted (first nvalid valid)
+    uint32_t *sperm = nullptr;        // [nrec] original record index
+    Chunk *chunks = nullptr;          // [max_chunks]
+    uint32_t *plane_cfirst = nullptr; // [nplanes_eff + 1] first chunk of each plane
+    PlaneLayout *d_planes = nullptr;  // [nplanes_eff]
+    int64_t *counters = nullptr;      // [0] skipped, [1] valid, [2] chunks
+    size_t bytes = 0;
+    bool stream_ordered = false;      // allocated with hipMallocAsync
+    hipStream_t alloc_stream = nullptr;
+};
+
+// Errors (thread-local message).
+mg_status set_error(mg_status s, const std::string &msg);
+
+// Build steps (plan.hip).  All asynchronous on `stream`.
+mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStream_t stream);
+mg_status launch_compute_indices(const DevGeom &g, int64_t nrec, const void *uvw,
+                                 mg_dtype uvw_dtype, int32_t *k_lo_u, int32_t *k_lo_v,
+                                 int32_t *o_u, int32_t *o_v, int32_t *plane, uint8_t *valid,
+                                 int64_t *d_nskipped, hipStream_t stream);
+
+// Hot kernels (grid.hip, degrid.hip).
+mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream_t stream);
+mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hipStream_t stream);
+
+// Gridder classes: support range -> slots per lane and LDS tile use.
+//   class 0: S <= 8   (one window slot per lane)
+//   class 1: S <= 16  (up to 4 slots per lane)
+//   class 2: S <= 32  (up to 16 slots per lane)
+//   class 3: S <= 64  (16 slots per lane, slots split over the 4 waves,
+//                      commits straight to the grid)
+inline int support_class(int S) { return S <= 8 ? 0 : S <= 16 ? 1 : S <= 32 ? 2 : 3; }
+
+constexpr int kWavesPerGroup = 4;
+constexpr int kGroupThreads = kWave * kWavesPerGroup;
+
+}  // namespace mg

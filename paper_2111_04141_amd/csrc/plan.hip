@@ -1,0 +1,429 @@
+// Plan building: index rule, bucket counting sort, chunk list, per-chunk
+// cell sort.
+//
+// The thesis sorts records by their position on the virtual NN grid before
+// gridding ("SS" ordering, Section 3.2.4) because the order in which records
+// reach the gridder sets how often accumulated values have to be committed
+// (Chapter 4).  Here the order is (plane, uv tile, cell): a counting sort by
+// (plane, tile) bucket over the whole record set, then a counting sort by
+// cell inside each chunk of at most R records.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mg {
+
+namespace {
+
+constexpr uint32_t kInvalidBucket = 0xffffffffu;
+
+// ---------------------------------------------------------------------------
+// index rule -> packed meta, bucket id, bucket histogram, skipped count
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void index_bucket_kernel(
+    DevGeom g, const PlaneLayout *__restrict__ planes, int64_t nrec, const T *__restrict__ uvw,
+    RecMeta *__restrict__ meta, uint32_t *__restrict__ bucket_of, uint32_t *__restrict__ hist,
+    int64_t *__restrict__ counters) {
+    __shared__ uint32_t s_skip;
+    if (threadIdx.x == 0) s_skip = 0;
+    __syncthreads();
+    uint32_t skipped = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrec;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        RecIndex ix = index_record<T>(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2]);
+        uint32_t b = kInvalidBucket;
+        if (ix.valid) {
+            const PlaneLayout pl = planes[ix.plane < 0 ? 0 : ix.plane];
+            uint32_t tu = (uint32_t)ix.ku >> pl.log2T;
+            uint32_t tv = (uint32_t)ix.kv >> pl.log2T;
+            b = (uint32_t)(pl.base + (int64_t)tv * pl.ntu + tu);
+            atomicAdd(&hist[b], 1u);
+        } else {
+            ++skipped;
+        }
+        meta[r] = pack_meta(ix);
+        bucket_of[r] = b;
+    }
+    if (skipped) atomicAdd(&s_skip, skipped);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_skip) atomicAdd((unsigned long long *)&counters[0],
+                                              (unsigned long long)s_skip);
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of (count, chunks-of-R) pairs over the buckets
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 16;
+constexpr int kScanBlock = 256 * kScanItems;
+
+__device__ inline uint2 pair_of(const uint32_t *hist, int64_t i, int64_t n, uint32_t R) {
+    if (i >= n) return make_uint2(0, 0);
+    uint32_t c = hist[i];
+    return make_uint2(c, (c + R - 1) / R);
+}
+
+__device__ inline uint2 add2(uint2 a, uint2 b) { return make_uint2(a.x + b.x, a.y + b.y); }
+
+// Block-wide exclusive scan of one uint2 per thread (256 threads).
+__device__ inline uint2 block_exclusive_scan(uint2 v, uint2 *total) {
+    __shared__ uint2 s[256];
+    const int t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint2 add = (t >= off) ? s[t - off] : make_uint2(0, 0);
+        __syncthreads();
+        s[t] = add2(s[t], add);
+        __syncthreads();
+    }
+    uint2 incl = s[t];
+    *total = s[255];
+    __syncthreads();
+    return make_uint2(incl.x - v.x, incl.y - v.y);
+}
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t *__restrict__ hist,
+                                                          int64_t n, uint32_t R,
+                                                          uint2 *__restrict__ block_sums) {
+    int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint2 acc = make_uint2(0, 0);
+    for (int i = 0; i < kScanItems; ++i) acc = add2(acc, pair_of(hist, base + i, n, R));
+    uint2 total;
+    block_exclusive_scan(acc, &total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// Single-block exclusive scan of the block sums (in place); writes the grand
+// total to *total.
+__global__ __launch_bounds__(256) void scan_sums_kernel(uint2 *__restrict__ sums, int64_t nb,
+                                                        uint2 *__restrict__ total) {
+    uint2 carry = make_uint2(0, 0);
+    for (int64_t base = 0; base < nb; base += 256) {
+        int64_t i = base + threadIdx.x;
+        uint2 v = (i < nb) ? sums[i] : make_uint2(0, 0);
+        uint2 tot;
+        uint2 ex = block_exclusive_scan(v, &tot);
+        if (i < nb) sums[i] = add2(ex, carry);
+        carry = add2(carry, tot);
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// Writes bstart[i] (first record of bucket i), cursor[i] (= bstart, used by
+// the scatter) and cstart[i] (first chunk of bucket i).
+__global__ __launch_bounds__(256) void scan_down_kernel(const uint32_t *__restrict__ hist,
+                                                        int64_t n, uint32_t R,
+                                                        const uint2 *__restrict__ block_off,
+                                                        uint32_t *__restrict__ bstart,
+                                                        uint32_t *__restrict__ cursor,
+                                                        uint32_t *__restrict__ cstart) {
+    int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint2 vals[kScanItems];
+    uint2 acc = make_uint2(0, 0);
+    for (int i = 0; i < kScanItems; ++i) {
+        vals[i] = pair_of(hist, base + i, n, R);
+        acc = add2(acc, vals[i]);
+    }
+    uint2 total;
+    uint2 run = add2(block_exclusive_scan(acc, &total), block_off[blockIdx.x]);
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t k = base + i;
+        if (k < n) {
+            bstart[k] = run.x;
+            cursor[k] = run.x;
+            cstart[k] = run.y;
+        }
+        run = add2(run, vals[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scatter records into bucket order (order inside a bucket is arbitrary;
+// the chunk sort below orders each chunk by cell)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void scatter_kernel(int64_t nrec,
+                                                      const RecMeta *__restrict__ meta,
+                                                      const uint32_t *__restrict__ bucket_of,
+                                                      uint32_t *__restrict__ cursor,
+                                                      RecMeta *__restrict__ smeta,
+                                                      uint32_t *__restrict__ sperm) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrec;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t b = bucket_of[r];
+        if (b == kInvalidBucket) continue;
+        uint32_t pos = atomicAdd(&cursor[b], 1u);
+        smeta[pos] = meta[r];
+        sperm[pos] = (uint32_t)r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// chunk list: bucket b with c records -> ceil(c/R) chunks
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void chunk_list_kernel(int64_t nb, uint32_t R,
+                                                         const uint32_t *__restrict__ hist,
+                                                         const uint32_t *__restrict__ bstart,
+                                                         const uint32_t *__restrict__ cstart,
+                                                         Chunk *__restrict__ chunks) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t c = hist[b];
+        uint32_t s = bstart[b];
+        uint32_t k0 = cstart[b];
+        for (uint32_t k = 0; k * R < c; ++k) {
+            Chunk ch;
+            ch.start = s + k * R;
+            ch.len = min(R, c - k * R);
+            ch.bucket = (uint32_t)b;
+            ch.bbox = 0;
+            chunks[k0 + k] = ch;
+        }
+    }
+}
+
+// plane_cfirst[p] = first chunk of plane p; plane_cfirst[P] = chunk count.
+// counters[1] = valid records, counters[2] = chunks.
+__global__ void plane_ranges_kernel(int32_t nplanes, const PlaneLayout *__restrict__ planes,
+                                    int64_t nb, const uint32_t *__restrict__ cstart,
+                                    const uint2 *__restrict__ total,
+                                    uint32_t *__restrict__ plane_cfirst,
+                                    int64_t *__restrict__ counters) {
+    int p = threadIdx.x;
+    if (p < nplanes) plane_cfirst[p] = (planes[p].base < nb) ? cstart[planes[p].base] : total->y;
+    if (p == 0) {
+        plane_cfirst[nplanes] = total->y;
+        counters[1] = total->x;
+        counters[2] = total->y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-chunk counting sort by cell inside the tile (row-major), in LDS;
+// also records the chunk's k_lo bounding box
+// ---------------------------------------------------------------------------
+constexpr int kMaxR = 2048;
+
+__global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restrict__ counters,
+                                                         const PlaneLayout *__restrict__ planes,
+                                                         int32_t nplanes,
+                                                         Chunk *__restrict__ chunks,
+                                                         RecMeta *__restrict__ smeta,
+                                                         uint32_t *__restrict__ sperm) {
+    __shared__ uint32_t hist[1024];
+    __shared__ RecMeta m_in[kMaxR];
+    __shared__ uint32_t p_in[kMaxR];
+    __shared__ uint32_t s_box[4];
+    const int64_t nchunks = counters[2];
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        Chunk ch = chunks[c];
+        // plane of the bucket (planes are few: linear search)
+        int p = 0;
+        while (p + 1 < nplanes && (int64_t)ch.bucket >= planes[p + 1].base) ++p;
+        const PlaneLayout pl = planes[p];
+        const uint32_t local = ch.bucket - (uint32_t)pl.base;
+        const uint32_t tu0 = (local % (uint32_t)pl.ntu) << pl.log2T;
+        const uint32_t tv0 = (local / (uint32_t)pl.ntu) << pl.log2T;
+        const int ncell = pl.T * pl.T;
+        for (int i = threadIdx.x; i < ncell; i += blockDim.x) hist[i] = 0;
+        if (threadIdx.x < 4) s_box[threadIdx.x] = (threadIdx.x & 1) ? 0u : 0xffffffffu;
+        __syncthreads();
+        uint32_t umin = 0xffffffffu, umax = 0, vmin = 0xffffffffu, vmax = 0;
+        for (uint32_t i = threadIdx.x; i < ch.len; i += blockDim.x) {
+            RecMeta m = smeta[ch.start + i];
+            m_in[i] = m;
+            p_in[i] = sperm[ch.start + i];
+            uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
+            atomicAdd(&hist[(dv << pl.log2T) | du], 1u);
+            umin = min(umin, du);
+            umax = max(umax, du);
+            vmin = min(vmin, dv);
+            vmax = max(vmax, dv);
+        }
+        atomicMin(&s_box[0], umin);
+        atomicMax(&s_box[1], umax);
+        atomicMin(&s_box[2], vmin);
+        atomicMax(&s_box[3], vmax);
+        __syncthreads();
+        {
+            // exclusive scan of the (up to 1024) cell counts: 4 per thread
+            uint2 v = make_uint2(0, 0);
+            uint32_t loc[4];
+            for (int k = 0; k < 4; ++k) {
+                int i = threadIdx.x * 4 + k;
+                loc[k] = (i < ncell) ? hist[i] : 0u;
+                v.x += loc[k];
+            }
+            uint2 tot;
+            uint2 ex = block_exclusive_scan(v, &tot);
+            uint32_t run = ex.x;
+            for (int k = 0; k < 4; ++k) {
+                int i = threadIdx.x * 4 + k;
+                if (i < ncell) hist[i] = run;
+                run += loc[k];
+            }
+        }
+        if (threadIdx.x == 0)
+            chunks[c].bbox = s_box[0] | (s_box[1] << 8) | (s_box[2] << 16) | (s_box[3] << 24);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < ch.len; i += blockDim.x) {
+            RecMeta m = m_in[i];
+            uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
+            uint32_t pos = atomicAdd(&hist[(dv << pl.log2T) | du], 1u);
+            smeta[ch.start + pos] = m;
+            sperm[ch.start + pos] = p_in[i];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// compute_indices: the index rule written out per record (parity/debug)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void indices_kernel(DevGeom g, int64_t nrec,
+                                                      const T *__restrict__ uvw,
+                                                      int32_t *k_lo_u, int32_t *k_lo_v,
+                                                      int32_t *o_u, int32_t *o_v, int32_t *plane,
+                                                      uint8_t *valid, int64_t *d_nskipped) {
+    __shared__ uint32_t s_skip;
+    if (threadIdx.x == 0) s_skip = 0;
+    __syncthreads();
+    uint32_t skipped = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrec;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        // k_lo and o are 0 for skipped records
+        RecIndex ix = index_record<T>(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2]);
+        k_lo_u[r] = ix.ku;
+        k_lo_v[r] = ix.kv;
+        o_u[r] = ix.ou;
+        o_v[r] = ix.ov;
+        plane[r] = ix.plane;
+        valid[r] = (uint8_t)ix.valid;
+        skipped += !ix.valid;
+    }
+    if (d_nskipped) {
+        if (skipped) atomicAdd(&s_skip, skipped);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_skip)
+            atomicAdd((unsigned long long *)d_nskipped, (unsigned long long)s_skip);
+    }
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int grid_blocks(int64_t n, int threads) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return (int)b;
+}
+
+template <typename T>
+hipError_t malloc_bytes(PlanState &P, T **p, size_t bytes, hipStream_t s) {
+    hipError_t e = P.stream_ordered ? hipMallocAsync((void **)p, bytes, s)
+                                    : hipMalloc((void **)p, bytes);
+    if (e == hipSuccess) P.bytes += bytes;
+    return e;
+}
+
+}  // namespace
+
+mg_status launch_compute_indices(const DevGeom &g, int64_t nrec, const void *uvw,
+                                 mg_dtype uvw_dtype, int32_t *k_lo_u, int32_t *k_lo_v,
+                                 int32_t *o_u, int32_t *o_v, int32_t *plane, uint8_t *valid,
+                                 int64_t *d_nskipped, hipStream_t stream) {
+    if (nrec == 0) return MG_OK;
+    int nb = grid_blocks(nrec, 256);
+    if (uvw_dtype == MG_F32)
+        hipLaunchKernelGGL(indices_kernel<float>, dim3(nb), dim3(256), 0, stream, g, nrec,
+                           (const float *)uvw, k_lo_u, k_lo_v, o_u, o_v, plane, valid, d_nskipped);
+    else
+        hipLaunchKernelGGL(indices_kernel<double>, dim3(nb), dim3(256), 0, stream, g, nrec,
+                           (const double *)uvw, k_lo_u, k_lo_v, o_u, o_v, plane, valid,
+                           d_nskipped);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("index kernel: ") + hipGetErrorString(e));
+    return MG_OK;
+}
+
+mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStream_t stream) {
+    const int64_t nrec = P.nrec;
+    const int64_t nb = P.nbuckets;
+    const uint32_t R = (uint32_t)P.R;
+    const int np = P.nplanes_eff;
+    hipError_t e = hipSuccess;
+    // persistent plan arrays
+    P.max_chunks = nb + nrec / R + 1;
+    if ((e = malloc_bytes(P, &P.smeta, sizeof(RecMeta) * (size_t)(nrec + 1), stream)) ||
+        (e = malloc_bytes(P, &P.sperm, sizeof(uint32_t) * (size_t)(nrec + 1), stream)) ||
+        (e = malloc_bytes(P, &P.chunks, sizeof(Chunk) * (size_t)P.max_chunks, stream)) ||
+        (e = malloc_bytes(P, &P.plane_cfirst, sizeof(uint32_t) * (size_t)(np + 1), stream)) ||
+        (e = malloc_bytes(P, &P.d_planes, sizeof(PlaneLayout) * (size_t)np, stream)) ||
+        (e = malloc_bytes(P, &P.counters, sizeof(int64_t) * 4, stream)))
+        return set_error(MG_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
+    // temporaries (stream-ordered)
+    RecMeta *meta = nullptr;
+    uint32_t *bucket_of = nullptr, *hist = nullptr, *bstart = nullptr, *cursor = nullptr,
+             *cstart = nullptr;
+    uint2 *sums = nullptr;
+    const int64_t nscan = (nb + kScanBlock - 1) / kScanBlock;
+    auto tmp = [&](void **p, size_t bytes) { return hipMallocAsync(p, bytes, stream); };
+    if ((e = tmp((void **)&meta, sizeof(RecMeta) * (size_t)(nrec + 1))) ||
+        (e = tmp((void **)&bucket_of, sizeof(uint32_t) * (size_t)(nrec + 1))) ||
+        (e = tmp((void **)&hist, sizeof(uint32_t) * (size_t)nb)) ||
+        (e = tmp((void **)&bstart, sizeof(uint32_t) * (size_t)nb)) ||
+        (e = tmp((void **)&cursor, sizeof(uint32_t) * (size_t)nb)) ||
+        (e = tmp((void **)&cstart, sizeof(uint32_t) * (size_t)nb)) ||
+        (e = tmp((void **)&sums, sizeof(uint2) * (size_t)(nscan + 1))))
+        return set_error(MG_ENOMEM, std::string("plan scratch: ") + hipGetErrorString(e));
+
+    hipMemcpyAsync(P.d_planes, P.planes.data(), sizeof(PlaneLayout) * np, hipMemcpyHostToDevice,
+                   stream);
+    // zero-fill with a kernel (no memset nodes, so the calls stay capturable)
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t *)P.counters,
+                       (int64_t)8, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_blocks(nb, 256)), dim3(256), 0, stream, hist,
+                       nb, 0u);
+    if (nrec > 0) {
+        int g1 = grid_blocks(nrec, 256);
+        if (uvw_dtype == MG_F32)
+            hipLaunchKernelGGL(index_bucket_kernel<float>, dim3(g1), dim3(256), 0, stream, P.geom,
+                               P.d_planes, nrec, (const float *)uvw, meta, bucket_of, hist,
+                               P.counters);
+        else
+            hipLaunchKernelGGL(index_bucket_kernel<double>, dim3(g1), dim3(256), 0, stream,
+                               P.geom, P.d_planes, nrec, (const double *)uvw, meta, bucket_of,
+                               hist, P.counters);
+    }
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nscan), dim3(256), 0, stream, hist, nb,
+                       R, sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, stream, sums, nscan, sums + nscan);
+    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nscan), dim3(256), 0, stream, hist, nb, R,
+                       sums, bstart, cursor, cstart);
+    if (nrec > 0)
+        hipLaunchKernelGGL(scatter_kernel, dim3(grid_blocks(nrec, 256)), dim3(256), 0, stream,
+                           nrec, meta, bucket_of, cursor, P.smeta, P.sperm);
+    hipLaunchKernelGGL(chunk_list_kernel, dim3(grid_blocks(nb, 256)), dim3(256), 0, stream, nb, R,
+                       hist, bstart, cstart, P.chunks);
+    hipLaunchKernelGGL(plane_ranges_kernel, dim3(1), dim3(256), 0, stream, np, P.d_planes, nb,
+                       cstart, sums + nscan, P.plane_cfirst, P.counters);
+    hipLaunchKernelGGL(chunk_sort_kernel, dim3(4096), dim3(256), 0, stream, P.counters,
+                       P.d_planes, np, P.chunks, P.smeta, P.sperm);
+    e = hipGetLastError();
+    hipFreeAsync(meta, stream);
+    hipFreeAsync(bucket_of, stream);
+    hipFreeAsync(hist, stream);
+    hipFreeAsync(bstart, stream);
+    hipFreeAsync(cursor, stream);
+    hipFreeAsync(cstart, stream);
+    hipFreeAsync(sums, stream);
+    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("plan kernels: ") + hipGetErrorString(e));
+    return MG_OK;
+}
+
+}  // namespace mg

@@ -304,3 +304,35 @@ def subsample(nrec: int, k: int, seed: int = SEED_SUBSAMPLE) -> np.ndarray:
     """Sorted random subset of k record indices out of nrec."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.sort(rng.choice(nrec, size=min(k, nrec), replace=False))
+
+
+def config_wproj_device(device, n_ant: int = 256, n_times: int = 32, n_chan: int = 128,
+                        n: int = 8192, nplanes: int = 32, s_min: int = 8, s_max: int = 64,
+                        beta: int = 4, r_max_m: float = 2500.0, seed: int = SEED_ANTENNAS,
+                        name: Optional[str] = None) -> Workload:
+    """config_wproj with the [time][baseline][channel] uvw expansion done on
+    `device` (torch), for the large workloads.  The per-channel scaling is
+    the same float64 product as the numpy path, so the values are identical;
+    uvw is returned as a float32 device tensor."""
+    import torch
+    ant = antennas_log_radial(n_ant, 20.0, r_max_m, seed)
+    bl = baselines_enu(ant)
+    uvw_m = baseline_uvw_m(bl, math.radians(-30.0), math.radians(-30.0), hour_angles(n_times))
+    freqs = np.linspace(1.2e9, 1.6e9, n_chan, endpoint=False)
+    um = torch.from_numpy(uvw_m).to(device)
+    fr = torch.from_numpy(freqs / C_LIGHT).to(device)
+    T, B, _ = uvw_m.shape
+    out = torch.empty(T * B * n_chan, 3, dtype=torch.float32, device=device)
+    umax = 0.0
+    wmax = 0.0
+    step = max(1, T // 8)
+    for t0 in range(0, T, step):
+        blk = um[t0:t0 + step, :, None, :] * fr[None, None, :, None]
+        umax = max(umax, float(blk[..., :2].abs().max()))
+        wmax = max(wmax, float(blk[..., 2].abs().max()))
+        out[t0 * B * n_chan:(t0 + blk.shape[0]) * B * n_chan] = blk.reshape(-1, 3).to(torch.float32)
+        del blk
+    scale = 0.5 * (n / 2 - s_max) / umax
+    bank = wproj_bank(nplanes, s_min, s_max, beta, wmax, scale)
+    return Workload(name or f"wproj-{n}-P{nplanes}-S{s_min}to{s_max}", n, 4, beta, scale,
+                    out, "wproj", s_max, bank=bank)
