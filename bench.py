@@ -40,7 +40,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--channels", type=int, default=128,
                     help="channels of the W-projection workload (128 = full size)")
@@ -57,6 +57,9 @@ def main():
     from paper_2111_04141_amd import workload as W
 
     dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(dev)
+    log(f"[bench] device {props.name}, {props.multi_processor_count} CUs, "
+        f"{props.total_memory / 2**30:.0f} GiB")
     t0 = time.time()
     wl = W.config_wproj_device(dev, n_chan=args.channels,
                                name=("wproj-8192-P32-S8to64-134M" if args.channels == 128

@@ -43,12 +43,15 @@ int lds_limit_bytes() {
     return v > 0 ? v : 65536;
 }
 
-// Tile side for a gridder class: the largest of 32, 16, 8 whose LDS region
-// (tile + S_max - 1)^2 x npol x 8 bytes fits the per-workgroup LDS limit.
+// Tile side for a gridder class: 16, or 8 where the LDS region
+// (tile + S_max - 1)^2 x npol x 8 bytes would not fit the per-workgroup LDS
+// limit.  Small tiles keep the region small, so several workgroups share a
+// CU; the record density of all but the sparsest planes keeps the per-chunk
+// region flush small next to the chunk's work.
 int tile_for_class(int cls, int npol, int lds_limit) {
     if (cls == 3) return 16;
     const int smax = cls == 0 ? 8 : cls == 1 ? 16 : 32;
-    for (int T : {32, 16, 8}) {
+    for (int T : {16, 8}) {
         size_t bytes = (size_t)(T + smax - 1) * (T + smax - 1) * npol * 8;
         if (bytes <= (size_t)lds_limit) return T;
     }
@@ -78,6 +81,7 @@ mg_status check_common(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t n
             return set_error(MG_EINVAL, "beta * support must be even");
         if (k->ntaps < (int64_t)g->beta * k->support + 1)
             return set_error(MG_EINVAL, "separable table shorter than beta*S+1");
+        if (k->ntaps > 0x7fffffffLL) return set_error(MG_EINVAL, "tap table too large");
     } else if (k->kind == MG_KERNEL_WPROJ) {
         if (k->nplanes < 1 || k->nplanes > kMaxPlanes)
             return set_error(MG_EINVAL, "nplanes must be in 1..128");
@@ -92,6 +96,8 @@ mg_status check_common(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t n
             const int64_t w = (int64_t)g->beta * S + 1;
             if (k->plane_offset[p] < 0 || k->plane_offset[p] + w * w > k->ntaps)
                 return set_error(MG_EINVAL, "plane table outside the tap array");
+            if (k->plane_offset[p] + w * w > 0x7fffffffLL)
+                return set_error(MG_EINVAL, "tap table too large");
         }
     } else {
         return set_error(MG_EINVAL, "unknown kernel kind");
@@ -167,6 +173,8 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
         L.ntu = (g->nu + L.T - 1) / L.T;
         L.ntv = (g->nv + L.T - 1) / L.T;
         L.base = base;
+        L.rowlen = g->beta * L.S + 1;
+        L.tap_off = (k->kind == MG_KERNEL_WPROJ) ? (uint32_t)k->plane_offset[p] : 0u;
         base += (int64_t)L.ntu * L.ntv;
     }
     P.nbuckets = base;

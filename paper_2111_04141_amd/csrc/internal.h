@@ -14,11 +14,13 @@ namespace mg {
 //   cell (k_lo_u, k_lo_v).
 struct PlaneLayout {
     int32_t S;          // support of the plane
-    int32_t T;          // tile side in cells (16 or 32)
+    int32_t T;          // tile side in cells (8, 16 or 32)
     int32_t log2T;
     int32_t ntu, ntv;   // tiles per axis
     int64_t base;       // first bucket of the plane
     int32_t cls;        // gridder class (see grid.hip)
+    int32_t rowlen;     // beta * S + 1: entries per table row
+    uint32_t tap_off;   // first table element of the plane
 };
 
 // One chunk: up to R records of one bucket, cell-sorted inside the chunk.
@@ -72,7 +74,7 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hip
 // Gridder classes: support range -> slots per lane and LDS tile use.
 //   class 0: S <= 8   (one window slot per lane)
 //   class 1: S <= 16  (up to 4 slots per lane)
-//   class 2: S <= 32  (up to 16 slots per lane)
+//   class 2: S <= 32  (up to 8 slots per lane, slots split over 2 waves)
 //   class 3: S <= 64  (16 slots per lane, slots split over the 4 waves,
 //                      commits straight to the grid)
 inline int support_class(int S) { return S <= 8 ? 0 : S <= 16 ? 1 : S <= 32 ? 2 : 3; }

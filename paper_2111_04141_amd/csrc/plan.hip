@@ -17,6 +17,38 @@ namespace {
 
 constexpr uint32_t kInvalidBucket = 0xffffffffu;
 
+// Wave-aggregated counter increment.  Lanes with `active` add 1 to
+// counters[key]; lanes sharing a key are served by one atomic issued by the
+// lowest of them.  Returns, for each active lane, the counter's value before
+// the group's add plus the lane's rank within its group (so the lanes of a
+// group get consecutive values in lane order).  Records arrive in
+// measurement-set order, where consecutive channels of a baseline share a
+// bucket, so one atomic per group replaces up to 64 serialised ones.
+__device__ inline uint32_t wave_counter_add(uint32_t *counters, uint32_t key, bool active,
+                                            bool need_value) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t pending = __ballot(active);
+    uint32_t result = 0;
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const uint32_t lkey = __builtin_amdgcn_readlane(key, leader);
+        const uint64_t group = __ballot(active && key == lkey) & pending;
+        uint32_t base = 0;
+        if (lane == leader) {
+            const uint32_t cnt = (uint32_t)__popcll(group);
+            if (need_value) base = atomicAdd(&counters[lkey], cnt);
+            else atomicAdd(&counters[lkey], cnt);
+        }
+        if (need_value) {
+            base = __builtin_amdgcn_readlane(base, leader);
+            if ((group >> lane) & 1ull) result = base + (uint32_t)__popcll(group & lt);
+        }
+        pending &= ~group;
+    }
+    return result;
+}
+
 // ---------------------------------------------------------------------------
 // index rule -> packed meta, bucket id, bucket histogram, skipped count
 // ---------------------------------------------------------------------------
@@ -29,21 +61,30 @@ __global__ __launch_bounds__(256) void index_bucket_kernel(
     if (threadIdx.x == 0) s_skip = 0;
     __syncthreads();
     uint32_t skipped = 0;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrec;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        RecIndex ix = index_record<T>(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2]);
+    // every lane of a wave runs the same number of iterations (the
+    // aggregated atomic needs the whole wave)
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int64_t r0 = first; r0 < nrec; r0 += stride) {
+        const int64_t r = r0 + (threadIdx.x & 63);
+        const bool in = r < nrec;
+        RecIndex ix;
+        ix.valid = 0;
+        if (in) ix = index_record<T>(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2]);
         uint32_t b = kInvalidBucket;
         if (ix.valid) {
             const PlaneLayout pl = planes[ix.plane < 0 ? 0 : ix.plane];
             uint32_t tu = (uint32_t)ix.ku >> pl.log2T;
             uint32_t tv = (uint32_t)ix.kv >> pl.log2T;
             b = (uint32_t)(pl.base + (int64_t)tv * pl.ntu + tu);
-            atomicAdd(&hist[b], 1u);
-        } else {
+        } else if (in) {
             ++skipped;
         }
-        meta[r] = pack_meta(ix);
-        bucket_of[r] = b;
+        wave_counter_add(hist, b, ix.valid != 0, false);
+        if (in) {
+            meta[r] = pack_meta(ix);
+            bucket_of[r] = b;
+        }
     }
     if (skipped) atomicAdd(&s_skip, skipped);
     __syncthreads();
@@ -148,13 +189,17 @@ __global__ __launch_bounds__(256) void scatter_kernel(int64_t nrec,
                                                       uint32_t *__restrict__ cursor,
                                                       RecMeta *__restrict__ smeta,
                                                       uint32_t *__restrict__ sperm) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrec;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t b = bucket_of[r];
-        if (b == kInvalidBucket) continue;
-        uint32_t pos = atomicAdd(&cursor[b], 1u);
-        smeta[pos] = meta[r];
-        sperm[pos] = (uint32_t)r;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int64_t r0 = first; r0 < nrec; r0 += stride) {
+        const int64_t r = r0 + (threadIdx.x & 63);
+        const uint32_t b = (r < nrec) ? bucket_of[r] : kInvalidBucket;
+        const bool act = b != kInvalidBucket;
+        const uint32_t pos = wave_counter_add(cursor, b, act, true);
+        if (act) {
+            smeta[pos] = meta[r];
+            sperm[pos] = (uint32_t)r;
+        }
     }
 }
 
@@ -199,7 +244,9 @@ __global__ void plane_ranges_kernel(int32_t nplanes, const PlaneLayout *__restri
 }
 
 // ---------------------------------------------------------------------------
-// per-chunk counting sort by cell inside the tile (row-major), in LDS;
+// per-chunk counting sort by cell inside the tile, column-major (u outer,
+// v inner: consecutive records step along v, so a moving window retires one
+// row of slots at a time), in LDS;
 // also records the chunk's k_lo bounding box
 // ---------------------------------------------------------------------------
 constexpr int kMaxR = 2048;
@@ -234,7 +281,7 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restri
             m_in[i] = m;
             p_in[i] = sperm[ch.start + i];
             uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
-            atomicAdd(&hist[(dv << pl.log2T) | du], 1u);
+            atomicAdd(&hist[(du << pl.log2T) | dv], 1u);
             umin = min(umin, du);
             umax = max(umax, du);
             vmin = min(vmin, dv);
@@ -269,7 +316,7 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restri
         for (uint32_t i = threadIdx.x; i < ch.len; i += blockDim.x) {
             RecMeta m = m_in[i];
             uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
-            uint32_t pos = atomicAdd(&hist[(dv << pl.log2T) | du], 1u);
+            uint32_t pos = atomicAdd(&hist[(du << pl.log2T) | dv], 1u);
             smeta[ch.start + pos] = m;
             sperm[ch.start + pos] = p_in[i];
         }
