@@ -49,11 +49,14 @@ int lds_limit_bytes() {
 // CU; the record density of all but the sparsest planes keeps the per-chunk
 // region flush small next to the chunk's work.
 int tile_for_class(int cls, int npol, int lds_limit) {
+    (void)npol;
     if (cls == 3) return 16;
     const int smax = cls == 0 ? 8 : cls == 1 ? 16 : 32;
+    // region: 8 int32 per cell (4 polarisations, re and im); keep room for
+    // two workgroups per CU
     for (int T : {16, 8}) {
-        size_t bytes = (size_t)(T + smax - 1) * (T + smax - 1) * npol * 8;
-        if (bytes <= (size_t)lds_limit) return T;
+        size_t bytes = (size_t)(T + smax - 1) * (T + smax - 1) * 8 * sizeof(int32_t);
+        if (2 * bytes <= (size_t)lds_limit) return T;
     }
     return 8;
 }
@@ -175,6 +178,7 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
         L.base = base;
         L.rowlen = g->beta * L.S + 1;
         L.tap_off = (k->kind == MG_KERNEL_WPROJ) ? (uint32_t)k->plane_offset[p] : 0u;
+        L.wmax = 0.0f;   // filled on the device by the plan build
         base += (int64_t)L.ntu * L.ntv;
     }
     P.nbuckets = base;

@@ -1,29 +1,35 @@
 // Gridding (scatter) kernels.
 //
-// Work unit: one chunk = up to R records of one (plane, uv tile) bucket,
-// cell-sorted.  A workgroup of 4 waves takes a chunk:
+// Work unit: one chunk = up to R cell-sorted records of one (plane, uv tile)
+// bucket, taken by a workgroup of 4 waves.
 //
-//  * Each wave keeps a moving window of grid cells in registers.  The
-//    window has one slot per kernel tap offset class: slot (su, sv),
-//    0 <= su, sv < S, owns the grid cells congruent to (su, sv) modulo S.
-//    Every record's S x S footprint holds exactly one cell of each class,
-//    so for every record every slot has work, and a slot's accumulators
-//    (4 polarisations, complex) keep summing contributions while its cell
-//    stays inside the footprint of consecutive records.  This is the
+//  * Each wave keeps a moving window of S x S slots in registers: slot
+//    (su, sv) owns the grid cells congruent to (su, sv) modulo S, so every
+//    record's S x S footprint holds exactly one cell of each slot, and a
+//    slot's accumulators (4 polarisations, complex) keep summing while its
+//    cell stays inside the footprints of consecutive records.  This is the
 //    owner-computes scheme of Romein's GPU gridder, which the thesis's
-//    Convolutional Gridder builds on (Chapter 4); here the slots are spread
-//    over the 64 lanes of a wave (K slots per lane) and the records come
-//    cell-sorted, so windows move rarely.
+//    Convolutional Gridder builds on (Chapter 4); the slots are spread over
+//    the 64 lanes of a wave and the records come cell-sorted, so windows
+//    move rarely where records are dense.
 //  * When a slot's cell leaves the footprint its sums are committed into an
-//    LDS copy of the chunk's grid region (tile plus S-1 halo), which all 4
-//    waves share (LDS float atomics).  At the end of the chunk the region
-//    is added to the grid in HBM with coalesced float atomics, so each grid
-//    cell sees at most one HBM update per chunk.
-//  * For supports above 32 the LDS region does not fit; the 4 waves split
-//    the S^2 slots between them and commit straight to HBM.
+//    LDS copy of the chunk's grid region (tile plus S-1 halo) shared by the
+//    4 waves.  The region holds 32-bit fixed point: each chunk first bounds
+//    every partial sum it can produce (2 * max|tap component| * sum over its
+//    records of max|visibility component|) and picks the power-of-two scale
+//    that maps that bound to 2^30, so integer LDS atomics (which run at full
+//    wave rate, unlike float LDS atomics, which serialise per lane) add the
+//    commits exactly and cannot overflow; the quantum is 2^-31 of the bound
+//    per commit.  At the end of the chunk the region is converted back to
+//    FP32 and added to the grid with float atomics, one per touched cell.
+//  * For supports above 32 the region does not fit; the 4 waves split the
+//    S^2 slots between them and commit straight to the grid.
 //
 // All polarisations are handled per visit: one tap load feeds 4 complex
-// multiply-adds (the thesis's Polarisation Gain, Section 3.5).
+// multiply-adds (the thesis's Polarisation Gain, Section 3.5).  Records are
+// read on the scalar unit (visibilities become SGPR operands of the FMAs);
+// the table conjugation for w < 0 is folded into the visibilities as sign
+// flips.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -33,36 +39,63 @@ namespace mg {
 namespace {
 
 constexpr uint32_t kNoCell = 0xffffffffu;
+constexpr int kBatch = 2;   // records per batch of scalar loads
 
 struct GridParams {
     int32_t npol, nu, nv, beta;
     int32_t p_lo, p_hi;       // planes handled by this launch
 };
 
-// Records processed per batch of scalar loads (fewer for many slots per
-// lane, to bound the registers holding the batch's taps).
-template <int KMAX> struct BatchOf { static constexpr int value = KMAX >= 8 ? 2 : 4; };
+// (kr + j ki)(vr + j vi) = kr vr - ki vi + j (kr vi + ki vr).  With the
+// conjugate table (w < 0) ki flips sign.  va = -vi (or +vi), vb = vr (or -vr).
+struct FoldedVis {
+    float vr[4], vi[4], va[4], vb[4];
+};
 
-// KMAX: slots per lane (compile-time upper bound); NG: slot groups (waves
-// that share one chunk's records but own different slots); LDS: commit into
-// the shared LDS region (else straight into the grid).
-//
-// Per record the wave does, on the scalar unit: decode the packed indices,
-// fold the table conjugation into the visibilities, form the record's tap
-// base.  Per slot, on the vector unit: one tap load (SGPR base + the slot's
-// cached byte offset) and 16 FMAs (4 polarisations x complex).  The slot
-// offsets and the window test are redone only when the record's first cell
-// differs from the previous record's; records are cell-sorted, so runs of
-// records share it.
+__device__ inline FoldedVis fold_vis(const RecMeta m, const float4 v01, const float4 v23) {
+    FoldedVis f;
+    f.vr[0] = v01.x; f.vi[0] = v01.y; f.vr[1] = v01.z; f.vi[1] = v01.w;
+    f.vr[2] = v23.x; f.vi[2] = v23.y; f.vr[3] = v23.z; f.vi[3] = v23.w;
+    const uint32_t flip = meta_conj(m) ? 0u : 0x80000000u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        f.va[q] = __uint_as_float(__float_as_uint(f.vi[q]) ^ flip);
+        f.vb[q] = __uint_as_float(__float_as_uint(f.vr[q]) ^ flip ^ 0x80000000u);
+    }
+    return f;
+}
+
+__device__ inline void fma_complex(float (&acc)[8], const float2 w, const FoldedVis &f) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc[2 * q] = fmaf(w.x, f.vr[q], fmaf(w.y, f.va[q], acc[2 * q]));
+        acc[2 * q + 1] = fmaf(w.x, f.vi[q], fmaf(w.y, f.vb[q], acc[2 * q + 1]));
+    }
+}
+
+__device__ inline void fma_real(float (&acc)[8], const float w, const FoldedVis &f) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc[2 * q] = fmaf(w, f.vr[q], acc[2 * q]);
+        acc[2 * q + 1] = fmaf(w, f.vi[q], acc[2 * q + 1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// moving-window gridder
+// ---------------------------------------------------------------------------
+// KMAX: slots per lane (compile-time bound); NG: waves sharing one chunk's
+// records but owning different slots; LDS: commit into the shared
+// fixed-point region (else straight into the grid with float atomics).
 template <int KMAX, int NG, bool SEP, typename TapT, bool LDS>
 __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
     const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
     const uint32_t *__restrict__ plane_cfirst, const PlaneLayout *__restrict__ planes,
     GridParams prm) {
-    extern __shared__ float2 region[];
+    extern __shared__ int32_t region[];   // [8][RH][RW]: (pol, re/im) planes
+    __shared__ float s_bound[kWavesPerGroup];
     constexpr int NSPLIT = kWavesPerGroup / NG;
-    constexpr int kBatch = BatchOf<KMAX>::value;
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);   // bytes per tap
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -86,31 +119,47 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
         const uint32_t cv0 = tv0 + ((ch.bbox >> 16) & 0xffu);
         const int RW = (int)((ch.bbox >> 8) & 0xffu) - (int)(ch.bbox & 0xffu) + S;
         const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
+        const int plane_cells = RH * RW;
         const uint32_t rowlen = (uint32_t)pl.rowlen;
         const char *tplane = reinterpret_cast<const char *>(taps) + (size_t)pl.tap_off * kElem;
+        const uint32_t rb0 = ch.start, re0 = ch.start + ch.len;
 
+        // fixed-point scale of this chunk: 2^scale * bound <= 2^30
+        int scale = 0;
         if constexpr (LDS) {
-            for (int i = threadIdx.x; i < npol * RH * RW; i += kGroupThreads)
-                region[i] = make_float2(0.0f, 0.0f);
+            for (int i = threadIdx.x; i < 8 * plane_cells; i += kGroupThreads) region[i] = 0;
+            float part = 0.0f;
+            for (uint32_t r = rb0 + threadIdx.x; r < re0; r += kGroupThreads) {
+                const float4 a = svis[2 * (size_t)r], b = svis[2 * (size_t)r + 1];
+                const float m = fmaxf(fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))),
+                                      fmaxf(fmaxf(fabsf(b.x), fabsf(b.y)), fmaxf(fabsf(b.z), fabsf(b.w))));
+                part += m;
+            }
+            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            if (lane == 0) s_bound[wave] = part;
+            __syncthreads();
+            float bound = 0.0f;
+            for (int w = 0; w < kWavesPerGroup; ++w) bound += s_bound[w];
+            // margin for the rounding of the sum above
+            bound = 2.0f * pl.wmax * bound * 1.0001f + 1e-30f;
+            int e;
+            frexpf(bound, &e);          // bound < 2^e
+            scale = max(-120, min(120, 30 - e));
+            scale = (int)uniform_u32((uint32_t)scale);
             __syncthreads();
         }
 
-        // slots of this wave; invalid slots keep offset 0 (a valid tap) and
-        // are never committed
+        // slots of this wave; per-lane flags are bit fields (bit k = slot k)
         const int nslots = S * S;
         const int spg = (nslots + NG - 1) / NG;
         const int kdyn = (spg + kWave - 1) / kWave;
-        // cell[k] = u | v << 16 of the slot's current cell (kNoCell: none yet;
-        // u = 0xffff never is a footprint cell since footprints end below
-        // the grid side, which is at most 65535)
         uint32_t cell[KMAX], offa[KMAX], offb[KMAX];
-        bool sval[KMAX];
+        uint32_t valid_bits = 0;
         float acc[KMAX][8];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const int sl = k * kWave + lane;
-            const int s = grp * spg + sl;
-            sval[k] = (k < kdyn) && (sl < spg) && (s < nslots);
+            if (k < kdyn && sl < spg && grp * spg + sl < nslots) valid_bits |= 1u << k;
             cell[k] = kNoCell;
             offa[k] = 0u;
             offb[k] = 0u;
@@ -118,17 +167,21 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
         }
 
-        auto commit = [&](float (&sums)[8], uint32_t cell_u, uint32_t cell_v) {
+        // adds a slot's sums to its cell
+        auto commit = [&](float (&sums)[8], uint32_t cell_uv) {
+            const uint32_t cu_ = cell_uv & 0xffffu, cv_ = cell_uv >> 16;
+            if constexpr (LDS) {
+                int32_t *dst = &region[(int)(cv_ - cv0) * RW + (int)(cu_ - cu0)];
 #pragma unroll
-            for (int pol = 0; pol < 4; ++pol) {
-                if (pol < npol) {
-                    if constexpr (LDS) {
-                        float2 *dst =
-                            &region[(pol * RH + (int)(cell_v - cv0)) * RW + (int)(cell_u - cu0)];
-                        atomicAdd(&dst->x, sums[2 * pol]);
-                        atomicAdd(&dst->y, sums[2 * pol + 1]);
-                    } else {
-                        float *dst = grid + 2 * (((int64_t)pol * prm.nv + cell_v) * prm.nu + cell_u);
+                for (int q = 0; q < 8; ++q) {
+                    const int32_t v = __float2int_rn(ldexpf(sums[q], scale));
+                    if (v != 0) atomicAdd(&dst[q * plane_cells], v);
+                }
+            } else {
+#pragma unroll
+                for (int pol = 0; pol < 4; ++pol) {
+                    if (pol < npol) {
+                        float *dst = grid + 2 * (((int64_t)pol * prm.nv + cv_) * prm.nu + cu_);
                         unsafeAtomicAdd(dst, sums[2 * pol]);
                         unsafeAtomicAdd(dst + 1, sums[2 * pol + 1]);
                     }
@@ -136,174 +189,159 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             }
         };
 
-        // one record: window update (only when its first cell changed) + FMAs
         uint32_t prev_kuv = 0xffffffffu;
-        auto process = [&](const RecMeta m, const float4 v01, const float4 v23) {
+        auto window_update = [&](const RecMeta m) {
             const uint32_t kuv = m.kuv;
-            if (kuv != prev_kuv) {
-                prev_kuv = kuv;
-                const uint32_t ku = meta_ku(m), kv = meta_kv(m);
-                bool moved[KMAX];
-                bool any = false;
+            if (kuv == prev_kuv) return;
+            prev_kuv = kuv;
+            const uint32_t ku = meta_ku(m), kv = meta_kv(m);
+            uint32_t moved_bits = 0;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (k < kdyn) {
+                    const uint32_t du = (cell[k] & 0xffffu) - ku, dv = (cell[k] >> 16) - kv;
+                    if (max(du, dv) >= (uint32_t)S) moved_bits |= 1u << k;
+                }
+            }
+            moved_bits &= valid_bits;
+            if (__ballot(moved_bits != 0) != 0) {
+                const uint32_t kmu = ku % (uint32_t)S, kmv = kv % (uint32_t)S;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k) {
-                    moved[k] = false;
-                    if (k < kdyn) {
-                        const uint32_t du = (cell[k] & 0xffffu) - ku, dv = (cell[k] >> 16) - kv;
-                        moved[k] = sval[k] && (max(du, dv) >= (uint32_t)S);
-                        any |= moved[k];
-                    }
-                }
-                if (__ballot(any) != 0) {
-                    const uint32_t kmu = ku % (uint32_t)S, kmv = kv % (uint32_t)S;
+                    if (k < kdyn && ((moved_bits >> k) & 1u)) {
+                        if (cell[k] != kNoCell) commit(acc[k], cell[k]);
 #pragma unroll
-                    for (int k = 0; k < KMAX; ++k) {
-                        if (k < kdyn && moved[k]) {
-                            if (cell[k] != kNoCell) commit(acc[k], cell[k] & 0xffffu, cell[k] >> 16);
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-                            // slot (su, sv) owns the cells congruent to it mod S
-                            const uint32_t sidx = (uint32_t)(grp * spg + k * kWave + lane);
-                            const uint32_t sv = sidx / (uint32_t)S, su = sidx - sv * (uint32_t)S;
-                            int du = (int)su - (int)kmu;
-                            int dv = (int)sv - (int)kmv;
-                            du += (du < 0) ? S : 0;
-                            dv += (dv < 0) ? S : 0;
-                            cell[k] = (ku + (uint32_t)du) | ((kv + (uint32_t)dv) << 16);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (k < kdyn) {
-                        const uint32_t du = sval[k] ? (cell[k] & 0xffffu) - ku : 0u;
-                        const uint32_t dv = sval[k] ? (cell[k] >> 16) - kv : 0u;
-                        if constexpr (SEP) {
-                            offa[k] = du * (uint32_t)beta * kElem;
-                            offb[k] = dv * (uint32_t)beta * kElem;
-                        } else {
-                            offa[k] = (dv * (uint32_t)beta * rowlen + du * (uint32_t)beta) * kElem;
-                        }
+                        for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
+                        // slot (su, sv) owns the cells congruent to it mod S
+                        const uint32_t sidx = (uint32_t)(grp * spg + k * kWave + lane);
+                        const uint32_t sv = sidx / (uint32_t)S, su = sidx - sv * (uint32_t)S;
+                        int du = (int)su - (int)kmu;
+                        int dv = (int)sv - (int)kmv;
+                        du += (du < 0) ? S : 0;
+                        dv += (dv < 0) ? S : 0;
+                        cell[k] = (ku + (uint32_t)du) | ((kv + (uint32_t)dv) << 16);
                     }
                 }
             }
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (k < kdyn) {
+                    const bool on = (valid_bits >> k) & 1u;
+                    const uint32_t du = on ? (cell[k] & 0xffffu) - ku : 0u;
+                    const uint32_t dv = on ? (cell[k] >> 16) - kv : 0u;
+                    if constexpr (SEP) {
+                        offa[k] = du * (uint32_t)beta * kElem;
+                        offb[k] = dv * (uint32_t)beta * kElem;
+                    } else {
+                        offa[k] = (dv * (uint32_t)beta * rowlen + du * (uint32_t)beta) * kElem;
+                    }
+                }
+            }
+        };
+
+        auto accumulate = [&](const RecMeta m, const FoldedVis &f) {
             const uint32_t ou1 = meta_ou(m) + 1, ov1 = meta_ov(m) + 1;
-            // (kr + j ki)(vr + j vi) = kr vr - ki vi + j (kr vi + ki vr); the
-            // conjugate table (w < 0) flips the sign of ki.
-            const uint32_t flip = meta_conj(m) ? 0u : 0x80000000u;
-            const float vr[4] = {v01.x, v01.z, v23.x, v23.z};
-            const float vi[4] = {v01.y, v01.w, v23.y, v23.w};
-            float va[4], vb[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                va[q] = __uint_as_float(__float_as_uint(vi[q]) ^ flip);
-                vb[q] = __uint_as_float(__float_as_uint(vr[q]) ^ flip ^ 0x80000000u);
-            }
             if constexpr (SEP) {
                 const char *tu = tplane + (size_t)ou1 * kElem;
                 const char *tv = tplane + (size_t)ov1 * kElem;
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (k < kdyn) {
-                        const float w = TapTraits<TapT>::real((const TapT *)(tu + offa[k]), 0) *
-                                        TapTraits<TapT>::real((const TapT *)(tv + offb[k]), 0);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            acc[k][2 * q] = fmaf(w, vr[q], acc[k][2 * q]);
-                            acc[k][2 * q + 1] = fmaf(w, vi[q], acc[k][2 * q + 1]);
-                        }
-                    }
-                }
+                for (int k = 0; k < KMAX; ++k)
+                    if (k < kdyn)
+                        fma_real(acc[k],
+                                 TapTraits<TapT>::real((const TapT *)(tu + offa[k]), 0) *
+                                     TapTraits<TapT>::real((const TapT *)(tv + offb[k]), 0),
+                                 f);
             } else {
                 const char *tb = tplane + (size_t)(ov1 * rowlen + ou1) * kElem;
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (k < kdyn) {
-                        const float2 w = TapTraits<TapT>::cplx((const TapT *)(tb + offa[k]), 0);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            acc[k][2 * q] = fmaf(w.x, vr[q], fmaf(w.y, va[q], acc[k][2 * q]));
-                            acc[k][2 * q + 1] = fmaf(w.x, vi[q], fmaf(w.y, vb[q], acc[k][2 * q + 1]));
-                        }
-                    }
-                }
+                for (int k = 0; k < KMAX; ++k)
+                    if (k < kdyn) fma_complex(acc[k], TapTraits<TapT>::cplx((const TapT *)(tb + offa[k]), 0), f);
             }
         };
 
         const uint32_t len = ch.len;
         const uint32_t rb = ch.start + (uint32_t)(((uint64_t)len * split) / NSPLIT);
         const uint32_t re = ch.start + (uint32_t)(((uint64_t)len * (split + 1)) / NSPLIT);
-        for (uint32_t r = rb; r < re; r += kBatch) {
-            RecMeta mm[kBatch];
-            float4 va4[kBatch], vb4[kBatch];
-#pragma unroll
-            for (int i = 0; i < kBatch; ++i) {
-                const uint32_t ri = min(r + (uint32_t)i, re - 1);
-                mm[i] = smeta[ri];
-                va4[i] = svis[2 * (size_t)ri];
-                vb4[i] = svis[2 * (size_t)ri + 1];
-            }
-            bool same = (r + kBatch <= re);
-#pragma unroll
-            for (int i = 0; i < kBatch; ++i) same = same && (mm[i].kuv == prev_kuv);
-            if (!SEP && KMAX < 16 && same) {
-                // the window does not move for the whole batch: issue all the
-                // batch's tap loads before the first multiply-add
-                float2 w[kBatch][KMAX];
+        if (rb < re) {
+            // records are read in batches on the scalar unit; the next batch's
+            // loads are issued after the current batch has been consumed
+            // (scalar loads complete out of order: waiting for one is waiting
+            // for all), so they overlap the current batch's multiply-adds
+            RecMeta nm[kBatch];
+            float4 na4[kBatch], nb4[kBatch];
+            auto load_batch = [&](uint32_t r0) {
 #pragma unroll
                 for (int i = 0; i < kBatch; ++i) {
-                    const uint32_t ou1 = meta_ou(mm[i]) + 1, ov1 = meta_ov(mm[i]) + 1;
-                    const char *tb = tplane + (size_t)(ov1 * rowlen + ou1) * kElem;
-#pragma unroll
-                    for (int k = 0; k < KMAX; ++k)
-                        if (k < kdyn) w[i][k] = TapTraits<TapT>::cplx((const TapT *)(tb + offa[k]), 0);
+                    const uint32_t ri = min(r0 + (uint32_t)i, re - 1);
+                    nm[i] = smeta[ri];
+                    na4[i] = svis[2 * (size_t)ri];
+                    nb4[i] = svis[2 * (size_t)ri + 1];
                 }
+            };
+            load_batch(rb);
+            for (uint32_t r = rb; r < re; r += kBatch) {
+                RecMeta mm[kBatch];
+                float4 va4[kBatch], vb4[kBatch];
 #pragma unroll
                 for (int i = 0; i < kBatch; ++i) {
-                    const uint32_t flip = meta_conj(mm[i]) ? 0u : 0x80000000u;
-                    const float vr[4] = {va4[i].x, va4[i].z, vb4[i].x, vb4[i].z};
-                    const float vi[4] = {va4[i].y, va4[i].w, vb4[i].y, vb4[i].w};
-                    float xa[4], xb[4];
+                    mm[i] = nm[i];
+                    va4[i] = na4[i];
+                    vb4[i] = nb4[i];
+                }
+                bool same = (r + kBatch <= re);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        xa[q] = __uint_as_float(__float_as_uint(vi[q]) ^ flip);
-                        xb[q] = __uint_as_float(__float_as_uint(vr[q]) ^ flip ^ 0x80000000u);
+                for (int i = 0; i < kBatch; ++i) same = same && (mm[i].kuv == prev_kuv);
+                same = uniform_u32(same ? 1u : 0u) != 0u;
+                __builtin_amdgcn_sched_barrier(0);
+                load_batch(r + kBatch);
+                if (!SEP && KMAX <= 4 && same) {
+                    // the window stays still for the whole batch: issue all
+                    // tap loads before the first multiply-add
+                    float2 w[kBatch][KMAX];
+#pragma unroll
+                    for (int i = 0; i < kBatch; ++i) {
+                        const uint32_t ou1 = meta_ou(mm[i]) + 1, ov1 = meta_ov(mm[i]) + 1;
+                        const char *tb = tplane + (size_t)(ov1 * rowlen + ou1) * kElem;
+#pragma unroll
+                        for (int k = 0; k < KMAX; ++k)
+                            if (k < kdyn) w[i][k] = TapTraits<TapT>::cplx((const TapT *)(tb + offa[k]), 0);
                     }
 #pragma unroll
-                    for (int k = 0; k < KMAX; ++k) {
-                        if (k < kdyn) {
+                    for (int i = 0; i < kBatch; ++i) {
+                        const FoldedVis f = fold_vis(mm[i], va4[i], vb4[i]);
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                acc[k][2 * q] = fmaf(w[i][k].x, vr[q], fmaf(w[i][k].y, xa[q], acc[k][2 * q]));
-                                acc[k][2 * q + 1] =
-                                    fmaf(w[i][k].x, vi[q], fmaf(w[i][k].y, xb[q], acc[k][2 * q + 1]));
-                            }
+                        for (int k = 0; k < KMAX; ++k)
+                            if (k < kdyn) fma_complex(acc[k], w[i][k], f);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kBatch; ++i) {
+                        if (r + (uint32_t)i < re) {
+                            window_update(mm[i]);
+                            accumulate(mm[i], fold_vis(mm[i], va4[i], vb4[i]));
                         }
                     }
                 }
-            } else {
-#pragma unroll
-                for (int i = 0; i < kBatch; ++i)
-                    if (r + (uint32_t)i < re) process(mm[i], va4[i], vb4[i]);
             }
-        }
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-            if (k < kdyn && sval[k] && cell[k] != kNoCell) commit(acc[k], cell[k] & 0xffffu, cell[k] >> 16);
+            for (int k = 0; k < KMAX; ++k)
+                if (k < kdyn && ((valid_bits >> k) & 1u) && cell[k] != kNoCell) commit(acc[k], cell[k]);
+        }
 
         if constexpr (LDS) {
             __syncthreads();
-            const int n = npol * RH * RW;
+            const int n = npol * plane_cells;
             for (int i = threadIdx.x; i < n; i += kGroupThreads) {
-                const float2 v = region[i];
-                if (v.x != 0.0f || v.y != 0.0f) {
-                    const int ru = i % RW;
-                    const int t = i / RW;
-                    const int rv = t % RH;
-                    const int pol = t / RH;
+                const int ru = i % RW;
+                const int t = i / RW;
+                const int rv = t % RH;
+                const int pol = t / RH;
+                const int32_t qr = region[(2 * pol) * plane_cells + rv * RW + ru];
+                const int32_t qi = region[(2 * pol + 1) * plane_cells + rv * RW + ru];
+                if ((qr | qi) != 0) {
                     float *dst = grid + 2 * (((int64_t)pol * prm.nv + cv0 + rv) * prm.nu + cu0 + ru);
-                    unsafeAtomicAdd(dst, v.x);
-                    unsafeAtomicAdd(dst + 1, v.y);
+                    unsafeAtomicAdd(dst, ldexpf((float)qr, -scale));
+                    unsafeAtomicAdd(dst + 1, ldexpf((float)qi, -scale));
                 }
             }
             __syncthreads();
@@ -350,7 +388,7 @@ void launch_one(const GridPtrs &a, const GridParams &prm, size_t lds, hipStream_
 template <bool SEP, typename TapT>
 hipError_t launch_class(int cls, const GridPtrs &a, const GridParams &prm, int smax, int tile,
                         hipStream_t stream, int blocks) {
-    const size_t lds = (cls <= 2) ? sizeof(float2) * prm.npol * (size_t)(tile + smax - 1) *
+    const size_t lds = (cls <= 2) ? sizeof(int32_t) * 8 * (size_t)(tile + smax - 1) *
                                         (size_t)(tile + smax - 1)
                                   : 0;
     switch (cls) {

@@ -21,6 +21,7 @@ struct PlaneLayout {
     int32_t cls;        // gridder class (see grid.hip)
     int32_t rowlen;     // beta * S + 1: entries per table row
     uint32_t tap_off;   // first table element of the plane
+    float wmax;         // bound on |re|, |im| of one tap weight of the plane
 };
 
 // One chunk: up to R records of one bucket, cell-sorted inside the chunk.
@@ -75,6 +76,8 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hip
 //   class 0: S <= 8   (one window slot per lane)
 //   class 1: S <= 16  (up to 4 slots per lane)
 //   class 2: S <= 32  (up to 8 slots per lane, slots split over 2 waves)
+// Classes 0-2 accumulate committed sums in a fixed-point LDS region (see
+// grid.hip); class 3 commits straight to the grid.
 //   class 3: S <= 64  (16 slots per lane, slots split over the 4 waves,
 //                      commits straight to the grid)
 inline int support_class(int S) { return S <= 8 ? 0 : S <= 16 ? 1 : S <= 32 ? 2 : 3; }

@@ -325,6 +325,35 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restri
 }
 
 // ---------------------------------------------------------------------------
+// per-plane bound on one tap weight's real and imaginary parts: max |tap
+// component| of the plane (W-projection), or max |tap|^2 (separable, whose
+// weight is the product of two taps)
+// ---------------------------------------------------------------------------
+template <typename TapT>
+__device__ inline float tap_abs(const TapT *t, int64_t i) {
+    return fabsf(TapTraits<TapT>::real(t, i));
+}
+
+template <typename TapT>
+__global__ __launch_bounds__(256) void plane_wmax_kernel(PlaneLayout *planes, const TapT *taps,
+                                                         int32_t beta, int32_t separable) {
+    __shared__ float s_max[256];
+    PlaneLayout &pl = planes[blockIdx.x];
+    const int64_t w = (int64_t)beta * pl.S + 1;
+    const int64_t n = separable ? w : 2 * w * w;       // real values
+    const int64_t first = separable ? 0 : 2 * (int64_t)pl.tap_off;
+    float m = 0.0f;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, tap_abs(taps, first + i));
+    s_max[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s_max[threadIdx.x] = fmaxf(s_max[threadIdx.x], s_max[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) pl.wmax = separable ? s_max[0] * s_max[0] : s_max[0];
+}
+
+// ---------------------------------------------------------------------------
 // compute_indices: the index rule written out per record (parity/debug)
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -461,6 +490,18 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
                        cstart, sums + nscan, P.plane_cfirst, P.counters);
     hipLaunchKernelGGL(chunk_sort_kernel, dim3(4096), dim3(256), 0, stream, P.counters,
                        P.d_planes, np, P.chunks, P.smeta, P.sperm);
+    {
+        const int sep = P.kind == MG_KERNEL_SEPARABLE ? 1 : 0;
+        if (P.tap_dtype == MG_F16)
+            hipLaunchKernelGGL(plane_wmax_kernel<__half>, dim3(np), dim3(256), 0, stream,
+                               P.d_planes, (const __half *)P.taps, P.geom.beta, sep);
+        else if (P.tap_dtype == MG_BF16)
+            hipLaunchKernelGGL(plane_wmax_kernel<__hip_bfloat16>, dim3(np), dim3(256), 0, stream,
+                               P.d_planes, (const __hip_bfloat16 *)P.taps, P.geom.beta, sep);
+        else
+            hipLaunchKernelGGL(plane_wmax_kernel<float>, dim3(np), dim3(256), 0, stream,
+                               P.d_planes, (const float *)P.taps, P.geom.beta, sep);
+    }
     e = hipGetLastError();
     hipFreeAsync(meta, stream);
     hipFreeAsync(bucket_of, stream);
