@@ -99,8 +99,8 @@ mg_status check_common(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t n
             const int64_t w = (int64_t)g->beta * S + 1;
             if (k->plane_offset[p] < 0 || k->plane_offset[p] + w * w > k->ntaps)
                 return set_error(MG_EINVAL, "plane table outside the tap array");
-            if (k->plane_offset[p] + w * w > 0x7fffffffLL)
-                return set_error(MG_EINVAL, "tap table too large");
+            if (k->plane_offset[p] + w * w > (1LL << 30))
+                return set_error(MG_EINVAL, "tap table too large (at most 2^30 complex taps)");
         }
     } else {
         return set_error(MG_EINVAL, "unknown kernel kind");
@@ -121,6 +121,7 @@ DevGeom make_geom(const mg_grid_desc *g, const mg_kernel_desc *k) {
         d.nplanes = k->nplanes;
         d.support = 0;
         d.inv_dw = k->inv_dw;
+        d.conj_base = k->ntaps;
         for (int p = 0; p < k->nplanes; ++p) {
             d.plane_support[p] = k->plane_support[p];
             d.plane_offset[p] = k->plane_offset[p];
@@ -185,13 +186,20 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
     if (base >= 0x7fffffffLL) return set_error(MG_EUNSUPPORTED, "too many (plane, tile) buckets");
     // private copy of the tap table(s)
     const size_t esz = dtype_size(k->tap_dtype) * (k->kind == MG_KERNEL_WPROJ ? 2 : 1);
-    P.taps_bytes = esz * (size_t)k->ntaps;
+    // W-projection: the bank followed by its complex conjugate (the table of
+    // records with w < 0)
+    const size_t copies = (k->kind == MG_KERNEL_WPROJ) ? 2 : 1;
+    P.taps_bytes = esz * (size_t)k->ntaps * copies;
     hipError_t e = stream_ordered ? hipMallocAsync(&P.taps, P.taps_bytes, stream)
                                   : hipMalloc(&P.taps, P.taps_bytes);
     if (e != hipSuccess) return set_error(MG_ENOMEM, "tap table allocation failed");
     P.bytes += P.taps_bytes;
-    e = hipMemcpyAsync(P.taps, k->taps, P.taps_bytes, hipMemcpyDeviceToDevice, stream);
+    e = hipMemcpyAsync(P.taps, k->taps, esz * (size_t)k->ntaps, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("tap copy: ") + hipGetErrorString(e));
+    if (copies == 2) {
+        e = launch_conjugate_copy(P.taps, k->tap_dtype, k->ntaps, stream);
+        if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("tap conjugate: ") + hipGetErrorString(e));
+    }
     return plan_build(P, uvw, uvw_dtype, stream);
 }
 

@@ -25,22 +25,25 @@ struct DevGeom {
     double inv_dw;
     int32_t plane_support[kMaxPlanes];
     int64_t plane_offset[kMaxPlanes];   // element offset of plane p
+    int64_t conj_base;                  // W-projection: element offset of the
+                                        // conjugated copy of the bank
 };
 
 // Per-record packed index, 8 bytes:
 //   kuv  = k_lo_u | k_lo_v << 16
-//   info = o_u | o_v << 8 | plane << 16 | conj << 24
+//   toff = W-projection: table element of the record's first tap, i.e.
+//            plane offset + (o_v + 1) * rowlen + (o_u + 1), inside the
+//            conjugated copy of the bank for w < 0;
+//          separable: (o_u + 1) | (o_v + 1) << 16.
+// The gridders then address tap (i, j) as toff + (j * rowlen + i) * beta
+// (or toff_u + i * beta, toff_v + j * beta) without decoding anything else.
 struct RecMeta {
     uint32_t kuv;
-    uint32_t info;
+    uint32_t toff;
 };
 
 __host__ __device__ inline uint32_t meta_ku(RecMeta m) { return m.kuv & 0xffffu; }
 __host__ __device__ inline uint32_t meta_kv(RecMeta m) { return m.kuv >> 16; }
-__host__ __device__ inline uint32_t meta_ou(RecMeta m) { return m.info & 0xffu; }
-__host__ __device__ inline uint32_t meta_ov(RecMeta m) { return (m.info >> 8) & 0xffu; }
-__host__ __device__ inline uint32_t meta_plane(RecMeta m) { return (m.info >> 16) & 0xffu; }
-__host__ __device__ inline uint32_t meta_conj(RecMeta m) { return (m.info >> 24) & 1u; }
 
 // One result of the index rule.
 struct RecIndex {
@@ -102,11 +105,17 @@ __device__ inline RecIndex index_record(const DevGeom &g, T u_, T v_, T w_) {
     return r;
 }
 
-__device__ inline RecMeta pack_meta(const RecIndex &r) {
+__device__ inline RecMeta pack_meta(const DevGeom &g, const RecIndex &r) {
     RecMeta m;
     m.kuv = (uint32_t)r.ku | ((uint32_t)r.kv << 16);
-    m.info = (uint32_t)r.ou | ((uint32_t)r.ov << 8) | ((uint32_t)(r.plane < 0 ? 0 : r.plane) << 16)
-             | ((uint32_t)r.conj << 24);
+    if (g.nplanes == 0) {
+        m.toff = (uint32_t)(r.ou + 1) | ((uint32_t)(r.ov + 1) << 16);
+    } else {
+        const int64_t rowlen = (int64_t)g.beta * r.S + 1;
+        const int64_t p = r.plane < 0 ? 0 : r.plane;
+        m.toff = (uint32_t)(g.plane_offset[p] + (int64_t)(r.ov + 1) * rowlen + (r.ou + 1) +
+                            (r.conj ? g.conj_base : 0));
+    }
     return m;
 }
 

@@ -50,7 +50,6 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_kernel(DegridArgs a, Dev
         const int RW = (int)((ch.bbox >> 8) & 0xffu) - (int)(ch.bbox & 0xffu) + S;
         const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
         const int rowlen = a.beta * S + 1;
-        const int64_t poff = SEP ? 0 : g.plane_offset[p];
         if constexpr (LDS) {
             const int n = npol * RH * RW;
             for (int i = threadIdx.x; i < n; i += kGroupThreads) {
@@ -68,22 +67,21 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_kernel(DegridArgs a, Dev
             const uint32_t r = ch.start + i;
             const RecMeta m = a.smeta[r];
             const uint32_t ku = meta_ku(m), kv = meta_kv(m);
-            const uint32_t ou1 = meta_ou(m) + 1, ov1 = meta_ov(m) + 1;
-            const float sgn = meta_conj(m) ? -1.0f : 1.0f;
             float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             for (int j = 0; j < S; ++j) {
                 float wv = 0.0f;
-                if constexpr (SEP) wv = TapTraits<TapT>::real(taps, (int64_t)(ov1 + j * a.beta));
-                const int64_t trow = poff + (int64_t)(ov1 + j * a.beta) * rowlen + ou1;
+                if constexpr (SEP) wv = TapTraits<TapT>::real(taps, (int64_t)((m.toff >> 16) + j * a.beta));
+                const int64_t trow = (int64_t)m.toff + (int64_t)j * a.beta * rowlen;
                 for (int i2 = 0; i2 < S; ++i2) {
                     float wr, wi;
                     if constexpr (SEP) {
-                        wr = TapTraits<TapT>::real(taps, (int64_t)(ou1 + i2 * a.beta)) * wv;
+                        wr = TapTraits<TapT>::real(taps, (int64_t)((m.toff & 0xffffu) + i2 * a.beta)) * wv;
                         wi = 0.0f;
                     } else {
+                        // records with w < 0 point into the conjugated bank
                         const float2 k = TapTraits<TapT>::cplx(taps, trow + i2 * a.beta);
                         wr = k.x;
-                        wi = sgn * k.y;
+                        wi = k.y;
                     }
 #pragma unroll
                     for (int pol = 0; pol < 4; ++pol) {

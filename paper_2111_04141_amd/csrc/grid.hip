@@ -27,9 +27,9 @@
 //
 // All polarisations are handled per visit: one tap load feeds 4 complex
 // multiply-adds (the thesis's Polarisation Gain, Section 3.5).  Records are
-// read on the scalar unit (visibilities become SGPR operands of the FMAs);
-// the table conjugation for w < 0 is folded into the visibilities as sign
-// flips.
+// read on the scalar unit (visibilities become SGPR operands of the FMAs),
+// and each carries the table offset of its first tap (in the conjugated copy
+// of the bank for w < 0), so the per-record scalar work is small.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -46,34 +46,30 @@ struct GridParams {
     int32_t p_lo, p_hi;       // planes handled by this launch
 };
 
-// (kr + j ki)(vr + j vi) = kr vr - ki vi + j (kr vi + ki vr).  With the
-// conjugate table (w < 0) ki flips sign.  va = -vi (or +vi), vb = vr (or -vr).
-struct FoldedVis {
-    float vr[4], vi[4], va[4], vb[4];
+// Visibilities of one record, 4 polarisations.
+struct RecVis {
+    float vr[4], vi[4];
 };
 
-__device__ inline FoldedVis fold_vis(const RecMeta m, const float4 v01, const float4 v23) {
-    FoldedVis f;
+__device__ inline RecVis unpack_vis(const float4 v01, const float4 v23) {
+    RecVis f;
     f.vr[0] = v01.x; f.vi[0] = v01.y; f.vr[1] = v01.z; f.vi[1] = v01.w;
     f.vr[2] = v23.x; f.vi[2] = v23.y; f.vr[3] = v23.z; f.vi[3] = v23.w;
-    const uint32_t flip = meta_conj(m) ? 0u : 0x80000000u;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        f.va[q] = __uint_as_float(__float_as_uint(f.vi[q]) ^ flip);
-        f.vb[q] = __uint_as_float(__float_as_uint(f.vr[q]) ^ flip ^ 0x80000000u);
-    }
     return f;
 }
 
-__device__ inline void fma_complex(float (&acc)[8], const float2 w, const FoldedVis &f) {
+// acc += w * v for 4 polarisations: (wr + j wi)(vr + j vi) =
+// wr vr - wi vi + j (wr vi + wi vr).  Records with w < 0 point into the
+// conjugated copy of the bank, so no sign logic is needed here.
+__device__ inline void fma_complex(float (&acc)[8], const float2 w, const RecVis &f) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        acc[2 * q] = fmaf(w.x, f.vr[q], fmaf(w.y, f.va[q], acc[2 * q]));
-        acc[2 * q + 1] = fmaf(w.x, f.vi[q], fmaf(w.y, f.vb[q], acc[2 * q + 1]));
+        acc[2 * q] = fmaf(w.x, f.vr[q], fmaf(w.y, -f.vi[q], acc[2 * q]));
+        acc[2 * q + 1] = fmaf(w.x, f.vi[q], fmaf(w.y, f.vr[q], acc[2 * q + 1]));
     }
 }
 
-__device__ inline void fma_real(float (&acc)[8], const float w, const FoldedVis &f) {
+__device__ inline void fma_real(float (&acc)[8], const float w, const RecVis &f) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         acc[2 * q] = fmaf(w, f.vr[q], acc[2 * q]);
@@ -121,7 +117,7 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
         const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
         const int plane_cells = RH * RW;
         const uint32_t rowlen = (uint32_t)pl.rowlen;
-        const char *tplane = reinterpret_cast<const char *>(taps) + (size_t)pl.tap_off * kElem;
+        const char *tbase = reinterpret_cast<const char *>(taps);
         const uint32_t rb0 = ch.start, re0 = ch.start + ch.len;
 
         // fixed-point scale of this chunk: 2^scale * bound <= 2^30
@@ -239,11 +235,10 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             }
         };
 
-        auto accumulate = [&](const RecMeta m, const FoldedVis &f) {
-            const uint32_t ou1 = meta_ou(m) + 1, ov1 = meta_ov(m) + 1;
+        auto accumulate = [&](const RecMeta m, const RecVis &f) {
             if constexpr (SEP) {
-                const char *tu = tplane + (size_t)ou1 * kElem;
-                const char *tv = tplane + (size_t)ov1 * kElem;
+                const char *tu = tbase + (size_t)(m.toff & 0xffffu) * kElem;
+                const char *tv = tbase + (size_t)(m.toff >> 16) * kElem;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k)
                     if (k < kdyn)
@@ -252,7 +247,7 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
                                      TapTraits<TapT>::real((const TapT *)(tv + offb[k]), 0),
                                  f);
             } else {
-                const char *tb = tplane + (size_t)(ov1 * rowlen + ou1) * kElem;
+                const char *tb = tbase + (size_t)m.toff * kElem;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k)
                     if (k < kdyn) fma_complex(acc[k], TapTraits<TapT>::cplx((const TapT *)(tb + offa[k]), 0), f);
@@ -269,13 +264,14 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             // for all), so they overlap the current batch's multiply-adds
             RecMeta nm[kBatch];
             float4 na4[kBatch], nb4[kBatch];
+            // the record arrays are padded by kBatch entries, so a batch may
+            // run past the chunk's end (those records are not used)
             auto load_batch = [&](uint32_t r0) {
 #pragma unroll
                 for (int i = 0; i < kBatch; ++i) {
-                    const uint32_t ri = min(r0 + (uint32_t)i, re - 1);
-                    nm[i] = smeta[ri];
-                    na4[i] = svis[2 * (size_t)ri];
-                    nb4[i] = svis[2 * (size_t)ri + 1];
+                    nm[i] = smeta[r0 + i];
+                    na4[i] = svis[2 * (size_t)(r0 + i)];
+                    nb4[i] = svis[2 * (size_t)(r0 + i) + 1];
                 }
             };
             load_batch(rb);
@@ -300,15 +296,14 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
                     float2 w[kBatch][KMAX];
 #pragma unroll
                     for (int i = 0; i < kBatch; ++i) {
-                        const uint32_t ou1 = meta_ou(mm[i]) + 1, ov1 = meta_ov(mm[i]) + 1;
-                        const char *tb = tplane + (size_t)(ov1 * rowlen + ou1) * kElem;
+                        const char *tb = tbase + (size_t)mm[i].toff * kElem;
 #pragma unroll
                         for (int k = 0; k < KMAX; ++k)
                             if (k < kdyn) w[i][k] = TapTraits<TapT>::cplx((const TapT *)(tb + offa[k]), 0);
                     }
 #pragma unroll
                     for (int i = 0; i < kBatch; ++i) {
-                        const FoldedVis f = fold_vis(mm[i], va4[i], vb4[i]);
+                        const RecVis f = unpack_vis(va4[i], vb4[i]);
 #pragma unroll
                         for (int k = 0; k < KMAX; ++k)
                             if (k < kdyn) fma_complex(acc[k], w[i][k], f);
@@ -318,7 +313,7 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
                     for (int i = 0; i < kBatch; ++i) {
                         if (r + (uint32_t)i < re) {
                             window_update(mm[i]);
-                            accumulate(mm[i], fold_vis(mm[i], va4[i], vb4[i]));
+                            accumulate(mm[i], unpack_vis(va4[i], vb4[i]));
                         }
                     }
                 }
@@ -415,7 +410,8 @@ hipError_t launch_class_t(mg_dtype dt, int cls, const GridPtrs &a, const GridPar
 mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream_t stream) {
     if (P.nrec == 0) return MG_OK;
     float4 *svis = nullptr;
-    hipError_t e = hipMallocAsync((void **)&svis, 2 * sizeof(float4) * (size_t)P.nrec, stream);
+    hipError_t e = hipMallocAsync((void **)&svis, 2 * sizeof(float4) * (size_t)(P.nrec + kBatch),
+                                  stream);
     if (e != hipSuccess) return set_error(MG_ENOMEM, "grid: gather buffer allocation failed");
     {
         int64_t nb = (P.nrec + 255) / 256;

@@ -68,6 +68,10 @@ mg_status launch_compute_indices(const DevGeom &g, int64_t nrec, const void *uvw
                                  int32_t *o_u, int32_t *o_v, int32_t *plane, uint8_t *valid,
                                  int64_t *d_nskipped, hipStream_t stream);
 
+// Writes the complex conjugate of the ntaps-element bank at taps into the
+// ntaps elements that follow it (plan.hip).
+hipError_t launch_conjugate_copy(void *taps, mg_dtype dt, int64_t ntaps, hipStream_t stream);
+
 // Hot kernels (grid.hip, degrid.hip).
 mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream_t stream);
 mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hipStream_t stream);

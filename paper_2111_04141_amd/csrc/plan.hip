@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void index_bucket_kernel(
         }
         wave_counter_add(hist, b, ix.valid != 0, false);
         if (in) {
-            meta[r] = pack_meta(ix);
+            meta[r] = pack_meta(g, ix);
             bucket_of[r] = b;
         }
     }
@@ -407,7 +407,31 @@ hipError_t malloc_bytes(PlanState &P, T **p, size_t bytes, hipStream_t s) {
     return e;
 }
 
+// bank[n + i] = conj(bank[i]) for complex taps stored as (re, im) pairs of T
+template <typename T>
+__global__ __launch_bounds__(256) void conjugate_copy_kernel(T *taps, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        taps[2 * (n + i)] = taps[2 * i];
+        taps[2 * (n + i) + 1] = -taps[2 * i + 1];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_conjugate_copy(void *taps, mg_dtype dt, int64_t n, hipStream_t stream) {
+    const int nb = grid_blocks(n, 256);
+    if (dt == MG_F16)
+        hipLaunchKernelGGL(conjugate_copy_kernel<__half>, dim3(nb), dim3(256), 0, stream,
+                           (__half *)taps, n);
+    else if (dt == MG_BF16)
+        hipLaunchKernelGGL(conjugate_copy_kernel<__hip_bfloat16>, dim3(nb), dim3(256), 0, stream,
+                           (__hip_bfloat16 *)taps, n);
+    else
+        hipLaunchKernelGGL(conjugate_copy_kernel<float>, dim3(nb), dim3(256), 0, stream,
+                           (float *)taps, n);
+    return hipGetLastError();
+}
 
 mg_status launch_compute_indices(const DevGeom &g, int64_t nrec, const void *uvw,
                                  mg_dtype uvw_dtype, int32_t *k_lo_u, int32_t *k_lo_v,
@@ -435,8 +459,9 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
     hipError_t e = hipSuccess;
     // persistent plan arrays
     P.max_chunks = nb + nrec / R + 1;
-    if ((e = malloc_bytes(P, &P.smeta, sizeof(RecMeta) * (size_t)(nrec + 1), stream)) ||
-        (e = malloc_bytes(P, &P.sperm, sizeof(uint32_t) * (size_t)(nrec + 1), stream)) ||
+    // +2: the gridders read records in pairs and may read one past the end
+    if ((e = malloc_bytes(P, &P.smeta, sizeof(RecMeta) * (size_t)(nrec + 2), stream)) ||
+        (e = malloc_bytes(P, &P.sperm, sizeof(uint32_t) * (size_t)(nrec + 2), stream)) ||
         (e = malloc_bytes(P, &P.chunks, sizeof(Chunk) * (size_t)P.max_chunks, stream)) ||
         (e = malloc_bytes(P, &P.plane_cfirst, sizeof(uint32_t) * (size_t)(np + 1), stream)) ||
         (e = malloc_bytes(P, &P.d_planes, sizeof(PlaneLayout) * (size_t)np, stream)) ||
