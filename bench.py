@@ -15,7 +15,8 @@ S_p^2, divided by the step time.
 Also printed: the dominant unit (the gridding kernels of a prepared plan,
 timed with HIP events on the launch stream) against the FP32 vector roof;
 degridding through the same plan; and the FP64 CPU oracle's rate on a
-1,000,000-record sample of the same workload.
+4,000,000-record sample of the same workload; and a serving trace
+(Poisson arrivals of uneven jobs) through the continuous-batching server.
 """
 import argparse
 import json
@@ -35,6 +36,41 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def serving_leg(dev, njobs):
+    """A Poisson trace of uneven gridding jobs through the serving API: the
+    jobs one at a time, then at offered load 0.8 (latency) and as one burst
+    (aggregate rate)."""
+    from paper_2111_04141_amd import serving as SV
+    t0 = time.time()
+    pools = SV.TracePools(dev)
+    jobs = SV.make_trace(pools, njobs)
+    log(f"[bench] serving trace: {njobs} jobs, pools built in {time.time() - t0:.1f}s")
+    SV.run_serial(pools, jobs[:4])                       # warm the allocator and kernels
+    serial = SV.run_serial(pools, jobs)
+    light = SV.run_served(pools, jobs, rho=0.8, mean_service_s=serial["mean_service_s"])
+    burst = SV.run_served(pools, jobs, rho=1e6, mean_service_s=serial["mean_service_s"])
+    log(f"[bench] serving: serial {serial['rate_updates_per_s']:.3e}/s, "
+        f"rho 0.8 p50 {light['latency_ms_p50']:.2f} ms p99 {light['latency_ms_p99']:.2f} ms, "
+        f"burst {burst['rate_updates_per_s']:.3e}/s (max running {burst['max_running']})")
+    return {
+        "trace": f"{njobs} jobs, Poisson arrivals, records log-uniform 1e4..1e7, grids "
+                 "512^2..4096^2, half 7x7 separable (beta 8), half W-projection 16 planes "
+                 "S 8->32 (beta 4), seed %d" % SV.W.SEED_TRACE,
+        "updates": serial["updates"],
+        "serial_rate_updates_per_s": serial["rate_updates_per_s"],
+        "serial_mean_service_ms": 1e3 * serial["mean_service_s"],
+        "rho0.8_latency_ms_p50": light["latency_ms_p50"],
+        "rho0.8_latency_ms_p99": light["latency_ms_p99"],
+        "rho0.8_rate_updates_per_s": light["rate_updates_per_s"],
+        "burst_rate_updates_per_s": burst["rate_updates_per_s"],
+        "burst_latency_ms_p50": burst["latency_ms_p50"],
+        "burst_latency_ms_p99": burst["latency_ms_p99"],
+        "burst_max_running": burst["max_running"],
+        "burst_bytes_peak": burst["bytes_peak"],
+        "budget_bytes": burst["budget"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +80,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--channels", type=int, default=128,
                     help="channels of the W-projection workload (128 = full size)")
+    ap.add_argument("--serving-jobs", type=int, default=40,
+                    help="jobs in the serving trace (0 = skip the serving measurement)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
@@ -178,6 +216,10 @@ def main():
         "context_paper_p100": "Conv Gridder FP32 Npol=4 max 3.62 GRecs/s x 36 = 1.30e11 "
                               "updates/s (S=6 real kernel, no w-term; Tesla P100)",
     }
+
+    if args.serving_jobs > 0:
+        del plan, vis_out
+        result["serving"] = serving_leg(dev, args.serving_jobs)
 
     if not args.no_cpu_baseline:
         import oracle

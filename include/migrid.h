@@ -93,13 +93,13 @@ typedef struct {
     mg_kernel_kind kind;
     mg_dtype tap_dtype;            /* MG_F32, MG_F16 or MG_BF16 */
     int32_t support;               /* separable: S (1..64) */
-    int32_t nplanes;               /* W-projection: number of planes (1..255) */
+    int32_t nplanes;               /* W-projection: number of planes (1..128) */
     const int32_t *plane_support;  /* W-projection: S_p per plane (1..64) */
     const int64_t *plane_offset;   /* W-projection: first complex tap of plane p */
     double inv_dw;                 /* W-projection: 1 / plane spacing in w */
     const void *taps;              /* device: the table(s) */
     int64_t ntaps;                 /* elements in taps (real for separable,
-                                      complex for W-projection) */
+                                      complex for W-projection, at most 2^30) */
 } mg_kernel_desc;
 
 /* Text of the status code. */
@@ -158,6 +158,54 @@ mg_status mg_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
 mg_status mg_degrid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
                     const void *uvw, mg_dtype uvw_dtype, const void *grid, void *vis_out,
                     int64_t *d_nskipped, hipStream_t stream);
+
+/* ---- serving: continuous batching of gridding jobs ----
+ *
+ * A server owns a pool of HIP streams (default priority) on the current
+ * device and a scheduler thread.  mg_server_submit queues a one-shot
+ * gridding job (the same computation as mg_grid) and returns at once.  The
+ * scheduler admits queued jobs in arrival order whenever a slot is free and
+ * the job's HBM footprint fits the budget beside the jobs already running,
+ * and launches each admitted job on the next stream, so the work of jobs
+ * that arrive while others run overlaps on the device.  A job's footprint is
+ * its caller buffers (uvw, vis, grid) plus the library scratch it needs; it
+ * is released when the job completes.  The caller keeps every buffer of a
+ * job alive until the job is done.  Jobs on different streams must not
+ * share an output grid. */
+typedef struct mg_server mg_server;
+
+typedef enum { MG_JOB_QUEUED = 0, MG_JOB_RUNNING = 1, MG_JOB_DONE = 2, MG_JOB_FAILED = 3 } mg_job_state;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, failed;
+    uint64_t bytes_in_use, bytes_peak, budget;
+    int32_t running, queued, max_running;
+} mg_server_stats;
+
+/* hbm_budget_bytes: admission budget; max_slots: jobs running at once
+ * (1..1024); nstreams: streams in the pool (1..64). */
+mg_status mg_server_create(mg_server **srv, size_t hbm_budget_bytes, int32_t max_slots,
+                           int32_t nstreams);
+
+/* Queues a job.  Returns MG_ENOMEM (nothing queued) if the job alone exceeds
+ * the budget, MG_EINVAL for bad arguments (as mg_grid).  *job_id receives the
+ * job's id. */
+mg_status mg_server_submit(mg_server *srv, const mg_grid_desc *g, const mg_kernel_desc *k,
+                           int64_t nrec, const void *uvw, mg_dtype uvw_dtype, const void *vis,
+                           void *grid, uint64_t *job_id);
+
+/* Job state; for a finished job *latency_s is the time from submission to
+ * the scheduler observing completion (may be NULL). */
+mg_status mg_server_poll(mg_server *srv, uint64_t job_id, mg_job_state *state,
+                         double *latency_s);
+
+/* Blocks until the job finishes; returns the job's own status. */
+mg_status mg_server_wait(mg_server *srv, uint64_t job_id, double *latency_s);
+
+mg_status mg_server_get_stats(mg_server *srv, mg_server_stats *out);
+
+/* Waits for every queued and running job, then releases the server. */
+mg_status mg_server_destroy(mg_server *srv);
 
 #ifdef __cplusplus
 }

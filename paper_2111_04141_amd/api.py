@@ -45,6 +45,13 @@ class KernelDesc(C.Structure):
                 ("taps", C.c_void_p), ("ntaps", C.c_int64)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
+                ("failed", C.c_uint64), ("bytes_in_use", C.c_uint64), ("bytes_peak", C.c_uint64),
+                ("budget", C.c_uint64), ("running", C.c_int32), ("queued", C.c_int32),
+                ("max_running", C.c_int32)]
+
+
 _lib = None
 
 
@@ -79,8 +86,16 @@ def lib():
     L.mg_plan_destroy.argtypes = [vp]
     L.mg_grid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
     L.mg_degrid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
+    L.mg_server_create.argtypes = [C.POINTER(vp), C.c_size_t, i32, i32]
+    L.mg_server_submit.argtypes = [vp, gd, kd, i64, vp, i32, vp, vp, C.POINTER(C.c_uint64)]
+    L.mg_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(i32), C.POINTER(C.c_double)]
+    L.mg_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
+    L.mg_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    L.mg_server_destroy.argtypes = [vp]
     for f in ("mg_compute_indices", "mg_plan_create", "mg_plan_grid", "mg_plan_degrid",
-              "mg_plan_nskipped", "mg_plan_bytes", "mg_plan_destroy", "mg_grid", "mg_degrid"):
+              "mg_plan_nskipped", "mg_plan_bytes", "mg_plan_destroy", "mg_grid", "mg_degrid",
+              "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait",
+              "mg_server_get_stats", "mg_server_destroy"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -249,6 +264,72 @@ def degrid(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, grid_in: torch.T
     _check(lib().mg_degrid(C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt, grid_in.data_ptr(),
                            out.data_ptr(), _ptr(nskipped), _stream_ptr(uvw.device)), "mg_degrid")
     return out
+
+
+class Server:
+    """Continuous-batching gridding server (mg_server_*): jobs are admitted in
+    arrival order as slots and HBM budget free up and run on a pool of
+    streams, so jobs that arrive while others run overlap on the device.
+    Every tensor of a job must stay alive until the job is done."""
+
+    JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, nstreams: int = 8):
+        self._h = C.c_void_p()
+        _check(lib().mg_server_create(C.byref(self._h), int(hbm_budget_bytes), int(max_slots),
+                                      int(nstreams)), "mg_server_create")
+        self._keep = {}
+
+    def submit(self, spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, vis: torch.Tensor,
+               grid_out: torch.Tensor) -> int:
+        dt = _check_uvw(uvw)
+        n = uvw.shape[0]
+        _check_vis(vis, n, spec.npol)
+        _check_grid(grid_out, spec)
+        # inputs are produced on torch's current stream; the server's streams
+        # must not start on them before that work is done
+        torch.cuda.current_stream(uvw.device).synchronize()
+        gd, kd = spec.desc(), bank.desc()
+        jid = C.c_uint64()
+        _check(lib().mg_server_submit(self._h, C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt,
+                                      vis.data_ptr(), grid_out.data_ptr(), C.byref(jid)),
+               "mg_server_submit")
+        self._keep[jid.value] = (uvw, vis, grid_out, bank)
+        return jid.value
+
+    def poll(self, job: int):
+        st, lat = C.c_int32(), C.c_double()
+        _check(lib().mg_server_poll(self._h, job, C.byref(st), C.byref(lat)), "mg_server_poll")
+        return st.value, lat.value
+
+    def wait(self, job: int) -> float:
+        lat = C.c_double()
+        _check(lib().mg_server_wait(self._h, job, C.byref(lat)), "mg_server_wait")
+        self._keep.pop(job, None)
+        return lat.value
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().mg_server_get_stats(self._h, C.byref(s)), "mg_server_get_stats")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().mg_server_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Plan:

@@ -336,3 +336,30 @@ def config_wproj_device(device, n_ant: int = 256, n_times: int = 32, n_chan: int
     bank = wproj_bank(nplanes, s_min, s_max, beta, wmax, scale)
     return Workload(name or f"wproj-{n}-P{nplanes}-S{s_min}to{s_max}", n, 4, beta, scale,
                     out, "wproj", s_max, bank=bank)
+
+
+def config_autograd_problem(device, seed: int = SEED_NOISE, n_sources: int = 50,
+                            sigma: float = 0.1):
+    """The differentiable grid/degrid workload: the 10,080,000-record
+    64-antenna array of config_autograd on a 2048^2 grid (7x7, beta 8), a
+    model grid W_true = FFT of a tapered image of `n_sources` point sources,
+    and V_obs = (degridded W_true) + sigma (n_r + j n_i) noise is produced by
+    the caller with the library (this function returns W_true and the noise).
+    Returns (workload, W_true [4, n, n] complex64, noise [nrec, 4] complex64)
+    as torch tensors on `device`."""
+    import torch
+    wl = config_autograd()
+    n = wl.n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    img = np.zeros((n, n), np.complex128)
+    xs = rng.integers(n // 4, 3 * n // 4, (n_sources, 2))
+    flux = rng.uniform(0.5, 2.0, n_sources)
+    for (x, y), f in zip(xs, flux):
+        img[y, x] += f
+    # taper the image so the model grid is smooth (Gaussian image-plane taper)
+    yy, xx = np.mgrid[0:n, 0:n]
+    img *= np.exp(-(((xx - n / 2) / (0.3 * n)) ** 2 + ((yy - n / 2) / (0.3 * n)) ** 2))
+    W1 = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(img)))
+    W = np.stack([W1, 0.5 * W1, 0.25 * W1, W1]).astype(np.complex64)
+    noise = vis_normal_torch(wl.nrec, 4, seed + 1, device) * sigma
+    return wl, torch.from_numpy(W).to(device), noise

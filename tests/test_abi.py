@@ -96,3 +96,15 @@ def test_python_binding_rejects_host_tensors():
         api.KernelBank("separable", torch.zeros(57), support=7)
     with pytest.raises(ValueError):
         api._check_uvw(torch.zeros(4, 3))
+
+
+def test_server_argument_checks_on_host(L):
+    h = C.c_void_p()
+    assert L.mg_server_create(None, 1 << 30, 4, 2) == api.MG_EINVAL
+    assert L.mg_server_create(C.byref(h), 0, 4, 2) == api.MG_EINVAL
+    assert L.mg_server_create(C.byref(h), 1 << 30, 0, 2) == api.MG_EINVAL
+    assert L.mg_server_create(C.byref(h), 1 << 30, 4, 0) == api.MG_EINVAL
+    assert L.mg_server_create(C.byref(h), 1 << 30, 4, 65) == api.MG_EINVAL
+    assert not h.value
+    assert L.mg_server_submit(None, None, None, 0, None, 0, None, None, None) == api.MG_EINVAL
+    assert L.mg_server_destroy(None) == api.MG_OK
