@@ -31,6 +31,24 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X published (packed FP32)
 FP32_UNPACKED_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes of one plan.grid call (gather + gridding kernels) on the default
+# workload: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, summed over the
+# call's dispatches and scaled by the reading of a plain device copy of known
+# size.  Valid only for the kernel sources with this digest; any change to
+# them makes the figure stale and it is then reported as null.
+MEASURED_TRAFFIC = {"sources": "ba9c3d8b8318f6dd", "bytes_per_call": 55832416476,
+                    "profile": "profiles/grid_wproj8192_134M_hbm_traffic.txt"}
+TRAFFIC_SOURCES = ("grid.hip", "plan.hip", "api.hip", "common.h", "internal.h")
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2111_04141_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -80,6 +98,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--channels", type=int, default=128,
                     help="channels of the W-projection workload (128 = full size)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--serving-jobs", type=int, default=40,
                     help="jobs in the serving trace (0 = skip the serving measurement)")
     args = ap.parse_args()
@@ -98,6 +118,16 @@ def main():
     props = torch.cuda.get_device_properties(dev)
     log(f"[bench] device {props.name}, {props.multi_processor_count} CUs, "
         f"{props.total_memory / 2**30:.0f} GiB")
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 device copies of {nb} bytes")
+        del src, dst
     t0 = time.time()
     wl = W.config_wproj_device(dev, n_chan=args.channels,
                                name=("wproj-8192-P32-S8to64-134M" if args.channels == 128
@@ -177,6 +207,10 @@ def main():
         f"plan degrid {degrid_ms:.3f} ms")
 
     flops = 32.0 * updates            # 4 polarisations x complex multiply-add
+    traffic = None
+    if (MEASURED_TRAFFIC is not None and args.channels == 128
+            and MEASURED_TRAFFIC["sources"] == sources_digest()):
+        traffic = MEASURED_TRAFFIC["bytes_per_call"]
     achieved_tflops = flops / (grid_ms * 1e-3) / 1e12
 
     result = {
@@ -208,7 +242,7 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "grid_window_kernel (all support classes) + gather, per plan.grid call",
             "flops_per_launch": flops,
             "frac_of_unpacked_fp32": achieved_tflops / FP32_UNPACKED_TFLOPS,

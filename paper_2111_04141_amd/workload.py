@@ -306,6 +306,37 @@ def subsample(nrec: int, k: int, seed: int = SEED_SUBSAMPLE) -> np.ndarray:
     return np.sort(rng.choice(nrec, size=min(k, nrec), replace=False))
 
 
+def config_precision_sample(k: int = 1_000_000, seed: int = SEED_SUBSAMPLE,
+                            n: int = 16384, nplanes: int = 32, s_min: int = 8,
+                            s_max: int = 64, beta: int = 4) -> Workload:
+    """A k-record random subsample of the 1,004,666,880-record precision
+    workload: 512 antennas log-radial 20 m .. 5 km (130816 baselines) x 16
+    times x 480 channels in 1.2-1.6 GHz, 16384^2 grid, W-projection with
+    32 planes, S 8 -> 64, oversampling 4.  Only the sampled records are
+    synthesised: record i of the [time][baseline][channel] order takes the
+    same float64 product as uvw_wavelengths, so the values equal those rows
+    of the full array.  The uv scale and the plane spacing come from the
+    full array's extremes (the largest |u|, |v|, |w| sit at the highest
+    frequency).  uvw is float32."""
+    ant = antennas_log_radial(512, 20.0, 5000.0, SEED_ANTENNAS)
+    bl = baselines_enu(ant)
+    uvw_m = baseline_uvw_m(bl, math.radians(-30.0), math.radians(-30.0), hour_angles(16))
+    freqs = np.linspace(1.2e9, 1.6e9, 480, endpoint=False)
+    f = freqs / C_LIGHT
+    T, B, _ = uvw_m.shape
+    C = f.shape[0]
+    idx = subsample(T * B * C, k, seed)
+    t, b, c = idx // (B * C), (idx // C) % B, idx % C
+    uvw = uvw_m[t, b] * f[c][:, None]
+    umax = float(np.max(np.abs(uvw_m[..., :2]))) * f[-1]
+    wmax = float(np.max(np.abs(uvw_m[..., 2]))) * f[-1]
+    scale = 0.5 * (n / 2 - s_max) / umax
+    bank = wproj_bank(nplanes, s_min, s_max, beta, wmax, scale)
+    return Workload(f"precision-{n}-P{nplanes}-S{s_min}to{s_max}-{k}-of-1.0G", n, 4, beta,
+                    scale, np.ascontiguousarray(uvw.astype(np.float32)), "wproj", s_max,
+                    bank=bank)
+
+
 def config_wproj_device(device, n_ant: int = 256, n_times: int = 32, n_chan: int = 128,
                         n: int = 8192, nplanes: int = 32, s_min: int = 8, s_max: int = 64,
                         beta: int = 4, r_max_m: float = 2500.0, seed: int = SEED_ANTENNAS,
