@@ -32,6 +32,10 @@
 // of the bank for w < 0), so the per-record scalar work is small.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include <type_traits>
+
 #include "internal.h"
 
 namespace mg {
@@ -77,6 +81,17 @@ __device__ inline void fma_real(float (&acc)[8], const float w, const RecVis &f)
     }
 }
 
+// Chunks are handed out through a per-launch counter (one vector atomic per
+// chunk and workgroup), so workgroups that draw small chunks take more of
+// them; chunk sizes vary from one record to R.  Each workgroup sees its
+// chunks in increasing order.
+__device__ inline uint32_t next_chunk(uint32_t *queue, uint32_t *slot) {
+    __syncthreads();   // the previous value has been read by every wave
+    if (threadIdx.x == 0) *slot = atomicAdd(queue, 1u);
+    __syncthreads();
+    return uniform_u32(*slot);
+}
+
 // ---------------------------------------------------------------------------
 // moving-window gridder
 // ---------------------------------------------------------------------------
@@ -88,7 +103,10 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
     const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
     const uint32_t *__restrict__ plane_cfirst, const PlaneLayout *__restrict__ planes,
-    GridParams prm) {
+    const uint32_t *__restrict__ nonfinite, uint32_t *__restrict__ queue, GridParams prm) {
+    // fixed point cannot hold NaN or Inf: calls whose visibilities are not
+    // all finite commit straight to the grid in FP32
+    const bool use_lds = LDS && uniform_u32(*nonfinite) == 0u;
     extern __shared__ int32_t region[];   // [8][RH][RW]: (pol, re/im) planes
     __shared__ float s_bound[kWavesPerGroup];
     constexpr int NSPLIT = kWavesPerGroup / NG;
@@ -102,7 +120,9 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
     const uint32_t c_begin = plane_cfirst[prm.p_lo];
     const uint32_t c_end = plane_cfirst[prm.p_hi];
 
-    for (uint32_t c = c_begin + blockIdx.x; c < c_end; c += gridDim.x) {
+    __shared__ uint32_t s_next;
+    for (uint32_t c = c_begin + next_chunk(queue, &s_next); c < c_end;
+         c = c_begin + next_chunk(queue, &s_next)) {
         const Chunk ch = chunks[c];
         int p = prm.p_lo;
         while (p + 1 < prm.p_hi && (int64_t)ch.bucket >= planes[p + 1].base) ++p;
@@ -122,7 +142,7 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
 
         // fixed-point scale of this chunk: 2^scale * bound <= 2^30
         int scale = 0;
-        if constexpr (LDS) {
+        if (use_lds) {
             for (int i = threadIdx.x; i < 8 * plane_cells; i += kGroupThreads) region[i] = 0;
             float part = 0.0f;
             for (uint32_t r = rb0 + threadIdx.x; r < re0; r += kGroupThreads) {
@@ -166,7 +186,7 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
         // adds a slot's sums to its cell
         auto commit = [&](float (&sums)[8], uint32_t cell_uv) {
             const uint32_t cu_ = cell_uv & 0xffffu, cv_ = cell_uv >> 16;
-            if constexpr (LDS) {
+            if (use_lds) {
                 int32_t *dst = &region[(int)(cv_ - cv0) * RW + (int)(cu_ - cu0)];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
@@ -323,7 +343,7 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
                 if (k < kdyn && ((valid_bits >> k) & 1u) && cell[k] != kNoCell) commit(acc[k], cell[k]);
         }
 
-        if constexpr (LDS) {
+        if (use_lds) {
             __syncthreads();
             const int n = npol * plane_cells;
             for (int i = threadIdx.x; i < n; i += kGroupThreads) {
@@ -344,12 +364,216 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// blocked output-stationary gridder (large supports)
+// ---------------------------------------------------------------------------
+// The grid region a chunk can touch (its tile plus an S - 1 halo) is cut
+// into 8 x 8-cell blocks, one cell per lane; block b belongs to wave
+// b mod NW of the workgroup (its k-th block is b = k NW + wave), and its 8
+// accumulators per lane stay in registers for the whole chunk.  Every wave
+// walks all records of the chunk (scalar loads).  Per record, lane k of a
+// wave tests block k against the record's footprint, so one vector compare
+// and a ballot give the wave's overlapped blocks (and those lying wholly
+// inside the footprint, which need no per-lane mask); each overlapped block
+// then takes one tap load and 16 multiply-adds per lane.  Nothing is
+// committed until the chunk ends; then each touched cell is added to the
+// grid with float atomics.  Where records are sparse, as in the high-|w|
+// planes of large support, this replaces the moving window's per-record
+// slot commits; the lane utilisation is S^2 over the overlapped blocks'
+// cells, about (S/(S+7))^2.
+template <int KMAX, int NW, bool SEP, typename TapT>
+__global__ __launch_bounds__(NW * kWave) void grid_block_kernel(
+    const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
+    const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
+    const uint32_t *__restrict__ plane_cfirst, const PlaneLayout *__restrict__ planes,
+    const uint32_t *__restrict__ nonfinite, uint32_t *__restrict__ queue, GridParams prm) {
+    // Lanes outside a footprint normally multiply a zero tap, which adds
+    // nothing; a non-finite visibility would turn that into NaN, so calls
+    // whose visibilities are not all finite take the masked path instead.
+    const bool exact = uniform_u32(*nonfinite) != 0u;
+    constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);   // bytes per tap
+    const int wave = (int)uniform_u32(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int lu = lane & 7, lv = lane >> 3;
+    const int npol = prm.npol;
+    const int beta = prm.beta;
+    const uint32_t c_begin = plane_cfirst[prm.p_lo];
+    const uint32_t c_end = plane_cfirst[prm.p_hi];
+    const char *tbase = reinterpret_cast<const char *>(taps);
+
+    int p = prm.p_lo;   // chunks come in increasing order: the plane only moves forward
+    __shared__ uint32_t s_next;
+    for (uint32_t c = c_begin + next_chunk(queue, &s_next); c < c_end;
+         c = c_begin + next_chunk(queue, &s_next)) {
+        const Chunk ch = chunks[c];
+        while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
+        const PlaneLayout pl = planes[p];
+        const int S = pl.S;
+        const uint32_t local = ch.bucket - (uint32_t)pl.base;
+        const int Tm = pl.T - 1;
+        const int cu0 = (int)((local % (uint32_t)pl.ntu) << pl.log2T);   // region = tile + halo
+        const int cv0 = (int)((local / (uint32_t)pl.ntu) << pl.log2T);
+        const int nbx = (pl.T + S - 1 + 7) >> 3;
+        const int nblocks = nbx * nbx;
+        const uint32_t rowlen = (uint32_t)pl.rowlen;
+
+        // lane k < KMAX: origin of the wave's block k, for the overlap tests
+        uint32_t blo_u = 0xffff0000u, blo_v = 0xffff0000u;   // never overlaps
+        {
+            const int b = lane * NW + wave;
+            if (lane < KMAX && b < nblocks) {
+                blo_u = (uint32_t)((b % nbx) << 3);
+                blo_v = (uint32_t)((b / nbx) << 3);
+            }
+        }
+        // per block: this lane's cell (packed u | v << 16, region-relative)
+        // and its tap offset in bytes relative to the footprint's first tap
+        uint32_t cuv[KMAX], voff[KMAX], voffv[KMAX];
+        float acc[KMAX][8];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int b = k * NW + wave;
+            const uint32_t cu = (uint32_t)(((b % nbx) << 3) + lu);
+            const uint32_t cv = (uint32_t)(((b / nbx) << 3) + lv);
+            cuv[k] = cu | (cv << 16);
+            if constexpr (SEP) {
+                voff[k] = cu * (uint32_t)beta * kElem;
+                voffv[k] = cv * (uint32_t)beta * kElem;
+            } else {
+                voff[k] = (cv * rowlen + cu) * (uint32_t)beta * kElem;
+                voffv[k] = 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
+        }
+        uint32_t touched = 0;
+
+        auto visit = [&](const RecMeta m, const RecVis &f, auto exact_t) {
+            constexpr bool EXACT = decltype(exact_t)::value;
+            // footprint origin relative to the region
+            const uint32_t a = meta_ku(m) & (uint32_t)Tm;
+            const uint32_t bq = meta_kv(m) & (uint32_t)Tm;
+            // block [lo, lo+7] overlaps [a, a+S-1] iff lo + 7 - a in [0, S+6];
+            // it lies inside iff lo - a in [0, S-8]
+            const uint32_t hit = (uint32_t)__ballot((blo_u + 7u - a <= (uint32_t)(S + 6)) &&
+                                                    (blo_v + 7u - bq <= (uint32_t)(S + 6)));
+            const uint32_t full = (uint32_t)__ballot((blo_u - a <= (uint32_t)(S - 8)) &&
+                                                     (blo_v - bq <= (uint32_t)(S - 8)));
+            touched |= hit;
+            const uint32_t ab = a | (bq << 16);
+            const char *tb;
+            const char *tbv = nullptr;
+            if constexpr (SEP) {
+                tb = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a * beta) * (int64_t)kElem;
+                tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq * beta) * (int64_t)kElem;
+            } else {
+                tb = tbase + ((int64_t)m.toff - (int64_t)(bq * rowlen + a) * beta) * (int64_t)kElem;
+            }
+            // tap of lane's cell in block k (uniform base + 32-bit lane offset)
+            auto tap = [&](const int k) {
+                uint32_t o = voff[k];
+                asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+                if constexpr (SEP) {
+                    uint32_t ov = voffv[k];
+                    asm volatile("" : "+v"(ov));
+                    const float t = TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
+                                    TapTraits<TapT>::real((const TapT *)(tbv + ov), 0);
+                    return make_float2(t, 0.0f);
+                } else {
+                    return TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
+                }
+            };
+            auto madd = [&](const int k, const float2 w) {
+                if constexpr (SEP)
+                    fma_real(acc[k], w.x, f);
+                else
+                    fma_complex(acc[k], w, f);
+            };
+            if constexpr (EXACT) {
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    if (!((hit >> k) & 1u)) continue;
+                    const uint32_t d = cuv[k] - ab;   // a borrow only where du < 0
+                    if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S) madd(k, tap(k));
+                }
+            } else {
+                // all tap loads of the record first, then the multiply-adds;
+                // lanes outside the footprint keep a zero tap
+                float2 w[KMAX];
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    w[k] = make_float2(0.0f, 0.0f);
+                    if (!((hit >> k) & 1u)) continue;
+                    const uint32_t d = cuv[k] - ab;
+                    if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S) w[k] = tap(k);
+                }
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if ((hit >> k) & 1u) madd(k, w[k]);
+            }
+        };
+
+        auto records = [&](auto exact_t) {
+            const uint32_t rb = ch.start, re = ch.start + ch.len;
+            RecMeta nm[kBatch];
+            float4 na4[kBatch], nb4[kBatch];
+            // the record arrays are padded by kBatch entries, so a batch may
+            // run past the chunk's end (those records are not used)
+            auto load_batch = [&](uint32_t r0) {
+#pragma unroll
+                for (int i = 0; i < kBatch; ++i) {
+                    nm[i] = smeta[r0 + i];
+                    na4[i] = svis[2 * (size_t)(r0 + i)];
+                    nb4[i] = svis[2 * (size_t)(r0 + i) + 1];
+                }
+            };
+            load_batch(rb);
+            for (uint32_t r = rb; r < re; r += kBatch) {
+                RecMeta mm[kBatch];
+                float4 va4[kBatch], vb4[kBatch];
+#pragma unroll
+                for (int i = 0; i < kBatch; ++i) {
+                    mm[i] = nm[i];
+                    va4[i] = na4[i];
+                    vb4[i] = nb4[i];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                load_batch(r + kBatch);
+#pragma unroll
+                for (int i = 0; i < kBatch; ++i)
+                    if (r + (uint32_t)i < re) visit(mm[i], unpack_vis(va4[i], vb4[i]), exact_t);
+            }
+        };
+        if (exact)
+            records(std::true_type{});
+        else
+            records(std::false_type{});
+
+        // commit: one float atomic per touched cell, polarisation and part
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (!((touched >> k) & 1u)) continue;
+            const int u = cu0 + (int)(cuv[k] & 0xffffu), v = cv0 + (int)(cuv[k] >> 16);
+            if (u >= prm.nu || v >= prm.nv) continue;
+#pragma unroll
+            for (int pol = 0; pol < 4; ++pol) {
+                if (pol < npol && (acc[k][2 * pol] != 0.0f || acc[k][2 * pol + 1] != 0.0f)) {
+                    float *dst = grid + 2 * (((int64_t)pol * prm.nv + v) * prm.nu + u);
+                    unsafeAtomicAdd(dst, acc[k][2 * pol]);
+                    unsafeAtomicAdd(dst + 1, acc[k][2 * pol + 1]);
+                }
+            }
+        }
+    }
+}
+
 // Gathers visibilities into sorted order, padded to 4 polarisations.
 __global__ __launch_bounds__(256) void gather_vis_kernel(const int64_t *__restrict__ counters,
                                                          int64_t nrec,
                                                          const uint32_t *__restrict__ sperm,
                                                          const float2 *__restrict__ vis,
-                                                         int32_t npol, float4 *__restrict__ svis) {
+                                                         int32_t npol, float4 *__restrict__ svis,
+                                                         uint32_t *__restrict__ nonfinite) {
     const int64_t nvalid = counters[1];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvalid && i < nrec;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -357,9 +581,17 @@ __global__ __launch_bounds__(256) void gather_vis_kernel(const int64_t *__restri
         float2 x[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) x[q] = (q < npol) ? v[q] : make_float2(0.0f, 0.0f);
+        bool finite = true;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) finite = finite && isfinite(x[q].x) && isfinite(x[q].y);
+        if (!finite) atomicOr(nonfinite, 1u);
         svis[2 * i] = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
         svis[2 * i + 1] = make_float4(x[2].x, x[2].y, x[3].x, x[3].y);
     }
+}
+
+__global__ void clear_words_kernel(uint32_t *w, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0u;
 }
 
 struct GridPtrs {
@@ -370,38 +602,73 @@ struct GridPtrs {
     const Chunk *chunks;
     const uint32_t *plane_cfirst;
     const PlaneLayout *planes;
+    const uint32_t *nonfinite;   // set by the gather if a visibility is not finite
+    uint32_t *queue;             // this launch's chunk counter
 };
 
+// Workgroups of `kernel` that fit on the device at once.
+template <typename Kern>
+int resident_groups(Kern kernel, int threads, size_t lds) {
+    int dev = 0, cus = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess)
+        per = 1;
+    return std::max(1, per) * std::max(1, cus);
+}
+
 template <int KMAX, int NG, bool SEP, typename TapT, bool LDS>
-void launch_one(const GridPtrs &a, const GridParams &prm, size_t lds, hipStream_t stream,
-                int blocks) {
-    hipLaunchKernelGGL((grid_window_kernel<KMAX, NG, SEP, TapT, LDS>), dim3(blocks),
+void launch_one(const GridPtrs &a, const GridParams &prm, size_t lds, hipStream_t stream) {
+    auto kern = grid_window_kernel<KMAX, NG, SEP, TapT, LDS>;
+    hipLaunchKernelGGL(kern, dim3(resident_groups(kern, kGroupThreads, lds)),
                        dim3(kGroupThreads), lds, stream, a.smeta, a.svis, a.grid,
-                       (const TapT *)a.taps, a.chunks, a.plane_cfirst, a.planes, prm);
+                       (const TapT *)a.taps, a.chunks, a.plane_cfirst, a.planes, a.nonfinite,
+                       a.queue, prm);
+}
+
+template <int KMAX, int NW, bool SEP, typename TapT>
+void launch_block(const GridPtrs &a, const GridParams &prm, hipStream_t stream) {
+    auto kern = grid_block_kernel<KMAX, NW, SEP, TapT>;
+    hipLaunchKernelGGL(kern, dim3(resident_groups(kern, NW * kWave, 0)), dim3(NW * kWave), 0,
+                       stream, a.smeta, a.svis, a.grid, (const TapT *)a.taps, a.chunks,
+                       a.plane_cfirst, a.planes, a.nonfinite, a.queue, prm);
+}
+
+// Largest region, in 8 x 8 blocks, of a chunk of tile side T and support S.
+inline int region_blocks(int T, int S) {
+    const int side = (T + S - 1 + 7) / 8;
+    return side * side;
 }
 
 template <bool SEP, typename TapT>
 hipError_t launch_class(int cls, const GridPtrs &a, const GridParams &prm, int smax, int tile,
-                        hipStream_t stream, int blocks) {
-    const size_t lds = (cls <= 2) ? sizeof(int32_t) * 8 * (size_t)(tile + smax - 1) *
+                        hipStream_t stream) {
+    const size_t lds = (cls <= 1) ? sizeof(int32_t) * 8 * (size_t)(tile + smax - 1) *
                                         (size_t)(tile + smax - 1)
                                   : 0;
     switch (cls) {
-    case 0: launch_one<1, 1, SEP, TapT, true>(a, prm, lds, stream, blocks); break;
-    case 1: launch_one<4, 1, SEP, TapT, true>(a, prm, lds, stream, blocks); break;
-    case 2: launch_one<8, 2, SEP, TapT, true>(a, prm, lds, stream, blocks); break;
-    default: launch_one<16, 4, SEP, TapT, false>(a, prm, 0, stream, blocks); break;
+    case 0: launch_one<1, 1, SEP, TapT, true>(a, prm, lds, stream); break;
+    case 1: launch_one<4, 1, SEP, TapT, true>(a, prm, lds, stream); break;
+    case 2:
+        // every block of the largest region has an owner
+        if (region_blocks(tile, smax) > 9 * 4) return hipErrorInvalidValue;
+        launch_block<9, 4, SEP, TapT>(a, prm, stream);
+        break;
+    default:
+        if (region_blocks(tile, smax) > 7 * 16) return hipErrorInvalidValue;
+        launch_block<7, 16, SEP, TapT>(a, prm, stream);
+        break;
     }
     return hipGetLastError();
 }
 
 template <bool SEP>
 hipError_t launch_class_t(mg_dtype dt, int cls, const GridPtrs &a, const GridParams &prm,
-                          int smax, int tile, hipStream_t stream, int blocks) {
+                          int smax, int tile, hipStream_t stream) {
     switch (dt) {
-    case MG_F16: return launch_class<SEP, __half>(cls, a, prm, smax, tile, stream, blocks);
-    case MG_BF16: return launch_class<SEP, __hip_bfloat16>(cls, a, prm, smax, tile, stream, blocks);
-    default: return launch_class<SEP, float>(cls, a, prm, smax, tile, stream, blocks);
+    case MG_F16: return launch_class<SEP, __half>(cls, a, prm, smax, tile, stream);
+    case MG_BF16: return launch_class<SEP, __hip_bfloat16>(cls, a, prm, smax, tile, stream);
+    default: return launch_class<SEP, float>(cls, a, prm, smax, tile, stream);
     }
 }
 
@@ -410,16 +677,24 @@ hipError_t launch_class_t(mg_dtype dt, int cls, const GridPtrs &a, const GridPar
 mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream_t stream) {
     if (P.nrec == 0) return MG_OK;
     float4 *svis = nullptr;
-    hipError_t e = hipMallocAsync((void **)&svis, 2 * sizeof(float4) * (size_t)(P.nrec + kBatch),
-                                  stream);
+    // sorted visibilities (padded by kBatch records), then the non-finite
+    // flag and one chunk counter per launch (at most one per plane)
+    const size_t nsv = 2 * (size_t)(P.nrec + kBatch);
+    const int nwords = 1 + P.nplanes_eff;
+    hipError_t e = hipMallocAsync((void **)&svis,
+                                  sizeof(float4) * nsv + sizeof(uint32_t) * (size_t)nwords, stream);
     if (e != hipSuccess) return set_error(MG_ENOMEM, "grid: gather buffer allocation failed");
+    uint32_t *nonfinite = reinterpret_cast<uint32_t *>(svis + nsv);
     {
+        hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(256), 0, stream, nonfinite, nwords);
         int64_t nb = (P.nrec + 255) / 256;
         if (nb > 16384) nb = 16384;
         hipLaunchKernelGGL(gather_vis_kernel, dim3((unsigned)nb), dim3(256), 0, stream,
-                           P.counters, P.nrec, P.sperm, (const float2 *)vis, P.geom.npol, svis);
+                           P.counters, P.nrec, P.sperm, (const float2 *)vis, P.geom.npol, svis,
+                           nonfinite);
     }
-    GridPtrs a{P.smeta, svis, (float *)grid, P.taps, P.chunks, P.plane_cfirst, P.d_planes};
+    GridPtrs a{P.smeta, svis, (float *)grid, P.taps, P.chunks, P.plane_cfirst, P.d_planes,
+               nonfinite, nullptr};
     GridParams prm{P.geom.npol, P.geom.nu, P.geom.nv, P.geom.beta, 0, 0};
     const bool sep = P.kind == MG_KERNEL_SEPARABLE;
     // one launch per run of consecutive planes of the same class
@@ -435,11 +710,9 @@ mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream
         prm.p_lo = p0;
         prm.p_hi = p1;
         const int cls = P.planes[p0].cls;
-        const int blocks = 2048;
-        e = sep ? launch_class_t<true>(P.tap_dtype, cls, a, prm, smax, P.planes[p0].T, stream,
-                                       blocks)
-                : launch_class_t<false>(P.tap_dtype, cls, a, prm, smax, P.planes[p0].T, stream,
-                                        blocks);
+        a.queue = nonfinite + 1 + p0;
+        e = sep ? launch_class_t<true>(P.tap_dtype, cls, a, prm, smax, P.planes[p0].T, stream)
+                : launch_class_t<false>(P.tap_dtype, cls, a, prm, smax, P.planes[p0].T, stream);
         p0 = p1;
     }
     hipFreeAsync(svis, stream);

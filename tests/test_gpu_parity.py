@@ -117,6 +117,34 @@ def test_grid_wproj_all_classes(torch_cuda, api, small_wproj):
     assert H.rel_l2(G, G_ref) < TOL
 
 
+def test_nonfinite_visibilities_follow_the_definition(torch_cuda, api, small_wproj):
+    """A NaN or Inf visibility makes exactly the cells of its footprint
+    non-finite, as in the definition (the gridders switch to FP32 commits for
+    such calls); every other cell keeps its value.  One non-finite record per
+    support class."""
+    wl = small_wproj
+    ix = oracle.index(H.oracle_geom(wl), wl.uvw)
+    S = np.where(ix["valid"] == 1, wl.bank.supports[np.maximum(ix["plane"], 0)], 0)
+    vis = W.vis_normal(wl.nrec, 4, seed=11).astype(np.complex128)
+    picks = []
+    for lo, hi in ((1, 8), (9, 16), (17, 32), (33, 64)):
+        cand = np.nonzero((S >= lo) & (S <= hi))[0]
+        picks.append(int(cand[len(cand) // 2]))
+    vis[picks[0], 0] = np.nan
+    vis[picks[1], 2] = complex(np.inf, 0.0)
+    vis[picks[2], 1] = complex(0.0, np.nan)
+    vis[picks[3], 3] = complex(-np.inf, 0.0)
+    G, G_ref = _grid_both(torch_cuda, api, wl, vis)
+    assert np.isnan(G_ref).any() and np.isinf(G_ref.real).any()
+    for part in ("real", "imag"):
+        g, r = getattr(G, part), getattr(G_ref, part)
+        assert np.array_equal(np.isnan(g), np.isnan(r)), part
+        assert np.array_equal(np.isposinf(g), np.isposinf(r)), part
+        assert np.array_equal(np.isneginf(g), np.isneginf(r)), part
+    fin = np.isfinite(G_ref)
+    assert H.rel_l2(G[fin], G_ref[fin]) < TOL
+
+
 @pytest.mark.parametrize("which", ["sep", "wproj"])
 def test_degrid(torch_cuda, api, small_sep, small_wproj, which):
     torch = torch_cuda
