@@ -1,14 +1,22 @@
-// Degridding (gather) kernels: vis_out[r] = sum_{i,j} conj(w_ij) G[k_lo + (i, j)],
-// the adjoint of the gridding map.
+// Degridding (gather): vis_out[r] = sum_{i,j} conj(w_ij) G[k_lo + (i, j)], the
+// adjoint of the gridding map.
 //
-// Work unit: one chunk of cell-sorted records of one (plane, tile) bucket.
-// The workgroup first copies the chunk's grid region (tile plus S-1 halo, all
-// polarisations, interleaved per cell) from HBM into LDS with coalesced
-// loads; then every lane takes whole records and sums their S x S footprint
-// from LDS, so no cross-lane reduction and no atomics are needed.  For
-// supports above 32 the region does not fit in LDS and lanes read the grid
-// through the caches instead.
+// Work unit: one chunk of records of one (plane, tile) bucket, the same
+// chunks the gridder uses.  The grid region the chunk can touch (its tile
+// plus an S - 1 halo) is cut into 8 x 8-cell blocks, one cell per lane;
+// block b belongs to wave b mod NW and its 4 polarisations stay in
+// registers for the whole chunk, so the grid is read once per chunk with
+// coalesced loads.  Every wave walks all records of the chunk (scalar
+// loads).  Per record, a vector compare and a ballot give the wave's blocks
+// that the footprint overlaps; each takes one tap load and 16 multiply-adds
+// per lane into the record's partial sums.  Partial sums of B records are
+// then reduced across the wave's lanes (a butterfly that halves the values
+// each lane holds at every step) and across the waves through LDS, and one
+// thread per (record, component) writes the result.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -16,162 +24,470 @@ namespace mg {
 
 namespace {
 
-struct DegridArgs {
-    const RecMeta *smeta;
-    const uint32_t *sperm;
-    const float *grid;        // [npol][nv][nu] complex64
-    float2 *vis_out;          // [nrec][npol]
-    const void *taps;
-    const Chunk *chunks;
-    const uint32_t *plane_cfirst;
-    const PlaneLayout *planes;
+struct DegridParams {
     int32_t npol, nu, nv, beta;
     int32_t p_lo, p_hi;
 };
 
-template <bool SEP, typename TapT, bool LDS>
-__global__ __launch_bounds__(kGroupThreads) void degrid_kernel(DegridArgs a, DevGeom g) {
-    extern __shared__ float2 region[];   // [row][col][pol]
-    const TapT *taps = (const TapT *)a.taps;
-    const int npol = a.npol;
-    const uint32_t c_begin = a.plane_cfirst[a.p_lo];
-    const uint32_t c_end = a.plane_cfirst[a.p_hi];
-    for (uint32_t c = c_begin + blockIdx.x; c < c_end; c += gridDim.x) {
-        const Chunk ch = a.chunks[c];
-        int p = a.p_lo;
-        while (p + 1 < a.p_hi && (int64_t)ch.bucket >= a.planes[p + 1].base) ++p;
-        const PlaneLayout pl = a.planes[p];
+// Next chunk of this launch (one vector atomic per chunk and workgroup).
+__device__ inline uint32_t next_chunk_dg(uint32_t *queue, uint32_t *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(queue, 1u);
+    __syncthreads();
+    return uniform_u32(*slot);
+}
+
+// In-place butterfly over the lanes of a wave: on entry every lane holds N
+// partial values; on exit lane l holds in v[0] the wave-wide sum of value
+// index idx(l), where idx takes the lane bits 5, 4, ... (one per halving step)
+// as its binary digits from the most significant down; lanes that differ
+// only in the remaining low bits hold the same sum.
+template <int N, int H>
+__device__ inline void reduce_halve(float (&v)[N], int lane) {
+    // offset of this step: 32 for the first halving, then 16, 8, ...
+    constexpr int kO = 32 >> (__builtin_ctz(N) - __builtin_ctz(2 * H));
+    const bool up = (lane & kO) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const float send = up ? v[i] : v[i + H];
+        const float keep = up ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, kO);
+    }
+    if constexpr (H > 1 && kO > 1) reduce_halve<N, H / 2>(v, lane);
+}
+
+template <int N>
+__device__ inline void wave_reduce_scatter(float (&v)[N], int lane) {
+    static_assert(N >= 2 && N <= 64 && (N & (N - 1)) == 0, "N: power of two in [2, 64]");
+    reduce_halve<N, N / 2>(v, lane);
+    // the lanes still sharing a value index: add across the remaining bits
+    constexpr int kSteps = __builtin_ctz(N);
+#pragma unroll
+    for (int s = kSteps; s < 6; ++s) v[0] += __shfl_xor(v[0], 32 >> s);
+}
+
+template <int N>
+__device__ inline int reduce_index(int lane) {
+    constexpr int kSteps = __builtin_ctz(N);
+    int idx = 0;
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) idx = 2 * idx + ((lane >> (5 - s)) & 1);
+    return idx;
+}
+
+template <int KMAX, int NW, int B, bool SEP, typename TapT>
+__global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
+    const RecMeta *__restrict__ smeta, const uint32_t *__restrict__ sperm,
+    const float *__restrict__ grid, float *__restrict__ vis_out, const TapT *__restrict__ taps,
+    const Chunk *__restrict__ chunks, const uint32_t *__restrict__ plane_cfirst,
+    const PlaneLayout *__restrict__ planes, uint32_t *__restrict__ queue, DegridParams prm) {
+    constexpr int NV = B * 8;   // partial values per lane: B records x 4 pol x (re, im)
+    constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);
+    __shared__ float s_part[2][NW][NV];
+    __shared__ uint32_t s_next;
+    const int wave = (int)uniform_u32(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int lu = lane & 7, lv = lane >> 3;
+    const int npol = prm.npol;
+    const int beta = prm.beta;
+    const uint32_t c_begin = plane_cfirst[prm.p_lo];
+    const uint32_t c_end = plane_cfirst[prm.p_hi];
+    const char *tbase = reinterpret_cast<const char *>(taps);
+    const int my_idx = reduce_index<NV>(lane);
+    const bool writer = (lane & ((64 / NV > 0 ? 64 / NV : 1) - 1)) == 0;
+    int p = prm.p_lo;
+    int parity = 0;
+
+    for (uint32_t c = c_begin + next_chunk_dg(queue, &s_next); c < c_end;
+         c = c_begin + next_chunk_dg(queue, &s_next)) {
+        const Chunk ch = chunks[c];
+        while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
+        const PlaneLayout pl = planes[p];
         const int S = pl.S;
         const uint32_t local = ch.bucket - (uint32_t)pl.base;
-        const uint32_t tu0 = (local % (uint32_t)pl.ntu) << pl.log2T;
-        const uint32_t tv0 = (local / (uint32_t)pl.ntu) << pl.log2T;
-        const uint32_t cu0 = tu0 + (ch.bbox & 0xffu);
-        const uint32_t cv0 = tv0 + ((ch.bbox >> 16) & 0xffu);
+        const int Tm = pl.T - 1;
+        const int cu0 = (int)((local % (uint32_t)pl.ntu) << pl.log2T);
+        const int cv0 = (int)((local / (uint32_t)pl.ntu) << pl.log2T);
+        const int nbx = (pl.T + S - 1 + 7) >> 3;
+        const int nblocks = nbx * nbx;
+        const uint32_t rowlen = (uint32_t)pl.rowlen;
+
+        uint32_t blo_u = 0xffff0000u, blo_v = 0xffff0000u;
+        {
+            const int b = lane * NW + wave;
+            if (lane < KMAX && b < nblocks) {
+                blo_u = (uint32_t)((b % nbx) << 3);
+                blo_v = (uint32_t)((b / nbx) << 3);
+            }
+        }
+        // this lane's cell of each block: grid values, packed coordinates and
+        // tap offset relative to the footprint's first tap
+        uint32_t cuv[KMAX], voff[KMAX], voffv[KMAX];
+        float g[KMAX][8];
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int b = k * NW + wave;
+            const uint32_t cu = (uint32_t)(((b % nbx) << 3) + lu);
+            const uint32_t cv = (uint32_t)(((b / nbx) << 3) + lv);
+            cuv[k] = cu | (cv << 16);
+            if constexpr (SEP) {
+                voff[k] = cu * (uint32_t)beta * kElem;
+                voffv[k] = cv * (uint32_t)beta * kElem;
+            } else {
+                voff[k] = (cv * rowlen + cu) * (uint32_t)beta * kElem;
+                voffv[k] = 0u;
+            }
+            const int u = cu0 + (int)cu, v = cv0 + (int)cv;
+            const bool in_grid = b < nblocks && u < prm.nu && v < prm.nv;
+#pragma unroll
+            for (int pol = 0; pol < 4; ++pol) {
+                float2 x = make_float2(0.0f, 0.0f);
+                if (in_grid && pol < npol)
+                    x = *reinterpret_cast<const float2 *>(
+                        grid + 2 * (((int64_t)pol * prm.nv + v) * prm.nu + u));
+                g[k][2 * pol] = x.x;
+                g[k][2 * pol + 1] = x.y;
+                bad = bad || !isfinite(x.x) || !isfinite(x.y);
+            }
+        }
+        // a zero tap times a non-finite grid value is NaN: chunks whose region
+        // holds one mask the taps outside each footprint instead
+        const bool exact = __syncthreads_or(bad) != 0;
+
+        auto visit = [&](const RecMeta m, float (&acc)[8], auto exact_t) {
+            constexpr bool EXACT = decltype(exact_t)::value;
+            const uint32_t a = meta_ku(m) & (uint32_t)Tm;
+            const uint32_t bq = meta_kv(m) & (uint32_t)Tm;
+            const uint32_t hit = (uint32_t)__ballot((blo_u + 7u - a <= (uint32_t)(S + 6)) &&
+                                                    (blo_v + 7u - bq <= (uint32_t)(S + 6)));
+            const uint32_t full = (uint32_t)__ballot((blo_u - a <= (uint32_t)(S - 8)) &&
+                                                     (blo_v - bq <= (uint32_t)(S - 8)));
+            const uint32_t ab = a | (bq << 16);
+            const char *tb;
+            const char *tbv = nullptr;
+            if constexpr (SEP) {
+                tb = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a * beta) * (int64_t)kElem;
+                tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq * beta) * (int64_t)kElem;
+            } else {
+                tb = tbase + ((int64_t)m.toff - (int64_t)(bq * rowlen + a) * beta) * (int64_t)kElem;
+            }
+            auto tap = [&](const int k) {
+                uint32_t o = voff[k];
+                asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+                if constexpr (SEP) {
+                    uint32_t ov = voffv[k];
+                    asm volatile("" : "+v"(ov));
+                    const float t = TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
+                                    TapTraits<TapT>::real((const TapT *)(tbv + ov), 0);
+                    return make_float2(t, 0.0f);
+                } else {
+                    return TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
+                }
+            };
+            // acc += conj(w) * G = (wr gr + wi gi) + j (wr gi - wi gr)
+            auto madd = [&](const int k, const float2 w) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float gr = g[k][2 * q], gi = g[k][2 * q + 1];
+                    acc[2 * q] = fmaf(w.x, gr, fmaf(w.y, gi, acc[2 * q]));
+                    acc[2 * q + 1] = fmaf(w.x, gi, fmaf(-w.y, gr, acc[2 * q + 1]));
+                }
+            };
+            if constexpr (EXACT) {
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    if (!((hit >> k) & 1u)) continue;
+                    const uint32_t d = cuv[k] - ab;   // a borrow only where du < 0
+                    if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S) madd(k, tap(k));
+                }
+            } else {
+                float2 w[KMAX];
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    w[k] = make_float2(0.0f, 0.0f);
+                    if (!((hit >> k) & 1u)) continue;
+                    const uint32_t d = cuv[k] - ab;
+                    if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S) w[k] = tap(k);
+                }
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if ((hit >> k) & 1u) madd(k, w[k]);
+            }
+        };
+
+        auto records = [&](auto exact_t) {
+            for (uint32_t r0 = ch.start; r0 < ch.start + ch.len; r0 += B) {
+                const uint32_t nb = min((uint32_t)B, ch.start + ch.len - r0);
+                float part[NV];
+#pragma unroll
+                for (int i = 0; i < NV; ++i) part[i] = 0.0f;
+#pragma unroll
+                for (int bi = 0; bi < B; ++bi) {
+                    if ((uint32_t)bi < nb) {
+                        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                        visit(smeta[r0 + bi], acc, exact_t);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) part[bi * 8 + q] = acc[q];
+                    }
+                }
+                wave_reduce_scatter<NV>(part, lane);
+                if (writer) s_part[parity][wave][my_idx] = part[0];
+                __syncthreads();
+                if ((int)threadIdx.x < NV) {
+                    const int bi = threadIdx.x >> 3, q = threadIdx.x & 7;
+                    if ((uint32_t)bi < nb && (q >> 1) < npol) {
+                        float sum = 0.0f;
+#pragma unroll
+                        for (int w = 0; w < NW; ++w) sum += s_part[parity][w][threadIdx.x];
+                        vis_out[((size_t)sperm[r0 + bi] * npol + (q >> 1)) * 2 + (q & 1)] = sum;
+                    }
+                }
+                // the other buffer takes the next group, so one barrier per
+                // group keeps the readers ahead of the next writers
+                parity ^= 1;
+            }
+        };
+        if (exact)
+            records(std::true_type{});
+        else
+            records(std::false_type{});
+    }
+}
+
+// Supports up to 32: the lanes of a wave take the taps of one record (tap
+// q = t * 64 + lane, q < S^2), so no lane sits outside a footprint.  The
+// chunk's grid region is staged once in LDS as [row][pol][col] float2 rows
+// of PITCH columns (a row stride of 4 PITCH + 8 float2, 16 banks modulo 64,
+// spreads the rows of a footprint over the LDS banks); the four waves of
+// the workgroup take groups of B records in turn, and each group's sums are
+// reduced across the wave's lanes only.
+template <int PITCH>
+constexpr int row_stride() { return 4 * PITCH + 8; }
+
+template <int NTAP, int PITCH, int B, bool SEP, typename TapT>
+__global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
+    const RecMeta *__restrict__ smeta, const uint32_t *__restrict__ sperm,
+    const float *__restrict__ grid, float *__restrict__ vis_out, const TapT *__restrict__ taps,
+    const Chunk *__restrict__ chunks, const uint32_t *__restrict__ plane_cfirst,
+    const PlaneLayout *__restrict__ planes, uint32_t *__restrict__ queue, DegridParams prm) {
+    constexpr int NV = B * 8;
+    constexpr int kPitch = PITCH;
+    constexpr int kRowStride = row_stride<PITCH>();
+    extern __shared__ float2 region[];   // [row][pol][PITCH], row stride kRowStride
+    __shared__ uint32_t s_next;
+    const int wave = (int)uniform_u32(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int npol = prm.npol;
+    const int beta = prm.beta;
+    const uint32_t c_begin = plane_cfirst[prm.p_lo];
+    const uint32_t c_end = plane_cfirst[prm.p_hi];
+    const int my_idx = reduce_index<NV>(lane);
+    const bool writer = (lane & ((64 / NV > 0 ? 64 / NV : 1) - 1)) == 0;
+    int p = prm.p_lo;
+
+    for (uint32_t c = c_begin + next_chunk_dg(queue, &s_next); c < c_end;
+         c = c_begin + next_chunk_dg(queue, &s_next)) {
+        const Chunk ch = chunks[c];
+        while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
+        const PlaneLayout pl = planes[p];
+        const int S = pl.S;
+        const uint32_t local = ch.bucket - (uint32_t)pl.base;
+        const int cu0 = (int)(((local % (uint32_t)pl.ntu) << pl.log2T) + (ch.bbox & 0xffu));
+        const int cv0 = (int)(((local / (uint32_t)pl.ntu) << pl.log2T) + ((ch.bbox >> 16) & 0xffu));
         const int RW = (int)((ch.bbox >> 8) & 0xffu) - (int)(ch.bbox & 0xffu) + S;
         const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
-        const int rowlen = a.beta * S + 1;
-        if constexpr (LDS) {
-            const int n = npol * RH * RW;
-            for (int i = threadIdx.x; i < n; i += kGroupThreads) {
-                const int ru = i % RW;
-                const int t = i / RW;
-                const int rv = t % RH;
-                const int pol = t / RH;
-                const float2 v = *reinterpret_cast<const float2 *>(
-                    a.grid + 2 * (((int64_t)pol * a.nv + cv0 + rv) * a.nu + cu0 + ru));
-                region[(rv * RW + ru) * npol + pol] = v;
-            }
-            __syncthreads();
+        const int rowlen = pl.rowlen;
+
+        // stage the region (cells outside it are never read)
+        for (int i = threadIdx.x; i < npol * RH * RW; i += kGroupThreads) {
+            const int ru = i % RW;
+            const int t = i / RW;
+            const int rv = t % RH;
+            const int pol = t / RH;
+            region[rv * kRowStride + pol * kPitch + ru] = *reinterpret_cast<const float2 *>(
+                grid + 2 * (((int64_t)pol * prm.nv + cv0 + rv) * prm.nu + cu0 + ru));
         }
-        for (uint32_t i = threadIdx.x; i < ch.len; i += kGroupThreads) {
-            const uint32_t r = ch.start + i;
-            const RecMeta m = a.smeta[r];
-            const uint32_t ku = meta_ku(m), kv = meta_kv(m);
-            float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int j = 0; j < S; ++j) {
-                float wv = 0.0f;
-                if constexpr (SEP) wv = TapTraits<TapT>::real(taps, (int64_t)((m.toff >> 16) + j * a.beta));
-                const int64_t trow = (int64_t)m.toff + (int64_t)j * a.beta * rowlen;
-                for (int i2 = 0; i2 < S; ++i2) {
-                    float wr, wi;
-                    if constexpr (SEP) {
-                        wr = TapTraits<TapT>::real(taps, (int64_t)((m.toff & 0xffffu) + i2 * a.beta)) * wv;
-                        wi = 0.0f;
-                    } else {
-                        // records with w < 0 point into the conjugated bank
-                        const float2 k = TapTraits<TapT>::cplx(taps, trow + i2 * a.beta);
-                        wr = k.x;
-                        wi = k.y;
-                    }
+        __syncthreads();
+
+        // this lane's taps: LDS offset and table offset relative to the
+        // footprint's first cell and first tap
+        int lg[NTAP], lt[NTAP], ltv[NTAP];
+        uint32_t on = 0;   // bit t: tap t of this lane lies in the footprint
+        const int nt = (S * S + 63) >> 6;
 #pragma unroll
-                    for (int pol = 0; pol < 4; ++pol) {
-                        if (pol < npol) {
-                            float2 gv;
-                            if constexpr (LDS) {
-                                gv = region[((kv - cv0 + j) * RW + (ku - cu0 + i2)) * npol + pol];
+        for (int t = 0; t < NTAP; ++t) {
+            const int q = t * 64 + lane;
+            const int j = q / S, i = q - (q / S) * S;
+            if (t < nt && q < S * S) on |= 1u << t;
+            lg[t] = j * kRowStride + i;
+            if constexpr (SEP) {
+                lt[t] = i * beta;
+                ltv[t] = j * beta;
+            } else {
+                lt[t] = (j * rowlen + i) * beta;
+                ltv[t] = 0;
+            }
+        }
+
+        // groups of B records, taken by the waves in turn
+        const uint32_t ngroups = (ch.len + B - 1) / B;
+        for (uint32_t gi = (uint32_t)wave; gi < ngroups; gi += kWavesPerGroup) {
+            const uint32_t r0 = ch.start + gi * B;
+            const uint32_t nb = min((uint32_t)B, ch.start + ch.len - r0);
+            float part[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) part[i] = 0.0f;
+#pragma unroll
+            for (int bi = 0; bi < B; ++bi) {
+                if ((uint32_t)bi < nb) {
+                    const RecMeta m = smeta[r0 + bi];
+                    const int sg = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
+#pragma unroll
+                    for (int t = 0; t < NTAP; ++t) {
+                        if (t < nt && ((on >> t) & 1u)) {
+                            float wr, wi;
+                            if constexpr (SEP) {
+                                wr = TapTraits<TapT>::real(taps, (int64_t)(m.toff & 0xffffu) + lt[t]) *
+                                     TapTraits<TapT>::real(taps, (int64_t)(m.toff >> 16) + ltv[t]);
+                                wi = 0.0f;
                             } else {
-                                gv = *reinterpret_cast<const float2 *>(
-                                    a.grid + 2 * (((int64_t)pol * a.nv + kv + j) * a.nu + ku + i2));
+                                const float2 w = TapTraits<TapT>::cplx(taps, (int64_t)m.toff + lt[t]);
+                                wr = w.x;
+                                wi = w.y;
                             }
-                            // conj(w) * G = (wr gr + wi gi) + j (wr gi - wi gr)
-                            acc[2 * pol] = fmaf(wr, gv.x, fmaf(wi, gv.y, acc[2 * pol]));
-                            acc[2 * pol + 1] = fmaf(wr, gv.y, fmaf(-wi, gv.x, acc[2 * pol + 1]));
+                            const float2 *gp = region + sg + lg[t];
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const float2 gv = gp[q * kPitch];
+                                float &ar = part[bi * 8 + 2 * q];
+                                float &ai = part[bi * 8 + 2 * q + 1];
+                                ar = fmaf(wr, gv.x, fmaf(wi, gv.y, ar));
+                                ai = fmaf(wr, gv.y, fmaf(-wi, gv.x, ai));
+                            }
                         }
                     }
                 }
             }
-            float2 *out = a.vis_out + (size_t)a.sperm[r] * npol;
-#pragma unroll
-            for (int pol = 0; pol < 4; ++pol)
-                if (pol < npol) out[pol] = make_float2(acc[2 * pol], acc[2 * pol + 1]);
+            wave_reduce_scatter<NV>(part, lane);
+            if (writer) {
+                const int bi = my_idx >> 3, q = my_idx & 7;
+                if ((uint32_t)bi < nb && (q >> 1) < npol)
+                    vis_out[((size_t)sperm[r0 + bi] * npol + (q >> 1)) * 2 + (q & 1)] = part[0];
+            }
         }
-        if constexpr (LDS) __syncthreads();
     }
 }
 
-// Zero the outputs of skipped records (and everything, before valid records
-// overwrite theirs).
-__global__ __launch_bounds__(256) void zero_vis_kernel(float2 *__restrict__ v, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        v[i] = make_float2(0.0f, 0.0f);
+// Outputs of skipped records are zero: they follow the valid ones in the
+// plan's sorted order.
+__global__ __launch_bounds__(256) void zero_skipped_kernel(const int64_t *__restrict__ counters,
+                                                           int64_t nrec,
+                                                           const uint32_t *__restrict__ sperm,
+                                                           int32_t npol,
+                                                           float2 *__restrict__ vis_out) {
+    const int64_t nvalid = counters[1];
+    for (int64_t i = nvalid + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrec;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float2 *o = vis_out + (size_t)sperm[i] * npol;
+        for (int q = 0; q < npol; ++q) o[q] = make_float2(0.0f, 0.0f);
+    }
 }
 
-template <bool SEP, typename TapT>
-hipError_t launch_deg(int cls, const DegridArgs &a, const DevGeom &g, int smax, int tile,
-                      hipStream_t stream, int blocks) {
-    if (cls <= 2) {
-        const size_t lds = sizeof(float2) * a.npol * (size_t)(tile + smax - 1) *
-                           (size_t)(tile + smax - 1);
-        hipLaunchKernelGGL((degrid_kernel<SEP, TapT, true>), dim3(blocks), dim3(kGroupThreads),
-                           lds, stream, a, g);
-    } else {
-        hipLaunchKernelGGL((degrid_kernel<SEP, TapT, false>), dim3(blocks), dim3(kGroupThreads),
-                           0, stream, a, g);
-    }
+__global__ void clear_queue_kernel(uint32_t *w, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0u;
+}
+
+struct DegridPtrs {
+    const RecMeta *smeta;
+    const uint32_t *sperm;
+    const float *grid;
+    float *vis_out;
+    const void *taps;
+    const Chunk *chunks;
+    const uint32_t *plane_cfirst;
+    const PlaneLayout *planes;
+    uint32_t *queue;
+};
+
+template <int KMAX, int NW, int B, bool SEP, typename TapT>
+hipError_t launch_dg(const DegridPtrs &a, const DegridParams &prm, int tile, int smax,
+                     hipStream_t stream) {
+    // every block of the largest region has an owner
+    const int side = (tile + smax - 1 + 7) / 8;
+    if (side * side > KMAX * NW) return hipErrorInvalidValue;
+    auto kern = degrid_block_kernel<KMAX, NW, B, SEP, TapT>;
+    int dev = 0, cus = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, NW * kWave, 0) != hipSuccess)
+        per = 1;
+    hipLaunchKernelGGL(kern, dim3(std::max(1, per) * std::max(1, cus)), dim3(NW * kWave), 0,
+                       stream, a.smeta, a.sperm, a.grid, a.vis_out, (const TapT *)a.taps,
+                       a.chunks, a.plane_cfirst, a.planes, a.queue, prm);
     return hipGetLastError();
 }
 
+template <int NTAP, int PITCH, bool SEP, typename TapT>
+hipError_t launch_dt(const DegridPtrs &a, const DegridParams &prm, int tile, int smax,
+                     hipStream_t stream) {
+    // the region must fit the compile-time pitch and the taps the lanes
+    if (tile + smax - 1 > PITCH || smax * smax > NTAP * 64) return hipErrorInvalidValue;
+    const size_t lds = sizeof(float2) * (size_t)row_stride<PITCH>() * (size_t)(tile + smax - 1);
+    // records per reduction group: fewer for many taps per lane (registers)
+    auto kern = degrid_taps_kernel<NTAP, PITCH, (NTAP > 4 ? 2 : 4), SEP, TapT>;
+    int dev = 0, cus = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kGroupThreads, lds) != hipSuccess)
+        per = 1;
+    hipLaunchKernelGGL(kern, dim3(std::max(1, per) * std::max(1, cus)), dim3(kGroupThreads), lds,
+                       stream, a.smeta, a.sperm, a.grid, a.vis_out, (const TapT *)a.taps,
+                       a.chunks, a.plane_cfirst, a.planes, a.queue, prm);
+    return hipGetLastError();
+}
+
+template <bool SEP, typename TapT>
+hipError_t launch_deg(int cls, const DegridPtrs &a, const DegridParams &prm, int tile, int smax,
+                      hipStream_t stream) {
+    switch (cls) {
+    case 0: return launch_dt<1, 32, SEP, TapT>(a, prm, tile, smax, stream);
+    case 1: return launch_dt<4, 32, SEP, TapT>(a, prm, tile, smax, stream);
+    case 2: return launch_dt<16, 48, SEP, TapT>(a, prm, tile, smax, stream);
+    default: return launch_dg<7, 16, 2, SEP, TapT>(a, prm, tile, smax, stream);
+    }
+}
+
 template <bool SEP>
-hipError_t launch_deg_t(mg_dtype dt, int cls, const DegridArgs &a, const DevGeom &g, int smax,
-                        int tile, hipStream_t stream, int blocks) {
+hipError_t launch_deg_t(mg_dtype dt, int cls, const DegridPtrs &a, const DegridParams &prm,
+                        int tile, int smax, hipStream_t stream) {
     switch (dt) {
-    case MG_F16:
-        return launch_deg<SEP, __half>(cls, a, g, smax, tile, stream, blocks);
-    case MG_BF16:
-        return launch_deg<SEP, __hip_bfloat16>(cls, a, g, smax, tile, stream, blocks);
-    default:
-        return launch_deg<SEP, float>(cls, a, g, smax, tile, stream, blocks);
+    case MG_F16: return launch_deg<SEP, __half>(cls, a, prm, tile, smax, stream);
+    case MG_BF16: return launch_deg<SEP, __hip_bfloat16>(cls, a, prm, tile, smax, stream);
+    default: return launch_deg<SEP, float>(cls, a, prm, tile, smax, stream);
     }
 }
 
 }  // namespace
 
 mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hipStream_t stream) {
-    const int64_t nv = P.nrec * P.geom.npol;
-    if (nv == 0) return MG_OK;
-    {
-        int64_t nb = (nv + 255) / 256;
-        if (nb > 16384) nb = 16384;
-        hipLaunchKernelGGL(zero_vis_kernel, dim3((unsigned)nb), dim3(256), 0, stream,
-                           (float2 *)vis_out, nv);
-    }
-    DegridArgs a;
-    a.smeta = P.smeta;
-    a.sperm = P.sperm;
-    a.grid = (const float *)grid;
-    a.vis_out = (float2 *)vis_out;
-    a.taps = P.taps;
-    a.chunks = P.chunks;
-    a.plane_cfirst = P.plane_cfirst;
-    a.planes = P.d_planes;
-    a.npol = P.geom.npol;
-    a.nu = P.geom.nu;
-    a.nv = P.geom.nv;
-    a.beta = P.geom.beta;
-    const bool sep = P.kind == MG_KERNEL_SEPARABLE;
-    hipError_t e = hipGetLastError();
+    if (P.nrec == 0) return MG_OK;
     const int np = P.nplanes_eff;
+    uint32_t *queues = nullptr;
+    hipError_t e = hipMallocAsync((void **)&queues, sizeof(uint32_t) * (size_t)np, stream);
+    if (e != hipSuccess) return set_error(MG_ENOMEM, "degrid: work queue allocation failed");
+    hipLaunchKernelGGL(clear_queue_kernel, dim3(1), dim3(256), 0, stream, queues, np);
+    {
+        int64_t nb = (P.nrec + 255) / 256;
+        if (nb > 4096) nb = 4096;
+        hipLaunchKernelGGL(zero_skipped_kernel, dim3((unsigned)nb), dim3(256), 0, stream,
+                           P.counters, P.nrec, P.sperm, P.geom.npol, (float2 *)vis_out);
+    }
+    DegridPtrs a{P.smeta, P.sperm, (const float *)grid, (float *)vis_out, P.taps, P.chunks,
+                 P.plane_cfirst, P.d_planes, nullptr};
+    DegridParams prm{P.geom.npol, P.geom.nu, P.geom.nv, P.geom.beta, 0, 0};
+    const bool sep = P.kind == MG_KERNEL_SEPARABLE;
+    // one launch per run of consecutive planes of the same class
     int p0 = 0;
     while (p0 < np && e == hipSuccess) {
         int p1 = p0 + 1;
@@ -180,14 +496,15 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hip
             smax = std::max(smax, P.planes[p1].S);
             ++p1;
         }
-        a.p_lo = p0;
-        a.p_hi = p1;
+        prm.p_lo = p0;
+        prm.p_hi = p1;
+        a.queue = queues + p0;
         const int cls = P.planes[p0].cls;
-        e = sep ? launch_deg_t<true>(P.tap_dtype, cls, a, P.geom, smax, P.planes[p0].T, stream, 2048)
-                : launch_deg_t<false>(P.tap_dtype, cls, a, P.geom, smax, P.planes[p0].T, stream,
-                                      2048);
+        e = sep ? launch_deg_t<true>(P.tap_dtype, cls, a, prm, P.planes[p0].T, smax, stream)
+                : launch_deg_t<false>(P.tap_dtype, cls, a, prm, P.planes[p0].T, smax, stream);
         p0 = p1;
     }
+    hipFreeAsync(queues, stream);
     if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("degrid kernels: ") + hipGetErrorString(e));
     return MG_OK;
 }

@@ -183,14 +183,19 @@ __global__ __launch_bounds__(256) void scan_down_kernel(const uint32_t *__restri
 // scatter records into bucket order (order inside a bucket is arbitrary;
 // the chunk sort below orders each chunk by cell)
 // ---------------------------------------------------------------------------
+// Valid records go to their bucket's slots; skipped records follow all valid
+// ones (sperm only: their outputs are zeroed by the degridder).
 __global__ __launch_bounds__(256) void scatter_kernel(int64_t nrec,
                                                       const RecMeta *__restrict__ meta,
                                                       const uint32_t *__restrict__ bucket_of,
                                                       uint32_t *__restrict__ cursor,
+                                                      const uint2 *__restrict__ total,
+                                                      int64_t *__restrict__ counters,
                                                       RecMeta *__restrict__ smeta,
                                                       uint32_t *__restrict__ sperm) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    const int64_t nvalid = (int64_t)total->x;
     for (int64_t r0 = first; r0 < nrec; r0 += stride) {
         const int64_t r = r0 + (threadIdx.x & 63);
         const uint32_t b = (r < nrec) ? bucket_of[r] : kInvalidBucket;
@@ -199,6 +204,9 @@ __global__ __launch_bounds__(256) void scatter_kernel(int64_t nrec,
         if (act) {
             smeta[pos] = meta[r];
             sperm[pos] = (uint32_t)r;
+        } else if (r < nrec) {
+            const int64_t q = nvalid + (int64_t)atomicAdd((unsigned long long *)&counters[3], 1ull);
+            if (q < nrec) sperm[q] = (uint32_t)r;
         }
     }
 }
@@ -228,7 +236,8 @@ __global__ __launch_bounds__(256) void chunk_list_kernel(int64_t nb, uint32_t R,
 }
 
 // plane_cfirst[p] = first chunk of plane p; plane_cfirst[P] = chunk count.
-// counters[1] = valid records, counters[2] = chunks.
+// counters[1] = valid records, counters[2] = chunks (counters[3] counts the
+// skipped records placed by the scatter).
 __global__ void plane_ranges_kernel(int32_t nplanes, const PlaneLayout *__restrict__ planes,
                                     int64_t nb, const uint32_t *__restrict__ cstart,
                                     const uint2 *__restrict__ total,
@@ -508,7 +517,8 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
                        sums, bstart, cursor, cstart);
     if (nrec > 0)
         hipLaunchKernelGGL(scatter_kernel, dim3(grid_blocks(nrec, 256)), dim3(256), 0, stream,
-                           nrec, meta, bucket_of, cursor, P.smeta, P.sperm);
+                           nrec, meta, bucket_of, cursor, sums + nscan, P.counters, P.smeta,
+                           P.sperm);
     hipLaunchKernelGGL(chunk_list_kernel, dim3(grid_blocks(nb, 256)), dim3(256), 0, stream, nb, R,
                        hist, bstart, cstart, P.chunks);
     hipLaunchKernelGGL(plane_ranges_kernel, dim3(1), dim3(256), 0, stream, np, P.d_planes, nb,
