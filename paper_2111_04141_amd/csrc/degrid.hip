@@ -37,42 +37,82 @@ __device__ inline uint32_t next_chunk_dg(uint32_t *queue, uint32_t *slot) {
     return uniform_u32(*slot);
 }
 
-// In-place butterfly over the lanes of a wave: on entry every lane holds N
-// partial values; on exit lane l holds in v[0] the wave-wide sum of value
-// index idx(l), where idx takes the lane bits 5, 4, ... (one per halving step)
-// as its binary digits from the most significant down; lanes that differ
-// only in the remaining low bits hold the same sum.
-template <int N, int H>
-__device__ inline void reduce_halve(float (&v)[N], int lane) {
-    // offset of this step: 32 for the first halving, then 16, 8, ...
-    constexpr int kO = 32 >> (__builtin_ctz(N) - __builtin_ctz(2 * H));
-    const bool up = (lane & kO) != 0;
+// Reduce-scatter over the 64 lanes of a wave.  On entry every lane holds N
+// partial values (N a power of two, 2..32); on exit v[0] of lane l holds the
+// wave-wide sum of value index reduce_index<N>(l).  Each halving step pairs
+// every lane with the lane that differs in one bit: a lane keeps the half of
+// its values selected by that bit and adds the partner's copy of the same
+// half.  The bits are taken in the order 32, 16 (the gfx950 half-wave and
+// row swaps, which exchange two registers in one instruction), then 8, 2, 1
+// (DPP row rotation and quad permutes), then 4 (a swizzle); steps beyond
+// log2(N) only add the partner's value, so lanes differing in those bits end
+// with the same sum.
+__device__ constexpr int kReduceBits[6] = {32, 16, 8, 2, 1, 4};
+
+__device__ inline float dpp_xor(float x, int o) {
+    const int xi = __float_as_int(x);
+    int r;
+    if (o == 8)
+        r = __builtin_amdgcn_update_dpp(0, xi, 0x128, 0xf, 0xf, false);   // row_ror:8
+    else if (o == 2)
+        r = __builtin_amdgcn_update_dpp(0, xi, 0x4e, 0xf, 0xf, false);    // quad_perm 2,3,0,1
+    else
+        r = __builtin_amdgcn_update_dpp(0, xi, 0xb1, 0xf, 0xf, false);    // quad_perm 1,0,3,2
+    return __int_as_float(r);
+}
+
+template <int N, int S, int H>
+__device__ inline void reduce_step(float (&v)[N], int lane) {
+    constexpr int o = kReduceBits[S];
 #pragma unroll
     for (int i = 0; i < H; ++i) {
-        const float send = up ? v[i] : v[i + H];
-        const float keep = up ? v[i + H] : v[i];
-        v[i] = keep + __shfl_xor(send, kO);
+        if constexpr (o == 32 || o == 16) {
+            const auto r = (o == 32)
+                               ? __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
+                                                                  __float_as_uint(v[i + H]), false, false)
+                               : __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]),
+                                                                  __float_as_uint(v[i + H]), false, false);
+            v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        } else {
+            const bool up = (lane & o) != 0;
+            const float keep = up ? v[i + H] : v[i];
+            const float send = up ? v[i] : v[i + H];
+            v[i] = keep + dpp_xor(send, o);
+        }
     }
-    if constexpr (H > 1 && kO > 1) reduce_halve<N, H / 2>(v, lane);
+    if constexpr (H > 1) reduce_step<N, S + 1, H / 2>(v, lane);
 }
 
 template <int N>
 __device__ inline void wave_reduce_scatter(float (&v)[N], int lane) {
-    static_assert(N >= 2 && N <= 64 && (N & (N - 1)) == 0, "N: power of two in [2, 64]");
-    reduce_halve<N, N / 2>(v, lane);
-    // the lanes still sharing a value index: add across the remaining bits
+    static_assert(N >= 2 && N <= 32 && (N & (N - 1)) == 0, "N: power of two in [2, 32]");
+    reduce_step<N, 0, N / 2>(v, lane);
     constexpr int kSteps = __builtin_ctz(N);
 #pragma unroll
-    for (int s = kSteps; s < 6; ++s) v[0] += __shfl_xor(v[0], 32 >> s);
+    for (int s = kSteps; s < 6; ++s) {
+        const int o = kReduceBits[s];
+        v[0] += (o == 4 || o == 32 || o == 16) ? __shfl_xor(v[0], o) : dpp_xor(v[0], o);
+    }
 }
 
+// Value index held by `lane` after wave_reduce_scatter<N>.
 template <int N>
 __device__ inline int reduce_index(int lane) {
     constexpr int kSteps = __builtin_ctz(N);
     int idx = 0;
 #pragma unroll
-    for (int s = 0; s < kSteps; ++s) idx = 2 * idx + ((lane >> (5 - s)) & 1);
+    for (int s = 0; s < kSteps; ++s) idx = 2 * idx + ((lane & kReduceBits[s]) ? 1 : 0);
     return idx;
+}
+
+// One lane per value index writes it: the lanes whose non-halving bits are 0.
+template <int N>
+__device__ inline bool reduce_writer(int lane) {
+    constexpr int kSteps = __builtin_ctz(N);
+    int mask = 0;
+#pragma unroll
+    for (int s = kSteps; s < 6; ++s) mask |= kReduceBits[s];
+    return (lane & mask) == 0;
 }
 
 template <int KMAX, int NW, int B, bool SEP, typename TapT>
@@ -94,7 +134,7 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
     const uint32_t c_end = plane_cfirst[prm.p_hi];
     const char *tbase = reinterpret_cast<const char *>(taps);
     const int my_idx = reduce_index<NV>(lane);
-    const bool writer = (lane & ((64 / NV > 0 ? 64 / NV : 1) - 1)) == 0;
+    const bool writer = reduce_writer<NV>(lane);
     int p = prm.p_lo;
     int parity = 0;
 
@@ -272,6 +312,7 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
     const Chunk *__restrict__ chunks, const uint32_t *__restrict__ plane_cfirst,
     const PlaneLayout *__restrict__ planes, uint32_t *__restrict__ queue, DegridParams prm) {
     constexpr int NV = B * 8;
+    constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);
     constexpr int kPitch = PITCH;
     constexpr int kRowStride = row_stride<PITCH>();
     extern __shared__ float2 region[];   // [row][pol][PITCH], row stride kRowStride
@@ -282,8 +323,9 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
     const int beta = prm.beta;
     const uint32_t c_begin = plane_cfirst[prm.p_lo];
     const uint32_t c_end = plane_cfirst[prm.p_hi];
+    const char *tbase = reinterpret_cast<const char *>(taps);
     const int my_idx = reduce_index<NV>(lane);
-    const bool writer = (lane & ((64 / NV > 0 ? 64 / NV : 1) - 1)) == 0;
+    const bool writer = reduce_writer<NV>(lane);
     int p = prm.p_lo;
 
     for (uint32_t c = c_begin + next_chunk_dg(queue, &s_next); c < c_end;
@@ -310,60 +352,122 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
         }
         __syncthreads();
 
-        // this lane's taps: LDS offset and table offset relative to the
-        // footprint's first cell and first tap
-        int lg[NTAP], lt[NTAP], ltv[NTAP];
-        uint32_t on = 0;   // bit t: tap t of this lane lies in the footprint
+        // this lane's taps: LDS offset and table byte offset relative to the
+        // footprint's first cell and first tap.  Taps t < nt - 1 lie in every
+        // footprint; tap nt - 1 only where q < S^2 (the others keep zeros).
+        int lg[NTAP];
+        uint32_t lt[NTAP], ltv[NTAP];
         const int nt = (S * S + 63) >> 6;
+        const bool last_full = (S * S) % 64 == 0;
+        const bool last_on = ((nt - 1) * 64 + lane) < S * S;
 #pragma unroll
         for (int t = 0; t < NTAP; ++t) {
             const int q = t * 64 + lane;
             const int j = q / S, i = q - (q / S) * S;
-            if (t < nt && q < S * S) on |= 1u << t;
             lg[t] = j * kRowStride + i;
             if constexpr (SEP) {
-                lt[t] = i * beta;
-                ltv[t] = j * beta;
+                lt[t] = (uint32_t)(i * beta) * kElem;
+                ltv[t] = (uint32_t)(j * beta) * kElem;
             } else {
-                lt[t] = (j * rowlen + i) * beta;
-                ltv[t] = 0;
+                lt[t] = (uint32_t)((j * rowlen + i) * beta) * kElem;
+                ltv[t] = 0u;
             }
         }
 
-        // groups of B records, taken by the waves in turn
+        // groups of B records, taken by the waves in turn; a short last group
+        // repeats the chunk's last record (its sums are not written)
+        const uint32_t rend = ch.start + ch.len;
         const uint32_t ngroups = (ch.len + B - 1) / B;
         for (uint32_t gi = (uint32_t)wave; gi < ngroups; gi += kWavesPerGroup) {
             const uint32_t r0 = ch.start + gi * B;
-            const uint32_t nb = min((uint32_t)B, ch.start + ch.len - r0);
+            const uint32_t nb = min((uint32_t)B, rend - r0);
             float part[NV];
 #pragma unroll
             for (int i = 0; i < NV; ++i) part[i] = 0.0f;
 #pragma unroll
             for (int bi = 0; bi < B; ++bi) {
-                if ((uint32_t)bi < nb) {
-                    const RecMeta m = smeta[r0 + bi];
-                    const int sg = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
+                const RecMeta m = smeta[min(r0 + (uint32_t)bi, rend - 1)];
+                const int sg = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
+                const char *tb;
+                const char *tbv = nullptr;
+                if constexpr (SEP) {
+                    tb = tbase + (size_t)(m.toff & 0xffffu) * kElem;
+                    tbv = tbase + (size_t)(m.toff >> 16) * kElem;
+                } else {
+                    tb = tbase + (size_t)m.toff * kElem;
+                }
+                if constexpr (NTAP > 4) {
+                    // many taps per lane: one tap at a time (registers)
 #pragma unroll
                     for (int t = 0; t < NTAP; ++t) {
-                        if (t < nt && ((on >> t) & 1u)) {
-                            float wr, wi;
+                        if (t >= nt) continue;
+                        if (t == nt - 1 && !last_full && !last_on) continue;
+                        uint32_t o = lt[t];
+                        asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+                        float2 w;
+                        if constexpr (SEP) {
+                            uint32_t ov = ltv[t];
+                            asm volatile("" : "+v"(ov));
+                            w = make_float2(TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
+                                                TapTraits<TapT>::real((const TapT *)(tbv + ov), 0),
+                                            0.0f);
+                        } else {
+                            w = TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
+                        }
+                        const float2 *gp = region + sg + lg[t];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const float2 gq = gp[q * kPitch];
+                            float &ar = part[bi * 8 + 2 * q];
+                            float &ai = part[bi * 8 + 2 * q + 1];
+                            ar = fmaf(w.x, gq.x, fmaf(w.y, gq.y, ar));
+                            ai = fmaf(w.x, gq.y, fmaf(-w.y, gq.x, ai));
+                        }
+                    }
+                } else {
+                    // loads of TB taps, then their multiply-adds
+                    constexpr int TB = NTAP < 4 ? NTAP : 4;
+#pragma unroll
+                    for (int t0 = 0; t0 < NTAP; t0 += TB) {
+                        float2 w[TB], gv[TB][4];
+                        auto load = [&](const int t, const int u) {
+                            uint32_t o = lt[t];
+                            asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
                             if constexpr (SEP) {
-                                wr = TapTraits<TapT>::real(taps, (int64_t)(m.toff & 0xffffu) + lt[t]) *
-                                     TapTraits<TapT>::real(taps, (int64_t)(m.toff >> 16) + ltv[t]);
-                                wi = 0.0f;
+                                uint32_t ov = ltv[t];
+                                asm volatile("" : "+v"(ov));
+                                w[u] = make_float2(TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
+                                                       TapTraits<TapT>::real((const TapT *)(tbv + ov), 0),
+                                                   0.0f);
                             } else {
-                                const float2 w = TapTraits<TapT>::cplx(taps, (int64_t)m.toff + lt[t]);
-                                wr = w.x;
-                                wi = w.y;
+                                w[u] = TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
                             }
                             const float2 *gp = region + sg + lg[t];
 #pragma unroll
+                            for (int q = 0; q < 4; ++q) gv[u][q] = gp[q * kPitch];
+                        };
+#pragma unroll
+                        for (int u = 0; u < TB; ++u) {
+                            const int t = t0 + u;
+                            if (t >= nt) continue;
+                            if (t < nt - 1 || last_full) {
+                                load(t, u);
+                            } else {
+                                w[u] = make_float2(0.0f, 0.0f);
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) gv[u][q] = make_float2(0.0f, 0.0f);
+                                if (last_on) load(t, u);
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < TB; ++u) {
+                            if (t0 + u >= nt) continue;
+#pragma unroll
                             for (int q = 0; q < 4; ++q) {
-                                const float2 gv = gp[q * kPitch];
                                 float &ar = part[bi * 8 + 2 * q];
                                 float &ai = part[bi * 8 + 2 * q + 1];
-                                ar = fmaf(wr, gv.x, fmaf(wi, gv.y, ar));
-                                ai = fmaf(wr, gv.y, fmaf(-wi, gv.x, ai));
+                                ar = fmaf(w[u].x, gv[u][q].x, fmaf(w[u].y, gv[u][q].y, ar));
+                                ai = fmaf(w[u].x, gv[u][q].y, fmaf(-w[u].y, gv[u][q].x, ai));
                             }
                         }
                     }
