@@ -93,12 +93,15 @@ __device__ inline uint32_t next_chunk(uint32_t *queue, uint32_t *slot) {
 }
 
 // ---------------------------------------------------------------------------
-// moving-window gridder
+// moving-window gridder (supports up to 16)
 // ---------------------------------------------------------------------------
-// KMAX: slots per lane (compile-time bound); NG: waves sharing one chunk's
-// records but owning different slots; LDS: commit into the shared
-// fixed-point region (else straight into the grid with float atomics).
-template <int KMAX, int NG, bool SEP, typename TapT, bool LDS>
+// KMAX: slots per lane (S^2 <= 64 KMAX).  The four waves of a workgroup take
+// consecutive quarters of the chunk's records, each with its own window.
+// Each slot keeps its cell and the term cell_v beta rowlen + cell_u beta of
+// its tap offset (bytes, modulo 2^32); a record subtracts its own term, so
+// the slot's tap offset costs one subtraction per record, and only slots
+// whose cell leaves the footprint do more work.
+template <int KMAX, bool SEP, typename TapT>
 __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
     const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
@@ -106,26 +109,24 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
     const uint32_t *__restrict__ nonfinite, uint32_t *__restrict__ queue, GridParams prm) {
     // fixed point cannot hold NaN or Inf: calls whose visibilities are not
     // all finite commit straight to the grid in FP32
-    const bool use_lds = LDS && uniform_u32(*nonfinite) == 0u;
+    const bool use_lds = uniform_u32(*nonfinite) == 0u;
     extern __shared__ int32_t region[];   // [8][RH][RW]: (pol, re/im) planes
     __shared__ float s_bound[kWavesPerGroup];
-    constexpr int NSPLIT = kWavesPerGroup / NG;
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);   // bytes per tap
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int grp = wave % NG;
-    const int split = wave / NG;
     const int npol = prm.npol;
-    const int beta = prm.beta;
+    const uint32_t beta = (uint32_t)prm.beta;
     const uint32_t c_begin = plane_cfirst[prm.p_lo];
     const uint32_t c_end = plane_cfirst[prm.p_hi];
+    const char *tbase = reinterpret_cast<const char *>(taps);
 
     __shared__ uint32_t s_next;
+    int p = prm.p_lo;   // chunks come in increasing order: the plane only moves forward
     for (uint32_t c = c_begin + next_chunk(queue, &s_next); c < c_end;
          c = c_begin + next_chunk(queue, &s_next)) {
         const Chunk ch = chunks[c];
-        int p = prm.p_lo;
-        while (p + 1 < prm.p_hi && (int64_t)ch.bucket >= planes[p + 1].base) ++p;
+        while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
         const PlaneLayout pl = planes[p];
         const int S = pl.S;
         const uint32_t local = ch.bucket - (uint32_t)pl.base;
@@ -137,8 +138,10 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
         const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
         const int plane_cells = RH * RW;
         const uint32_t rowlen = (uint32_t)pl.rowlen;
-        const char *tbase = reinterpret_cast<const char *>(taps);
         const uint32_t rb0 = ch.start, re0 = ch.start + ch.len;
+        // offset terms per cell step (bytes)
+        const uint32_t su_step = beta * kElem;
+        const uint32_t sv_step = SEP ? beta * kElem : beta * rowlen * kElem;
 
         // fixed-point scale of this chunk: 2^scale * bound <= 2^30
         int scale = 0;
@@ -165,20 +168,23 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             __syncthreads();
         }
 
-        // slots of this wave; per-lane flags are bit fields (bit k = slot k)
+        // slots of this wave: slot k * 64 + lane; per-lane flags are bit
+        // fields (bit k = slot k)
         const int nslots = S * S;
-        const int spg = (nslots + NG - 1) / NG;
-        const int kdyn = (spg + kWave - 1) / kWave;
-        uint32_t cell[KMAX], offa[KMAX], offb[KMAX];
+        const int kdyn = (nslots + kWave - 1) / kWave;
+        uint32_t cell[KMAX], lo[KMAX], lov[KMAX], suv[KMAX];
         uint32_t valid_bits = 0;
         float acc[KMAX][8];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            const int sl = k * kWave + lane;
-            if (k < kdyn && sl < spg && grp * spg + sl < nslots) valid_bits |= 1u << k;
+            if (k < kdyn && k * kWave + lane < nslots) valid_bits |= 1u << k;
+            // slot (su, sv) owns the cells congruent to it mod S
+            const uint32_t sidx = (uint32_t)(k * kWave + lane);
+            const uint32_t sv = sidx / (uint32_t)S;
+            suv[k] = (sidx - sv * (uint32_t)S) | (sv << 16);
             cell[k] = kNoCell;
-            offa[k] = 0u;
-            offb[k] = 0u;
+            lo[k] = 0u;
+            lov[k] = 0u;
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
         }
@@ -205,7 +211,10 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             }
         };
 
+        // window of the current footprint: slots whose cell left it commit
+        // and take the cell congruent to them inside the new footprint
         uint32_t prev_kuv = 0xffffffffu;
+        uint32_t ru = 0, rv = 0;   // the record's offset terms (bytes, modulo 2^32)
         auto window_update = [&](const RecMeta m) {
             const uint32_t kuv = m.kuv;
             if (kuv == prev_kuv) return;
@@ -215,8 +224,8 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
                 if (k < kdyn) {
-                    const uint32_t du = (cell[k] & 0xffffu) - ku, dv = (cell[k] >> 16) - kv;
-                    if (max(du, dv) >= (uint32_t)S) moved_bits |= 1u << k;
+                    const uint32_t d = cell[k] - kuv;   // a borrow only where du < 0
+                    if (max(d & 0xffffu, d >> 16) >= (uint32_t)S) moved_bits |= 1u << k;
                 }
             }
             moved_bits &= valid_bits;
@@ -228,55 +237,62 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
                         if (cell[k] != kNoCell) commit(acc[k], cell[k]);
 #pragma unroll
                         for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-                        // slot (su, sv) owns the cells congruent to it mod S
-                        const uint32_t sidx = (uint32_t)(grp * spg + k * kWave + lane);
-                        const uint32_t sv = sidx / (uint32_t)S, su = sidx - sv * (uint32_t)S;
-                        int du = (int)su - (int)kmu;
-                        int dv = (int)sv - (int)kmv;
+                        int du = (int)(suv[k] & 0xffffu) - (int)kmu;
+                        int dv = (int)(suv[k] >> 16) - (int)kmv;
                         du += (du < 0) ? S : 0;
                         dv += (dv < 0) ? S : 0;
-                        cell[k] = (ku + (uint32_t)du) | ((kv + (uint32_t)dv) << 16);
+                        const uint32_t nu_ = ku + (uint32_t)du, nv_ = kv + (uint32_t)dv;
+                        cell[k] = nu_ | (nv_ << 16);
+                        if constexpr (SEP) {
+                            lo[k] = nu_ * su_step;
+                            lov[k] = nv_ * sv_step;
+                        } else {
+                            lo[k] = nv_ * sv_step + nu_ * su_step;
+                        }
                     }
                 }
             }
+            if constexpr (SEP) {
+                ru = ku * su_step;
+                rv = kv * sv_step;
+            } else {
+                ru = kv * sv_step + ku * su_step;
+            }
+            // lanes without a slot (S^2 not a multiple of 64) read the
+            // footprint's first tap: their offset term follows the record's
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                if (k < kdyn) {
-                    const bool on = (valid_bits >> k) & 1u;
-                    const uint32_t du = on ? (cell[k] & 0xffffu) - ku : 0u;
-                    const uint32_t dv = on ? (cell[k] >> 16) - kv : 0u;
-                    if constexpr (SEP) {
-                        offa[k] = du * (uint32_t)beta * kElem;
-                        offb[k] = dv * (uint32_t)beta * kElem;
-                    } else {
-                        offa[k] = (dv * (uint32_t)beta * rowlen + du * (uint32_t)beta) * kElem;
-                    }
+                if (k < kdyn && !((valid_bits >> k) & 1u)) {
+                    lo[k] = ru;
+                    lov[k] = rv;
                 }
             }
         };
 
-        auto accumulate = [&](const RecMeta m, const RecVis &f) {
+        // tap of slot k for a record (uniform base + 32-bit lane offset)
+        auto tap = [&](const RecMeta m, const int k) {
             if constexpr (SEP) {
                 const char *tu = tbase + (size_t)(m.toff & 0xffffu) * kElem;
                 const char *tv = tbase + (size_t)(m.toff >> 16) * kElem;
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    if (k < kdyn)
-                        fma_real(acc[k],
-                                 TapTraits<TapT>::real((const TapT *)(tu + offa[k]), 0) *
-                                     TapTraits<TapT>::real((const TapT *)(tv + offb[k]), 0),
-                                 f);
+                const uint32_t ou = lo[k] - ru, ov = lov[k] - rv;
+                return make_float2(TapTraits<TapT>::real((const TapT *)(tu + ou), 0) *
+                                       TapTraits<TapT>::real((const TapT *)(tv + ov), 0),
+                                   0.0f);
             } else {
                 const char *tb = tbase + (size_t)m.toff * kElem;
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    if (k < kdyn) fma_complex(acc[k], TapTraits<TapT>::cplx((const TapT *)(tb + offa[k]), 0), f);
+                return TapTraits<TapT>::cplx((const TapT *)(tb + (lo[k] - ru)), 0);
             }
+        };
+        auto madd = [&](const int k, const float2 w, const RecVis &f) {
+            if constexpr (SEP)
+                fma_real(acc[k], w.x, f);
+            else
+                fma_complex(acc[k], w, f);
         };
 
         const uint32_t len = ch.len;
-        const uint32_t rb = ch.start + (uint32_t)(((uint64_t)len * split) / NSPLIT);
-        const uint32_t re = ch.start + (uint32_t)(((uint64_t)len * (split + 1)) / NSPLIT);
+        const uint32_t rb = ch.start + (uint32_t)(((uint64_t)len * wave) / kWavesPerGroup);
+        const uint32_t re = ch.start + (uint32_t)(((uint64_t)len * (wave + 1)) / kWavesPerGroup);
         if (rb < re) {
             // records are read in batches on the scalar unit; the next batch's
             // loads are issued after the current batch has been consumed
@@ -304,37 +320,20 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
                     va4[i] = na4[i];
                     vb4[i] = nb4[i];
                 }
-                bool same = (r + kBatch <= re);
-#pragma unroll
-                for (int i = 0; i < kBatch; ++i) same = same && (mm[i].kuv == prev_kuv);
-                same = uniform_u32(same ? 1u : 0u) != 0u;
                 __builtin_amdgcn_sched_barrier(0);
                 load_batch(r + kBatch);
-                if (!SEP && KMAX <= 4 && same) {
-                    // the window stays still for the whole batch: issue all
-                    // tap loads before the first multiply-add
-                    float2 w[kBatch][KMAX];
 #pragma unroll
-                    for (int i = 0; i < kBatch; ++i) {
-                        const char *tb = tbase + (size_t)mm[i].toff * kElem;
-#pragma unroll
-                        for (int k = 0; k < KMAX; ++k)
-                            if (k < kdyn) w[i][k] = TapTraits<TapT>::cplx((const TapT *)(tb + offa[k]), 0);
-                    }
-#pragma unroll
-                    for (int i = 0; i < kBatch; ++i) {
+                for (int i = 0; i < kBatch; ++i) {
+                    if (r + (uint32_t)i < re) {
+                        window_update(mm[i]);
                         const RecVis f = unpack_vis(va4[i], vb4[i]);
+                        float2 w[KMAX];
 #pragma unroll
                         for (int k = 0; k < KMAX; ++k)
-                            if (k < kdyn) fma_complex(acc[k], w[i][k], f);
-                    }
-                } else {
+                            if (k < kdyn) w[k] = tap(mm[i], k);
 #pragma unroll
-                    for (int i = 0; i < kBatch; ++i) {
-                        if (r + (uint32_t)i < re) {
-                            window_update(mm[i]);
-                            accumulate(mm[i], unpack_vis(va4[i], vb4[i]));
-                        }
+                        for (int k = 0; k < KMAX; ++k)
+                            if (k < kdyn) madd(k, w[k], f);
                     }
                 }
             }
@@ -347,14 +346,14 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             __syncthreads();
             const int n = npol * plane_cells;
             for (int i = threadIdx.x; i < n; i += kGroupThreads) {
-                const int ru = i % RW;
+                const int ru_ = i % RW;
                 const int t = i / RW;
-                const int rv = t % RH;
+                const int rv_ = t % RH;
                 const int pol = t / RH;
-                const int32_t qr = region[(2 * pol) * plane_cells + rv * RW + ru];
-                const int32_t qi = region[(2 * pol + 1) * plane_cells + rv * RW + ru];
+                const int32_t qr = region[(2 * pol) * plane_cells + rv_ * RW + ru_];
+                const int32_t qi = region[(2 * pol + 1) * plane_cells + rv_ * RW + ru_];
                 if ((qr | qi) != 0) {
-                    float *dst = grid + 2 * (((int64_t)pol * prm.nv + cv0 + rv) * prm.nu + cu0 + ru);
+                    float *dst = grid + 2 * (((int64_t)pol * prm.nv + cv0 + rv_) * prm.nu + cu0 + ru_);
                     unsafeAtomicAdd(dst, ldexpf((float)qr, -scale));
                     unsafeAtomicAdd(dst + 1, ldexpf((float)qi, -scale));
                 }
@@ -617,9 +616,9 @@ int resident_groups(Kern kernel, int threads, size_t lds) {
     return std::max(1, per) * std::max(1, cus);
 }
 
-template <int KMAX, int NG, bool SEP, typename TapT, bool LDS>
+template <int KMAX, bool SEP, typename TapT>
 void launch_one(const GridPtrs &a, const GridParams &prm, size_t lds, hipStream_t stream) {
-    auto kern = grid_window_kernel<KMAX, NG, SEP, TapT, LDS>;
+    auto kern = grid_window_kernel<KMAX, SEP, TapT>;
     hipLaunchKernelGGL(kern, dim3(resident_groups(kern, kGroupThreads, lds)),
                        dim3(kGroupThreads), lds, stream, a.smeta, a.svis, a.grid,
                        (const TapT *)a.taps, a.chunks, a.plane_cfirst, a.planes, a.nonfinite,
@@ -647,8 +646,8 @@ hipError_t launch_class(int cls, const GridPtrs &a, const GridParams &prm, int s
                                         (size_t)(tile + smax - 1)
                                   : 0;
     switch (cls) {
-    case 0: launch_one<1, 1, SEP, TapT, true>(a, prm, lds, stream); break;
-    case 1: launch_one<4, 1, SEP, TapT, true>(a, prm, lds, stream); break;
+    case 0: launch_one<1, SEP, TapT>(a, prm, lds, stream); break;
+    case 1: launch_one<4, SEP, TapT>(a, prm, lds, stream); break;
     case 2:
         // every block of the largest region has an owner
         if (region_blocks(tile, smax) > 9 * 4) return hipErrorInvalidValue;

@@ -52,7 +52,7 @@ struct PlanState {
     Chunk *chunks = nullptr;          // [max_chunks]
     uint32_t *plane_cfirst = nullptr; // [nplanes_eff + 1] first chunk of each plane
     PlaneLayout *d_planes = nullptr;  // [nplanes_eff]
-    int64_t *counters = nullptr;      // [0] skipped, [1] valid, [2] chunks, [3] scratch
+    int64_t *counters = nullptr;      // [0] skipped, [1] valid, [2] chunks, [3], [4] scratch
     size_t bytes = 0;
     bool stream_ordered = false;      // allocated with hipMallocAsync
     hipStream_t alloc_stream = nullptr;

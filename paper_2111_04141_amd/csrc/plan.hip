@@ -9,6 +9,8 @@
 // cell inside each chunk of at most R records.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace mg {
@@ -265,22 +267,54 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restri
                                                          int32_t nplanes,
                                                          Chunk *__restrict__ chunks,
                                                          RecMeta *__restrict__ smeta,
-                                                         uint32_t *__restrict__ sperm) {
+                                                         uint32_t *__restrict__ sperm,
+                                                         uint32_t *__restrict__ queue) {
     __shared__ uint32_t hist[1024];
     __shared__ RecMeta m_in[kMaxR];
     __shared__ uint32_t p_in[kMaxR];
     __shared__ uint32_t s_box[4];
+    __shared__ uint32_t s_next;
     const int64_t nchunks = counters[2];
-    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    // chunks are handed out through a counter: their sizes vary from one
+    // record to R
+    auto next = [&]() -> int64_t {
+        __syncthreads();
+        if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
+        __syncthreads();
+        return (int64_t)__builtin_amdgcn_readfirstlane(s_next);
+    };
+    int p = 0;   // chunks come in increasing order: the plane only moves forward
+    for (int64_t c = next(); c < nchunks; c = next()) {
         Chunk ch = chunks[c];
-        // plane of the bucket (planes are few: linear search)
-        int p = 0;
         while (p + 1 < nplanes && (int64_t)ch.bucket >= planes[p + 1].base) ++p;
         const PlaneLayout pl = planes[p];
         const uint32_t local = ch.bucket - (uint32_t)pl.base;
         const uint32_t tu0 = (local % (uint32_t)pl.ntu) << pl.log2T;
         const uint32_t tv0 = (local / (uint32_t)pl.ntu) << pl.log2T;
         const int ncell = pl.T * pl.T;
+        if (pl.cls >= 2) {
+            // the output-stationary kernels of the large supports take the
+            // records in any order: only the bounding box is needed
+            if (threadIdx.x < 4) s_box[threadIdx.x] = (threadIdx.x & 1) ? 0u : 0xffffffffu;
+            __syncthreads();
+            uint32_t umin = 0xffffffffu, umax = 0, vmin = 0xffffffffu, vmax = 0;
+            for (uint32_t i = threadIdx.x; i < ch.len; i += blockDim.x) {
+                const RecMeta m = smeta[ch.start + i];
+                const uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
+                umin = min(umin, du);
+                umax = max(umax, du);
+                vmin = min(vmin, dv);
+                vmax = max(vmax, dv);
+            }
+            atomicMin(&s_box[0], umin);
+            atomicMax(&s_box[1], umax);
+            atomicMin(&s_box[2], vmin);
+            atomicMax(&s_box[3], vmax);
+            __syncthreads();
+            if (threadIdx.x == 0)
+                chunks[c].bbox = s_box[0] | (s_box[1] << 8) | (s_box[2] << 16) | (s_box[3] << 24);
+            continue;
+        }
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) hist[i] = 0;
         if (threadIdx.x < 4) s_box[threadIdx.x] = (threadIdx.x & 1) ? 0u : 0xffffffffu;
         __syncthreads();
@@ -474,7 +508,7 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         (e = malloc_bytes(P, &P.chunks, sizeof(Chunk) * (size_t)P.max_chunks, stream)) ||
         (e = malloc_bytes(P, &P.plane_cfirst, sizeof(uint32_t) * (size_t)(np + 1), stream)) ||
         (e = malloc_bytes(P, &P.d_planes, sizeof(PlaneLayout) * (size_t)np, stream)) ||
-        (e = malloc_bytes(P, &P.counters, sizeof(int64_t) * 4, stream)))
+        (e = malloc_bytes(P, &P.counters, sizeof(int64_t) * 6, stream)))
         return set_error(MG_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
     // temporaries (stream-ordered)
     RecMeta *meta = nullptr;
@@ -496,7 +530,7 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
                    stream);
     // zero-fill with a kernel (no memset nodes, so the calls stay capturable)
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t *)P.counters,
-                       (int64_t)8, 0u);
+                       (int64_t)12, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_blocks(nb, 256)), dim3(256), 0, stream, hist,
                        nb, 0u);
     if (nrec > 0) {
@@ -523,8 +557,18 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
                        hist, bstart, cstart, P.chunks);
     hipLaunchKernelGGL(plane_ranges_kernel, dim3(1), dim3(256), 0, stream, np, P.d_planes, nb,
                        cstart, sums + nscan, P.plane_cfirst, P.counters);
-    hipLaunchKernelGGL(chunk_sort_kernel, dim3(4096), dim3(256), 0, stream, P.counters,
-                       P.d_planes, np, P.chunks, P.smeta, P.sperm);
+    {
+        // as many workgroups as fit at once; they draw chunks from counters[4]
+        int dev = 0, cus = 0, per = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, chunk_sort_kernel, 256, 0) !=
+            hipSuccess)
+            per = 1;
+        hipLaunchKernelGGL(chunk_sort_kernel, dim3(std::max(1, per) * std::max(1, cus)), dim3(256),
+                           0, stream, P.counters, P.d_planes, np, P.chunks, P.smeta, P.sperm,
+                           reinterpret_cast<uint32_t *>(P.counters + 4));
+    }
     {
         const int sep = P.kind == MG_KERNEL_SEPARABLE ? 1 : 0;
         if (P.tap_dtype == MG_F16)
