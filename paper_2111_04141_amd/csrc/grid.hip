@@ -302,15 +302,19 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             float4 na4[kBatch], nb4[kBatch];
             // the record arrays are padded by kBatch entries, so a batch may
             // run past the chunk's end (those records are not used)
-            auto load_batch = [&](uint32_t r0) {
+            const RecMeta *pm = smeta + rb;
+            const float4 *pv = svis + 2 * (size_t)rb;
+            auto load_batch = [&]() {
 #pragma unroll
                 for (int i = 0; i < kBatch; ++i) {
-                    nm[i] = smeta[r0 + i];
-                    na4[i] = svis[2 * (size_t)(r0 + i)];
-                    nb4[i] = svis[2 * (size_t)(r0 + i) + 1];
+                    nm[i] = pm[i];
+                    na4[i] = pv[2 * i];
+                    nb4[i] = pv[2 * i + 1];
                 }
+                pm += kBatch;
+                pv += 2 * kBatch;
             };
-            load_batch(rb);
+            load_batch();
             for (uint32_t r = rb; r < re; r += kBatch) {
                 RecMeta mm[kBatch];
                 float4 va4[kBatch], vb4[kBatch];
@@ -321,7 +325,7 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
                     vb4[i] = nb4[i];
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                load_batch(r + kBatch);
+                load_batch();
 #pragma unroll
                 for (int i = 0; i < kBatch; ++i) {
                     if (r + (uint32_t)i < re) {
@@ -497,14 +501,16 @@ __global__ __launch_bounds__(NW * kWave) void grid_block_kernel(
                 }
             } else {
                 // all tap loads of the record first, then the multiply-adds;
-                // lanes outside the footprint keep a zero tap
+                // lanes outside the footprint keep a zero tap (one vector
+                // test per overlapped block, no separate path for blocks
+                // inside the footprint)
                 float2 w[KMAX];
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k) {
                     w[k] = make_float2(0.0f, 0.0f);
                     if (!((hit >> k) & 1u)) continue;
                     const uint32_t d = cuv[k] - ab;
-                    if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S) w[k] = tap(k);
+                    if (max(d & 0xffffu, d >> 16) < (uint32_t)S) w[k] = tap(k);
                 }
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k)
@@ -518,15 +524,19 @@ __global__ __launch_bounds__(NW * kWave) void grid_block_kernel(
             float4 na4[kBatch], nb4[kBatch];
             // the record arrays are padded by kBatch entries, so a batch may
             // run past the chunk's end (those records are not used)
-            auto load_batch = [&](uint32_t r0) {
+            const RecMeta *pm = smeta + rb;
+            const float4 *pv = svis + 2 * (size_t)rb;
+            auto load_batch = [&]() {
 #pragma unroll
                 for (int i = 0; i < kBatch; ++i) {
-                    nm[i] = smeta[r0 + i];
-                    na4[i] = svis[2 * (size_t)(r0 + i)];
-                    nb4[i] = svis[2 * (size_t)(r0 + i) + 1];
+                    nm[i] = pm[i];
+                    na4[i] = pv[2 * i];
+                    nb4[i] = pv[2 * i + 1];
                 }
+                pm += kBatch;
+                pv += 2 * kBatch;
             };
-            load_batch(rb);
+            load_batch();
             for (uint32_t r = rb; r < re; r += kBatch) {
                 RecMeta mm[kBatch];
                 float4 va4[kBatch], vb4[kBatch];
@@ -537,7 +547,7 @@ __global__ __launch_bounds__(NW * kWave) void grid_block_kernel(
                     vb4[i] = nb4[i];
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                load_batch(r + kBatch);
+                load_batch();
 #pragma unroll
                 for (int i = 0; i < kBatch; ++i)
                     if (r + (uint32_t)i < re) visit(mm[i], unpack_vis(va4[i], vb4[i]), exact_t);

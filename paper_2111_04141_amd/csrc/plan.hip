@@ -262,6 +262,26 @@ __global__ void plane_ranges_kernel(int32_t nplanes, const PlaneLayout *__restri
 // ---------------------------------------------------------------------------
 constexpr int kMaxR = 2048;
 
+// Folds a wave's bounding box into s_box with one LDS atomic per bound: the
+// wave reduces first (an atomic on one LDS word from every lane is turned
+// by the compiler into a lane-by-lane scalar loop).
+__device__ inline void box_to_lds(uint32_t *s_box, uint32_t umin, uint32_t umax, uint32_t vmin,
+                                  uint32_t vmax) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        umin = min(umin, (uint32_t)__shfl_xor((int)umin, off));
+        umax = max(umax, (uint32_t)__shfl_xor((int)umax, off));
+        vmin = min(vmin, (uint32_t)__shfl_xor((int)vmin, off));
+        vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&s_box[0], umin);
+        atomicMax(&s_box[1], umax);
+        atomicMin(&s_box[2], vmin);
+        atomicMax(&s_box[3], vmax);
+    }
+}
+
 __global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restrict__ counters,
                                                          const PlaneLayout *__restrict__ planes,
                                                          int32_t nplanes,
@@ -306,10 +326,7 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restri
                 vmin = min(vmin, dv);
                 vmax = max(vmax, dv);
             }
-            atomicMin(&s_box[0], umin);
-            atomicMax(&s_box[1], umax);
-            atomicMin(&s_box[2], vmin);
-            atomicMax(&s_box[3], vmax);
+            box_to_lds(s_box, umin, umax, vmin, vmax);
             __syncthreads();
             if (threadIdx.x == 0)
                 chunks[c].bbox = s_box[0] | (s_box[1] << 8) | (s_box[2] << 16) | (s_box[3] << 24);
@@ -330,10 +347,7 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restri
             vmin = min(vmin, dv);
             vmax = max(vmax, dv);
         }
-        atomicMin(&s_box[0], umin);
-        atomicMax(&s_box[1], umax);
-        atomicMin(&s_box[2], vmin);
-        atomicMax(&s_box[3], vmax);
+        box_to_lds(s_box, umin, umax, vmin, vmax);
         __syncthreads();
         {
             // exclusive scan of the (up to 1024) cell counts: 4 per thread
