@@ -1,8 +1,9 @@
 // Gridding (scatter) kernels.
 //
-// Work unit: one chunk = up to R cell-sorted records of one (plane, uv tile)
-// bucket, taken by a workgroup of 4 waves.
+// Work unit: one chunk = up to R records of one (plane, uv tile) bucket,
+// taken by one workgroup; chunks are handed out through a per-launch counter.
 //
+// Supports up to 16: moving window (grid_window_kernel).
 //  * Each wave keeps a moving window of S x S slots in registers: slot
 //    (su, sv) owns the grid cells congruent to (su, sv) modulo S, so every
 //    record's S x S footprint holds exactly one cell of each slot, and a
@@ -13,17 +14,19 @@
 //    the 64 lanes of a wave and the records come cell-sorted, so windows
 //    move rarely where records are dense.
 //  * When a slot's cell leaves the footprint its sums are committed into an
-//    LDS copy of the chunk's grid region (tile plus S-1 halo) shared by the
-//    4 waves.  The region holds 32-bit fixed point: each chunk first bounds
-//    every partial sum it can produce (2 * max|tap component| * sum over its
-//    records of max|visibility component|) and picks the power-of-two scale
-//    that maps that bound to 2^30, so integer LDS atomics (which run at full
-//    wave rate, unlike float LDS atomics, which serialise per lane) add the
-//    commits exactly and cannot overflow; the quantum is 2^-31 of the bound
-//    per commit.  At the end of the chunk the region is converted back to
-//    FP32 and added to the grid with float atomics, one per touched cell.
-//  * For supports above 32 the region does not fit; the 4 waves split the
-//    S^2 slots between them and commit straight to the grid.
+//    LDS copy of the chunk's grid region (bounding box plus S-1 halo) shared
+//    by the 4 waves.  The region holds 32-bit fixed point: each chunk first
+//    bounds every partial sum it can produce (2 * max|tap component| * sum
+//    over its records of max|visibility component|) and picks the
+//    power-of-two scale that maps that bound to 2^30, so integer LDS atomics
+//    (which run at full wave rate, unlike float LDS atomics, which serialise
+//    per lane) add the commits exactly and cannot overflow; truncation costs
+//    at most 2^-30 of the bound per commit.  At the end of the chunk the
+//    region is converted back to FP32 and added to the grid with float
+//    atomics, one per touched cell.
+//
+// Supports above 16: blocked output-stationary kernel (grid_block_kernel),
+// for the sparse planes of large |w|; see the kernel's comment.
 //
 // All polarisations are handled per visit: one tap load feeds 4 complex
 // multiply-adds (the thesis's Polarisation Gain, Section 3.5).  Records are
@@ -189,16 +192,16 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
         }
 
-        // adds a slot's sums to its cell
+        // adds a slot's sums to its cell (fixed point: scaled by the exact
+        // power of two 2^scale and truncated, at most one quantum per commit)
+        const float fscale = ldexpf(1.0f, scale);
         auto commit = [&](float (&sums)[8], uint32_t cell_uv) {
             const uint32_t cu_ = cell_uv & 0xffffu, cv_ = cell_uv >> 16;
             if (use_lds) {
                 int32_t *dst = &region[(int)(cv_ - cv0) * RW + (int)(cu_ - cu0)];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int32_t v = __float2int_rn(ldexpf(sums[q], scale));
-                    if (v != 0) atomicAdd(&dst[q * plane_cells], v);
-                }
+                for (int q = 0; q < 8; ++q)
+                    atomicAdd(&dst[q * plane_cells], (int32_t)(sums[q] * fscale));
             } else {
 #pragma unroll
                 for (int pol = 0; pol < 4; ++pol) {
