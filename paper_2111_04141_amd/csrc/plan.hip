@@ -262,92 +262,37 @@ __global__ void plane_ranges_kernel(int32_t nplanes, const PlaneLayout *__restri
 // ---------------------------------------------------------------------------
 constexpr int kMaxR = 2048;
 
-// Folds a wave's bounding box into s_box with one LDS atomic per bound: the
-// wave reduces first (an atomic on one LDS word from every lane is turned
-// by the compiler into a lane-by-lane scalar loop).
-__device__ inline void box_to_lds(uint32_t *s_box, uint32_t umin, uint32_t umax, uint32_t vmin,
-                                  uint32_t vmax) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        umin = min(umin, (uint32_t)__shfl_xor((int)umin, off));
-        umax = max(umax, (uint32_t)__shfl_xor((int)umax, off));
-        vmin = min(vmin, (uint32_t)__shfl_xor((int)vmin, off));
-        vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMin(&s_box[0], umin);
-        atomicMax(&s_box[1], umax);
-        atomicMin(&s_box[2], vmin);
-        atomicMax(&s_box[3], vmax);
-    }
-}
 
-__global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restrict__ counters,
+__global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restrict__ plane_cfirst,
+                                                         int32_t p_split,
                                                          const PlaneLayout *__restrict__ planes,
-                                                         int32_t nplanes,
-                                                         Chunk *__restrict__ chunks,
+                                                         const Chunk *__restrict__ chunks,
                                                          RecMeta *__restrict__ smeta,
-                                                         uint32_t *__restrict__ sperm,
-                                                         uint32_t *__restrict__ queue) {
+                                                         uint32_t *__restrict__ sperm) {
     __shared__ uint32_t hist[1024];
     __shared__ RecMeta m_in[kMaxR];
     __shared__ uint32_t p_in[kMaxR];
-    __shared__ uint32_t s_box[4];
-    __shared__ uint32_t s_next;
-    const int64_t nchunks = counters[2];
-    // chunks are handed out through a counter: their sizes vary from one
-    // record to R
-    auto next = [&]() -> int64_t {
-        __syncthreads();
-        if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
-        __syncthreads();
-        return (int64_t)__builtin_amdgcn_readfirstlane(s_next);
-    };
+    // only the planes before p_split (supports up to 16) are cell-sorted; the
+    // kernels of the larger supports take the records in any order
+    const uint32_t c_end = plane_cfirst[p_split];
     int p = 0;   // chunks come in increasing order: the plane only moves forward
-    for (int64_t c = next(); c < nchunks; c = next()) {
-        Chunk ch = chunks[c];
-        while (p + 1 < nplanes && (int64_t)ch.bucket >= planes[p + 1].base) ++p;
+    for (uint32_t c = blockIdx.x; c < c_end; c += gridDim.x) {
+        const Chunk ch = chunks[c];
+        while (p + 1 < p_split && c >= plane_cfirst[p + 1]) ++p;
         const PlaneLayout pl = planes[p];
         const uint32_t local = ch.bucket - (uint32_t)pl.base;
         const uint32_t tu0 = (local % (uint32_t)pl.ntu) << pl.log2T;
         const uint32_t tv0 = (local / (uint32_t)pl.ntu) << pl.log2T;
         const int ncell = pl.T * pl.T;
-        if (pl.cls >= 2) {
-            // the output-stationary kernels of the large supports take the
-            // records in any order: only the bounding box is needed
-            if (threadIdx.x < 4) s_box[threadIdx.x] = (threadIdx.x & 1) ? 0u : 0xffffffffu;
-            __syncthreads();
-            uint32_t umin = 0xffffffffu, umax = 0, vmin = 0xffffffffu, vmax = 0;
-            for (uint32_t i = threadIdx.x; i < ch.len; i += blockDim.x) {
-                const RecMeta m = smeta[ch.start + i];
-                const uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
-                umin = min(umin, du);
-                umax = max(umax, du);
-                vmin = min(vmin, dv);
-                vmax = max(vmax, dv);
-            }
-            box_to_lds(s_box, umin, umax, vmin, vmax);
-            __syncthreads();
-            if (threadIdx.x == 0)
-                chunks[c].bbox = s_box[0] | (s_box[1] << 8) | (s_box[2] << 16) | (s_box[3] << 24);
-            continue;
-        }
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) hist[i] = 0;
-        if (threadIdx.x < 4) s_box[threadIdx.x] = (threadIdx.x & 1) ? 0u : 0xffffffffu;
         __syncthreads();
-        uint32_t umin = 0xffffffffu, umax = 0, vmin = 0xffffffffu, vmax = 0;
         for (uint32_t i = threadIdx.x; i < ch.len; i += blockDim.x) {
             RecMeta m = smeta[ch.start + i];
             m_in[i] = m;
             p_in[i] = sperm[ch.start + i];
             uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
             atomicAdd(&hist[(du << pl.log2T) | dv], 1u);
-            umin = min(umin, du);
-            umax = max(umax, du);
-            vmin = min(vmin, dv);
-            vmax = max(vmax, dv);
         }
-        box_to_lds(s_box, umin, umax, vmin, vmax);
         __syncthreads();
         {
             // exclusive scan of the (up to 1024) cell counts: 4 per thread
@@ -367,8 +312,6 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restri
                 run += loc[k];
             }
         }
-        if (threadIdx.x == 0)
-            chunks[c].bbox = s_box[0] | (s_box[1] << 8) | (s_box[2] << 16) | (s_box[3] << 24);
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < ch.len; i += blockDim.x) {
             RecMeta m = m_in[i];
@@ -378,6 +321,53 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const int64_t *__restri
             sperm[ch.start + pos] = p_in[i];
         }
         __syncthreads();
+    }
+}
+
+// Bounding box of each chunk's k_lo, relative to its tile origin: one wave
+// per chunk (no barriers), so the many small chunks of the sparse planes
+// cost little.
+__global__ __launch_bounds__(256) void chunk_bbox_kernel(const int64_t *__restrict__ counters,
+                                                         const uint32_t *__restrict__ plane_cfirst,
+                                                         int32_t nplanes,
+                                                         const PlaneLayout *__restrict__ planes,
+                                                         const RecMeta *__restrict__ smeta,
+                                                         Chunk *__restrict__ chunks) {
+    const int64_t nchunks = counters[2];
+    const int lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
+                                                          (threadIdx.x >> 6));
+    for (uint32_t c = first; (int64_t)c < nchunks; c += waves) {
+        const Chunk ch = chunks[c];
+        // plane of chunk c: the last p with plane_cfirst[p] <= c
+        int lo = 0, hi = nplanes - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (plane_cfirst[mid] <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        const PlaneLayout pl = planes[lo];
+        const uint32_t local = ch.bucket - (uint32_t)pl.base;
+        const uint32_t tu0 = (local % (uint32_t)pl.ntu) << pl.log2T;
+        const uint32_t tv0 = (local / (uint32_t)pl.ntu) << pl.log2T;
+        uint32_t umin = 0xffffffffu, umax = 0, vmin = 0xffffffffu, vmax = 0;
+        for (uint32_t i = lane; i < ch.len; i += 64) {
+            const RecMeta m = smeta[ch.start + i];
+            const uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
+            umin = min(umin, du);
+            umax = max(umax, du);
+            vmin = min(vmin, dv);
+            vmax = max(vmax, dv);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            umin = min(umin, (uint32_t)__shfl_xor((int)umin, off));
+            umax = max(umax, (uint32_t)__shfl_xor((int)umax, off));
+            vmin = min(vmin, (uint32_t)__shfl_xor((int)vmin, off));
+            vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off));
+        }
+        if (lane == 0) chunks[c].bbox = umin | (umax << 8) | (vmin << 16) | (vmax << 24);
     }
 }
 
@@ -572,16 +562,27 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
     hipLaunchKernelGGL(plane_ranges_kernel, dim3(1), dim3(256), 0, stream, np, P.d_planes, nb,
                        cstart, sums + nscan, P.plane_cfirst, P.counters);
     {
-        // as many workgroups as fit at once; they draw chunks from counters[4]
+        // cell sort of the chunks of supports up to 16 (planes before p_split),
+        // then the bounding box of every chunk
+        int p_split = np;
+        for (int p = 0; p < np; ++p)
+            if (P.planes[p].cls >= 2) {
+                p_split = p;
+                break;
+            }
         int dev = 0, cus = 0, per = 0;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, chunk_sort_kernel, 256, 0) !=
             hipSuccess)
             per = 1;
-        hipLaunchKernelGGL(chunk_sort_kernel, dim3(std::max(1, per) * std::max(1, cus)), dim3(256),
-                           0, stream, P.counters, P.d_planes, np, P.chunks, P.smeta, P.sperm,
-                           reinterpret_cast<uint32_t *>(P.counters + 4));
+        if (p_split > 0)
+            hipLaunchKernelGGL(chunk_sort_kernel, dim3(std::max(1, per) * std::max(1, cus)),
+                               dim3(256), 0, stream, P.plane_cfirst, p_split, P.d_planes,
+                               P.chunks, P.smeta, P.sperm);
+        hipLaunchKernelGGL(chunk_bbox_kernel, dim3(grid_blocks(P.max_chunks * 64, 256)),
+                           dim3(256), 0, stream, P.counters, P.plane_cfirst, np, P.d_planes,
+                           P.smeta, P.chunks);
     }
     {
         const int sep = P.kind == MG_KERNEL_SEPARABLE ? 1 : 0;
