@@ -136,7 +136,8 @@ DevGeom make_geom(const mg_grid_desc *g, const mg_kernel_desc *k) {
 }
 
 void free_plan_memory(PlanState &P, hipStream_t s) {
-    void *ptrs[] = {P.taps, P.smeta, P.sperm, P.chunks, P.plane_cfirst, P.d_planes, P.counters};
+    void *ptrs[] = {P.taps,          P.smeta, P.sperm,        P.chunks,   P.plane_cfirst,
+                    P.bucket_cfirst, P.units, P.group_nunits, P.d_planes, P.counters};
     for (void *p : ptrs) {
         if (!p) continue;
         if (P.stream_ordered) hipFreeAsync(p, s);
@@ -147,6 +148,9 @@ void free_plan_memory(PlanState &P, hipStream_t s) {
     P.sperm = nullptr;
     P.chunks = nullptr;
     P.plane_cfirst = nullptr;
+    P.bucket_cfirst = nullptr;
+    P.units = nullptr;
+    P.group_nunits = nullptr;
     P.d_planes = nullptr;
     P.counters = nullptr;
 }
@@ -167,7 +171,6 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
     P.R = (int32_t)std::max<int64_t>(64, std::min<int64_t>(2048, R));
     const int lds = lds_limit_bytes();
     P.planes.resize(P.nplanes_eff);
-    int64_t base = 0;
     for (int p = 0; p < P.nplanes_eff; ++p) {
         PlaneLayout &L = P.planes[p];
         L.S = (k->kind == MG_KERNEL_WPROJ) ? k->plane_support[p] : k->support;
@@ -176,11 +179,28 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
         L.log2T = ilog2(L.T);
         L.ntu = (g->nu + L.T - 1) / L.T;
         L.ntv = (g->nv + L.T - 1) / L.T;
-        L.base = base;
         L.rowlen = g->beta * L.S + 1;
         L.tap_off = (k->kind == MG_KERNEL_WPROJ) ? (uint32_t)k->plane_offset[p] : 0u;
         L.wmax = 0.0f;   // filled on the device by the plan build
-        base += (int64_t)L.ntu * L.ntv;
+    }
+    // groups: runs of consecutive planes of one class above 1 share their
+    // buckets tile-major; every other plane is a group of its own
+    int64_t base = 0;
+    for (int p0 = 0; p0 < P.nplanes_eff;) {
+        int p1 = p0 + 1;
+        if (P.planes[p0].cls >= 2)
+            while (p1 < P.nplanes_eff && P.planes[p1].cls == P.planes[p0].cls) ++p1;
+        int smax = 0;
+        for (int p = p0; p < p1; ++p) smax = std::max(smax, P.planes[p].S);
+        for (int p = p0; p < p1; ++p) {
+            PlaneLayout &L = P.planes[p];
+            L.base = base;
+            L.grp_first = p0;
+            L.grp_n = p1 - p0;
+            L.grp_smax = smax;
+        }
+        base += (int64_t)P.planes[p0].ntu * P.planes[p0].ntv * (p1 - p0);
+        p0 = p1;
     }
     P.nbuckets = base;
     if (base >= 0x7fffffffLL) return set_error(MG_EUNSUPPORTED, "too many (plane, tile) buckets");

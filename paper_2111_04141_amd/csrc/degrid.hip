@@ -142,12 +142,14 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
          c = c_begin + next_chunk_dg(queue, &s_next)) {
         const Chunk ch = chunks[c];
         while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
-        const PlaneLayout pl = planes[p];
+        int pc;
+        uint32_t tile;
+        bucket_plane_tile(planes[p], ch.bucket, &pc, &tile);
+        const PlaneLayout pl = planes[pc];
         const int S = pl.S;
-        const uint32_t local = ch.bucket - (uint32_t)pl.base;
         const int Tm = pl.T - 1;
-        const int cu0 = (int)((local % (uint32_t)pl.ntu) << pl.log2T);
-        const int cv0 = (int)((local / (uint32_t)pl.ntu) << pl.log2T);
+        const int cu0 = (int)((tile % (uint32_t)pl.ntu) << pl.log2T);
+        const int cv0 = (int)((tile / (uint32_t)pl.ntu) << pl.log2T);
         const int nbx = (pl.T + S - 1 + 7) >> 3;
         const int nblocks = nbx * nbx;
         const uint32_t rowlen = (uint32_t)pl.rowlen;
@@ -332,11 +334,13 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
          c = c_begin + next_chunk_dg(queue, &s_next)) {
         const Chunk ch = chunks[c];
         while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
-        const PlaneLayout pl = planes[p];
+        int pc;
+        uint32_t tile;
+        bucket_plane_tile(planes[p], ch.bucket, &pc, &tile);
+        const PlaneLayout pl = planes[pc];
         const int S = pl.S;
-        const uint32_t local = ch.bucket - (uint32_t)pl.base;
-        const int cu0 = (int)(((local % (uint32_t)pl.ntu) << pl.log2T) + (ch.bbox & 0xffu));
-        const int cv0 = (int)(((local / (uint32_t)pl.ntu) << pl.log2T) + ((ch.bbox >> 16) & 0xffu));
+        const int cu0 = (int)(((tile % (uint32_t)pl.ntu) << pl.log2T) + (ch.bbox & 0xffu));
+        const int cv0 = (int)(((tile / (uint32_t)pl.ntu) << pl.log2T) + ((ch.bbox >> 16) & 0xffu));
         const int RW = (int)((ch.bbox >> 8) & 0xffu) - (int)(ch.bbox & 0xffu) + S;
         const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
         const int rowlen = pl.rowlen;

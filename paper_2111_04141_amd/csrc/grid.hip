@@ -132,6 +132,8 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
         while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
         const PlaneLayout pl = planes[p];
         const int S = pl.S;
+        // planes of the window classes form groups of one: the bucket's
+        // offset from the plane's base is its tile
         const uint32_t local = ch.bucket - (uint32_t)pl.base;
         const uint32_t tu0 = (local % (uint32_t)pl.ntu) << pl.log2T;
         const uint32_t tv0 = (local / (uint32_t)pl.ntu) << pl.log2T;
@@ -387,11 +389,15 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
 // planes of large support, this replaces the moving window's per-record
 // slot commits; the lane utilisation is S^2 over the overlapped blocks'
 // cells, about (S/(S+7))^2.
+// W-projection instances are held to 128 VGPRs (four waves per SIMD), which
+// they fit without spilling; separable ones need a few more registers.
 template <int KMAX, int NW, bool SEP, typename TapT>
-__global__ __launch_bounds__(NW * kWave) void grid_block_kernel(
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(SEP ? 1 : 4)))
+void grid_block_kernel(
     const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
-    const uint32_t *__restrict__ plane_cfirst, const PlaneLayout *__restrict__ planes,
+    const uint32_t *__restrict__ bucket_cfirst, const uint2 *__restrict__ units,
+    const uint32_t *__restrict__ group_nunits, const PlaneLayout *__restrict__ planes,
     const uint32_t *__restrict__ nonfinite, uint32_t *__restrict__ queue, GridParams prm) {
     // Lanes outside a footprint normally multiply a zero tap, which adds
     // nothing; a non-finite visibility would turn that into NaN, so calls
@@ -403,180 +409,203 @@ __global__ __launch_bounds__(NW * kWave) void grid_block_kernel(
     const int lu = lane & 7, lv = lane >> 3;
     const int npol = prm.npol;
     const int beta = prm.beta;
-    const uint32_t c_begin = plane_cfirst[prm.p_lo];
-    const uint32_t c_end = plane_cfirst[prm.p_hi];
     const char *tbase = reinterpret_cast<const char *>(taps);
 
-    int p = prm.p_lo;   // chunks come in increasing order: the plane only moves forward
-    __shared__ uint32_t s_next;
-    for (uint32_t c = c_begin + next_chunk(queue, &s_next); c < c_end;
-         c = c_begin + next_chunk(queue, &s_next)) {
-        const Chunk ch = chunks[c];
-        while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
-        const PlaneLayout pl = planes[p];
-        const int S = pl.S;
-        const uint32_t local = ch.bucket - (uint32_t)pl.base;
-        const int Tm = pl.T - 1;
-        const int cu0 = (int)((local % (uint32_t)pl.ntu) << pl.log2T);   // region = tile + halo
-        const int cv0 = (int)((local / (uint32_t)pl.ntu) << pl.log2T);
-        const int nbx = (pl.T + S - 1 + 7) >> 3;
-        const int nblocks = nbx * nbx;
-        const uint32_t rowlen = (uint32_t)pl.rowlen;
+    // The launch covers one plane group.  Its work comes in units: chunks of
+    // one tile (in any of the group's planes), accumulated together in
+    // registers and committed once per unit over the tile's region (the
+    // tile plus the group's largest halo).
+    const PlaneLayout g0 = planes[prm.p_lo];
+    const int Tm = g0.T - 1;
+    const uint32_t ntu = (uint32_t)g0.ntu;
+    const uint32_t gn = (uint32_t)g0.grp_n;
+    const uint32_t gbase = (uint32_t)g0.base;
+    const uint32_t nunits = group_nunits[prm.p_lo];
+    const uint2 *gunits = units + bucket_cfirst[gbase];
+    const int nbx = (g0.T + g0.grp_smax - 1 + 7) >> 3;
+    const int nblocks = nbx * nbx;
 
-        // lane k < KMAX: origin of the wave's block k, for the overlap tests
-        uint32_t blo_u = 0xffff0000u, blo_v = 0xffff0000u;   // never overlaps
-        {
-            const int b = lane * NW + wave;
-            if (lane < KMAX && b < nblocks) {
-                blo_u = (uint32_t)((b % nbx) << 3);
-                blo_v = (uint32_t)((b / nbx) << 3);
-            }
-        }
-        // per block: this lane's cell (packed u | v << 16, region-relative)
-        // and its tap offset in bytes relative to the footprint's first tap
-        uint32_t cuv[KMAX], voff[KMAX], voffv[KMAX];
-        float acc[KMAX][8];
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int b = k * NW + wave;
-            const uint32_t cu = (uint32_t)(((b % nbx) << 3) + lu);
-            const uint32_t cv = (uint32_t)(((b / nbx) << 3) + lv);
-            cuv[k] = cu | (cv << 16);
-            if constexpr (SEP) {
-                voff[k] = cu * (uint32_t)beta * kElem;
-                voffv[k] = cv * (uint32_t)beta * kElem;
-            } else {
-                voff[k] = (cv * rowlen + cu) * (uint32_t)beta * kElem;
-                voffv[k] = 0u;
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-        }
-        uint32_t touched = 0;
-
-        auto visit = [&](const RecMeta m, const RecVis &f, auto exact_t) {
-            constexpr bool EXACT = decltype(exact_t)::value;
-            // footprint origin relative to the region
-            const uint32_t a = meta_ku(m) & (uint32_t)Tm;
-            const uint32_t bq = meta_kv(m) & (uint32_t)Tm;
-            // block [lo, lo+7] overlaps [a, a+S-1] iff lo + 7 - a in [0, S+6];
-            // it lies inside iff lo - a in [0, S-8]
-            const uint32_t hit = (uint32_t)__ballot((blo_u + 7u - a <= (uint32_t)(S + 6)) &&
-                                                    (blo_v + 7u - bq <= (uint32_t)(S + 6)));
-            const uint32_t full = (uint32_t)__ballot((blo_u - a <= (uint32_t)(S - 8)) &&
-                                                     (blo_v - bq <= (uint32_t)(S - 8)));
-            touched |= hit;
-            const uint32_t ab = a | (bq << 16);
-            const char *tb;
-            const char *tbv = nullptr;
-            if constexpr (SEP) {
-                tb = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a * beta) * (int64_t)kElem;
-                tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq * beta) * (int64_t)kElem;
-            } else {
-                tb = tbase + ((int64_t)m.toff - (int64_t)(bq * rowlen + a) * beta) * (int64_t)kElem;
-            }
-            // tap of lane's cell in block k (uniform base + 32-bit lane offset)
-            auto tap = [&](const int k) {
-                uint32_t o = voff[k];
-                asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
-                if constexpr (SEP) {
-                    uint32_t ov = voffv[k];
-                    asm volatile("" : "+v"(ov));
-                    const float t = TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
-                                    TapTraits<TapT>::real((const TapT *)(tbv + ov), 0);
-                    return make_float2(t, 0.0f);
-                } else {
-                    return TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
-                }
-            };
-            auto madd = [&](const int k, const float2 w) {
-                if constexpr (SEP)
-                    fma_real(acc[k], w.x, f);
-                else
-                    fma_complex(acc[k], w, f);
-            };
-            if constexpr (EXACT) {
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (!((hit >> k) & 1u)) continue;
-                    const uint32_t d = cuv[k] - ab;   // a borrow only where du < 0
-                    if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S) madd(k, tap(k));
-                }
-            } else {
-                // all tap loads of the record first, then the multiply-adds;
-                // lanes outside the footprint keep a zero tap (one vector
-                // test per overlapped block, no separate path for blocks
-                // inside the footprint)
-                float2 w[KMAX];
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    w[k] = make_float2(0.0f, 0.0f);
-                    if (!((hit >> k) & 1u)) continue;
-                    const uint32_t d = cuv[k] - ab;
-                    if (max(d & 0xffffu, d >> 16) < (uint32_t)S) w[k] = tap(k);
-                }
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    if ((hit >> k) & 1u) madd(k, w[k]);
-            }
-        };
-
-        auto records = [&](auto exact_t) {
-            const uint32_t rb = ch.start, re = ch.start + ch.len;
-            RecMeta nm[kBatch];
-            float4 na4[kBatch], nb4[kBatch];
-            // the record arrays are padded by kBatch entries, so a batch may
-            // run past the chunk's end (those records are not used)
-            const RecMeta *pm = smeta + rb;
-            const float4 *pv = svis + 2 * (size_t)rb;
-            auto load_batch = [&]() {
-#pragma unroll
-                for (int i = 0; i < kBatch; ++i) {
-                    nm[i] = pm[i];
-                    na4[i] = pv[2 * i];
-                    nb4[i] = pv[2 * i + 1];
-                }
-                pm += kBatch;
-                pv += 2 * kBatch;
-            };
-            load_batch();
-            for (uint32_t r = rb; r < re; r += kBatch) {
-                RecMeta mm[kBatch];
-                float4 va4[kBatch], vb4[kBatch];
-#pragma unroll
-                for (int i = 0; i < kBatch; ++i) {
-                    mm[i] = nm[i];
-                    va4[i] = na4[i];
-                    vb4[i] = nb4[i];
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                load_batch();
-#pragma unroll
-                for (int i = 0; i < kBatch; ++i)
-                    if (r + (uint32_t)i < re) visit(mm[i], unpack_vis(va4[i], vb4[i]), exact_t);
-            }
-        };
-        if (exact)
-            records(std::true_type{});
-        else
-            records(std::false_type{});
-
-        // commit: one float atomic per touched cell, polarisation and part
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            if (!((touched >> k) & 1u)) continue;
-            const int u = cu0 + (int)(cuv[k] & 0xffffu), v = cv0 + (int)(cuv[k] >> 16);
-            if (u >= prm.nu || v >= prm.nv) continue;
-#pragma unroll
-            for (int pol = 0; pol < 4; ++pol) {
-                if (pol < npol && (acc[k][2 * pol] != 0.0f || acc[k][2 * pol + 1] != 0.0f)) {
-                    float *dst = grid + 2 * (((int64_t)pol * prm.nv + v) * prm.nu + u);
-                    unsafeAtomicAdd(dst, acc[k][2 * pol]);
-                    unsafeAtomicAdd(dst + 1, acc[k][2 * pol + 1]);
-                }
-            }
+    // lane k < KMAX: origin of the wave's block k, for the overlap tests
+    uint32_t blo_u = 0xffff0000u, blo_v = 0xffff0000u;   // never overlaps
+    {
+        const int b = lane * NW + wave;
+        if (lane < KMAX && b < nblocks) {
+            blo_u = (uint32_t)((b % nbx) << 3);
+            blo_v = (uint32_t)((b / nbx) << 3);
         }
     }
+    // per block: this lane's cell (packed u | v << 16, region-relative)
+    uint32_t cuv[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int b = k * NW + wave;
+        cuv[k] = (uint32_t)(((b % nbx) << 3) + lu) | ((uint32_t)(((b / nbx) << 3) + lv) << 16);
+    }
+
+    __shared__ uint32_t s_next;
+    // the exact or fast path is chosen once per launch, outside the unit loop
+    auto work = [&](auto exact_t) {
+        for (uint32_t i = next_chunk(queue, &s_next); i < nunits; i = next_chunk(queue, &s_next)) {
+            const uint2 un = gunits[i];
+            const uint32_t c0 = un.x, c1 = un.x + un.y;
+            const uint32_t t = (chunks[c0].bucket - gbase) / gn;
+            const int cu0 = (int)((t % ntu) << g0.log2T);
+            const int cv0 = (int)((t / ntu) << g0.log2T);
+
+            float acc[KMAX][8];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
+            uint32_t touched = 0;
+
+            for (uint32_t c = c0; c < c1; ++c) {
+                const Chunk ch = chunks[c];
+                const int p = g0.grp_first + (int)((ch.bucket - gbase) % gn);
+                const PlaneLayout pl = planes[p];
+                const int S = pl.S;
+                const uint32_t rowlen = (uint32_t)pl.rowlen;
+                // this lane's tap offset in each block, in bytes relative to
+                // the footprint's first tap
+                uint32_t voff[KMAX], voffv[KMAX];
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    const uint32_t cu = cuv[k] & 0xffffu, cv = cuv[k] >> 16;
+                    if constexpr (SEP) {
+                        voff[k] = cu * (uint32_t)beta * kElem;
+                        voffv[k] = cv * (uint32_t)beta * kElem;
+                    } else {
+                        voff[k] = (cv * rowlen + cu) * (uint32_t)beta * kElem;
+                        voffv[k] = 0u;
+                    }
+                }
+
+                auto visit = [&](const RecMeta m, const RecVis &f, auto exact_t) {
+                    constexpr bool EXACT = decltype(exact_t)::value;
+                    // footprint origin relative to the region
+                    const uint32_t a = meta_ku(m) & (uint32_t)Tm;
+                    const uint32_t bq = meta_kv(m) & (uint32_t)Tm;
+                    // block [lo, lo+7] overlaps [a, a+S-1] iff lo + 7 - a in
+                    // [0, S+6]; it lies inside iff lo - a in [0, S-8]
+                    const uint32_t hit = (uint32_t)__ballot((blo_u + 7u - a <= (uint32_t)(S + 6)) &&
+                                                            (blo_v + 7u - bq <= (uint32_t)(S + 6)));
+                    const uint32_t full = (uint32_t)__ballot((blo_u - a <= (uint32_t)(S - 8)) &&
+                                                             (blo_v - bq <= (uint32_t)(S - 8)));
+                    touched |= hit;
+                    const uint32_t ab = a | (bq << 16);
+                    const char *tb_;
+                    const char *tbv = nullptr;
+                    if constexpr (SEP) {
+                        tb_ = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a * beta) * (int64_t)kElem;
+                        tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq * beta) * (int64_t)kElem;
+                    } else {
+                        tb_ = tbase + ((int64_t)m.toff - (int64_t)(bq * rowlen + a) * beta) * (int64_t)kElem;
+                    }
+                    // tap of lane's cell in block k (uniform base + 32-bit lane offset)
+                    auto tap = [&](const int k) {
+                        uint32_t o = voff[k];
+                        asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+                        if constexpr (SEP) {
+                            uint32_t ov = voffv[k];
+                            asm volatile("" : "+v"(ov));
+                            const float t_ = TapTraits<TapT>::real((const TapT *)(tb_ + o), 0) *
+                                             TapTraits<TapT>::real((const TapT *)(tbv + ov), 0);
+                            return make_float2(t_, 0.0f);
+                        } else {
+                            return TapTraits<TapT>::cplx((const TapT *)(tb_ + o), 0);
+                        }
+                    };
+                    auto madd = [&](const int k, const float2 w) {
+                        if constexpr (SEP)
+                            fma_real(acc[k], w.x, f);
+                        else
+                            fma_complex(acc[k], w, f);
+                    };
+                    if constexpr (EXACT) {
+#pragma unroll
+                        for (int k = 0; k < KMAX; ++k) {
+                            if (!((hit >> k) & 1u)) continue;
+                            const uint32_t d = cuv[k] - ab;   // a borrow only where du < 0
+                            if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S)
+                                madd(k, tap(k));
+                        }
+                    } else {
+                        // all tap loads of the record first, then the
+                        // multiply-adds; lanes outside the footprint keep a
+                        // zero tap (one vector test per overlapped block)
+                        float2 w[KMAX];
+#pragma unroll
+                        for (int k = 0; k < KMAX; ++k) {
+                            w[k] = make_float2(0.0f, 0.0f);
+                            if (!((hit >> k) & 1u)) continue;
+                            const uint32_t d = cuv[k] - ab;
+                            if (max(d & 0xffffu, d >> 16) < (uint32_t)S) w[k] = tap(k);
+                        }
+#pragma unroll
+                        for (int k = 0; k < KMAX; ++k)
+                            if ((hit >> k) & 1u) madd(k, w[k]);
+                    }
+                };
+
+                auto records = [&](auto exact_t) {
+                    const uint32_t rb = ch.start, re = ch.start + ch.len;
+                    RecMeta nm[kBatch];
+                    float4 na4[kBatch], nb4[kBatch];
+                    // the record arrays are padded by kBatch entries, so a
+                    // batch may run past the chunk's end (those are not used)
+                    const RecMeta *pm = smeta + rb;
+                    const float4 *pv = svis + 2 * (size_t)rb;
+                    auto load_batch = [&]() {
+#pragma unroll
+                        for (int i = 0; i < kBatch; ++i) {
+                            nm[i] = pm[i];
+                            na4[i] = pv[2 * i];
+                            nb4[i] = pv[2 * i + 1];
+                        }
+                        pm += kBatch;
+                        pv += 2 * kBatch;
+                    };
+                    load_batch();
+                    for (uint32_t r = rb; r < re; r += kBatch) {
+                        RecMeta mm[kBatch];
+                        float4 va4[kBatch], vb4[kBatch];
+#pragma unroll
+                        for (int i = 0; i < kBatch; ++i) {
+                            mm[i] = nm[i];
+                            va4[i] = na4[i];
+                            vb4[i] = nb4[i];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                        load_batch();
+#pragma unroll
+                        for (int i = 0; i < kBatch; ++i)
+                            if (r + (uint32_t)i < re) visit(mm[i], unpack_vis(va4[i], vb4[i]), exact_t);
+                    }
+                };
+                records(exact_t);
+            }
+
+            // commit: one float atomic per touched cell, polarisation and part
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (!((touched >> k) & 1u)) continue;
+                const int u = cu0 + (int)(cuv[k] & 0xffffu), v = cv0 + (int)(cuv[k] >> 16);
+                if (u >= prm.nu || v >= prm.nv) continue;
+#pragma unroll
+                for (int pol = 0; pol < 4; ++pol) {
+                    if (pol < npol && (acc[k][2 * pol] != 0.0f || acc[k][2 * pol + 1] != 0.0f)) {
+                        float *dst = grid + 2 * (((int64_t)pol * prm.nv + v) * prm.nu + u);
+                        unsafeAtomicAdd(dst, acc[k][2 * pol]);
+                        unsafeAtomicAdd(dst + 1, acc[k][2 * pol + 1]);
+                    }
+                }
+            }
+        }
+    };
+    if (exact)
+        work(std::true_type{});
+    else
+        work(std::false_type{});
 }
 
 // Gathers visibilities into sorted order, padded to 4 polarisations.
@@ -613,6 +642,9 @@ struct GridPtrs {
     const void *taps;
     const Chunk *chunks;
     const uint32_t *plane_cfirst;
+    const uint32_t *bucket_cfirst;
+    const uint2 *units;
+    const uint32_t *group_nunits;
     const PlaneLayout *planes;
     const uint32_t *nonfinite;   // set by the gather if a visibility is not finite
     uint32_t *queue;             // this launch's chunk counter
@@ -643,7 +675,8 @@ void launch_block(const GridPtrs &a, const GridParams &prm, hipStream_t stream) 
     auto kern = grid_block_kernel<KMAX, NW, SEP, TapT>;
     hipLaunchKernelGGL(kern, dim3(resident_groups(kern, NW * kWave, 0)), dim3(NW * kWave), 0,
                        stream, a.smeta, a.svis, a.grid, (const TapT *)a.taps, a.chunks,
-                       a.plane_cfirst, a.planes, a.nonfinite, a.queue, prm);
+                       a.bucket_cfirst, a.units, a.group_nunits, a.planes, a.nonfinite, a.queue,
+                       prm);
 }
 
 // Largest region, in 8 x 8 blocks, of a chunk of tile side T and support S.
@@ -705,8 +738,8 @@ mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream
                            P.counters, P.nrec, P.sperm, (const float2 *)vis, P.geom.npol, svis,
                            nonfinite);
     }
-    GridPtrs a{P.smeta, svis, (float *)grid, P.taps, P.chunks, P.plane_cfirst, P.d_planes,
-               nonfinite, nullptr};
+    GridPtrs a{P.smeta,          svis,    (float *)grid,  P.taps,     P.chunks,  P.plane_cfirst,
+               P.bucket_cfirst, P.units, P.group_nunits, P.d_planes, nonfinite, nullptr};
     GridParams prm{P.geom.npol, P.geom.nu, P.geom.nv, P.geom.beta, 0, 0};
     const bool sep = P.kind == MG_KERNEL_SEPARABLE;
     // one launch per run of consecutive planes of the same class

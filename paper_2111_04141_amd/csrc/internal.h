@@ -9,20 +9,36 @@
 namespace mg {
 
 // Per-plane layout of the record buckets and the kernel each plane runs.
-//   Buckets are (plane, uv tile) pairs, numbered plane-major.  A tile is
-//   T x T cells; a record belongs to the tile holding its footprint's first
-//   cell (k_lo_u, k_lo_v).
+//   Buckets are (plane, uv tile) pairs.  A tile is T x T cells; a record
+//   belongs to the tile holding its footprint's first cell (k_lo_u, k_lo_v).
+//   Planes are gathered into groups: a maximal run of consecutive planes of
+//   one support class above 16 forms one group, every other plane is a group
+//   of its own.  The buckets of a group are numbered tile-major,
+//     bucket = base + tile * grp_n + (plane - grp_first),
+//   so the records of one tile in all the group's planes are contiguous and
+//   the output-stationary kernels commit each tile's region once.
 struct PlaneLayout {
     int32_t S;          // support of the plane
     int32_t T;          // tile side in cells (8, 16 or 32)
     int32_t log2T;
     int32_t ntu, ntv;   // tiles per axis
-    int64_t base;       // first bucket of the plane
+    int64_t base;       // first bucket of the plane's group
     int32_t cls;        // gridder class (see grid.hip)
     int32_t rowlen;     // beta * S + 1: entries per table row
     uint32_t tap_off;   // first table element of the plane
     float wmax;         // bound on |re|, |im| of one tap weight of the plane
+    int32_t grp_first;  // first plane of the group
+    int32_t grp_n;      // planes in the group
+    int32_t grp_smax;   // largest support in the group
 };
+
+// Plane and tile of a bucket, given the layout of any plane of its group.
+__host__ __device__ inline void bucket_plane_tile(const PlaneLayout &g, uint32_t bucket,
+                                                  int *plane, uint32_t *tile) {
+    const uint32_t local = bucket - (uint32_t)g.base;
+    *plane = g.grp_first + (int)(local % (uint32_t)g.grp_n);
+    *tile = local / (uint32_t)g.grp_n;
+}
 
 // One chunk: up to R records of one bucket, cell-sorted inside the chunk.
 //   bbox: k_lo ranges of the chunk's records relative to the tile origin,
@@ -50,7 +66,10 @@ struct PlanState {
     RecMeta *smeta = nullptr;         // [nrec] sorted (first nvalid valid)
     uint32_t *sperm = nullptr;        // [nrec] original record index
     Chunk *chunks = nullptr;          // [max_chunks]
-    uint32_t *plane_cfirst = nullptr; // [nplanes_eff + 1] first chunk of each plane
+    uint32_t *plane_cfirst = nullptr; // [nplanes_eff + 1] first chunk of each plane's group
+    uint32_t *bucket_cfirst = nullptr; // [nbuckets + 1] first chunk of each bucket
+    uint2 *units = nullptr;           // [max_chunks] units of the plane groups (see plan.hip)
+    uint32_t *group_nunits = nullptr; // [nplanes_eff] unit count, at each group's first plane
     PlaneLayout *d_planes = nullptr;  // [nplanes_eff]
     int64_t *counters = nullptr;      // [0] skipped, [1] valid, [2] chunks, [3], [4] scratch
     size_t bytes = 0;

@@ -75,10 +75,11 @@ __global__ __launch_bounds__(256) void index_bucket_kernel(
         if (in) ix = index_record<T>(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2]);
         uint32_t b = kInvalidBucket;
         if (ix.valid) {
-            const PlaneLayout pl = planes[ix.plane < 0 ? 0 : ix.plane];
+            const int p = ix.plane < 0 ? 0 : ix.plane;
+            const PlaneLayout pl = planes[p];
             uint32_t tu = (uint32_t)ix.ku >> pl.log2T;
             uint32_t tv = (uint32_t)ix.kv >> pl.log2T;
-            b = (uint32_t)(pl.base + (int64_t)tv * pl.ntu + tu);
+            b = (uint32_t)(pl.base + ((int64_t)tv * pl.ntu + tu) * pl.grp_n + (p - pl.grp_first));
         } else if (in) {
             ++skipped;
         }
@@ -241,17 +242,82 @@ __global__ __launch_bounds__(256) void chunk_list_kernel(int64_t nb, uint32_t R,
 // counters[1] = valid records, counters[2] = chunks (counters[3] counts the
 // skipped records placed by the scatter).
 __global__ void plane_ranges_kernel(int32_t nplanes, const PlaneLayout *__restrict__ planes,
-                                    int64_t nb, const uint32_t *__restrict__ cstart,
+                                    int64_t nb, uint32_t *__restrict__ cstart,
                                     const uint2 *__restrict__ total,
                                     uint32_t *__restrict__ plane_cfirst,
                                     int64_t *__restrict__ counters) {
-    int p = threadIdx.x;
-    if (p < nplanes) plane_cfirst[p] = (planes[p].base < nb) ? cstart[planes[p].base] : total->y;
-    if (p == 0) {
+    for (int p = threadIdx.x; p < nplanes; p += blockDim.x)
+        plane_cfirst[p] = (planes[p].base < nb) ? cstart[planes[p].base] : total->y;
+    if (threadIdx.x == 0) {
         plane_cfirst[nplanes] = total->y;
+        cstart[nb] = total->y;   // end of the last bucket's chunks
         counters[1] = total->x;
         counters[2] = total->y;
     }
+}
+
+// ---------------------------------------------------------------------------
+// units of a plane group (supports above 16): the chunks of one tile, over
+// all planes of the group, split greedily into runs of at most `cap`
+// records (a chunk is never split).  The block gridder takes a unit at a
+// time and commits the tile's region once per unit rather than once per
+// chunk.  units[first chunk of the group + k] = (first chunk, chunk count)
+// of the group's unit k; group_nunits[g] = unit count (cleared beforehand).
+// A wave's units are consecutive and in tile order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void unit_list_kernel(const PlaneLayout *__restrict__ planes,
+                                                        int32_t g,
+                                                        const uint32_t *__restrict__ bucket_cfirst,
+                                                        const Chunk *__restrict__ chunks,
+                                                        uint32_t cap, uint2 *__restrict__ units,
+                                                        uint32_t *__restrict__ group_nunits) {
+    const PlaneLayout pl = planes[g];
+    const uint32_t ntiles = (uint32_t)pl.ntu * (uint32_t)pl.ntv;
+    const uint32_t n = (uint32_t)pl.grp_n;
+    const int64_t base = pl.base;
+    const int lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t cs = 0, ce = 0;
+    if (t < ntiles) {
+        cs = bucket_cfirst[base + (int64_t)t * n];
+        ce = bucket_cfirst[base + (int64_t)(t + 1) * n];
+    }
+    // pass 1: unit count of this tile (acc = cap opens a unit at the first chunk)
+    uint32_t cnt = 0;
+    for (uint32_t c = cs, acc = cap; c < ce; ++c) {
+        const uint32_t len = chunks[c].len;
+        if (acc + len > cap) {
+            ++cnt;
+            acc = len;
+        } else {
+            acc += len;
+        }
+    }
+    // wave prefix sum; one lane reserves the wave's units
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    const uint32_t wtotal = __shfl(incl, 63, 64);
+    uint32_t wbase = 0;
+    if (lane == 63 && wtotal) wbase = atomicAdd(&group_nunits[g], wtotal);
+    wbase = __shfl(wbase, 63, 64);
+    // pass 2: write them
+    uint2 *out = units + bucket_cfirst[base] + wbase + (incl - cnt);
+    uint32_t head = cs;
+    for (uint32_t c = cs, acc = cap; c < ce; ++c) {
+        const uint32_t len = chunks[c].len;
+        if (acc + len > cap) {
+            if (c > cs) *out++ = make_uint2(head, c - head);
+            head = c;
+            acc = len;
+        } else {
+            acc += len;
+        }
+    }
+    if (ce > cs) *out = make_uint2(head, ce - head);
 }
 
 // ---------------------------------------------------------------------------
@@ -279,10 +345,12 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restr
     for (uint32_t c = blockIdx.x; c < c_end; c += gridDim.x) {
         const Chunk ch = chunks[c];
         while (p + 1 < p_split && c >= plane_cfirst[p + 1]) ++p;
-        const PlaneLayout pl = planes[p];
-        const uint32_t local = ch.bucket - (uint32_t)pl.base;
-        const uint32_t tu0 = (local % (uint32_t)pl.ntu) << pl.log2T;
-        const uint32_t tv0 = (local / (uint32_t)pl.ntu) << pl.log2T;
+        int pp;
+        uint32_t tile;
+        bucket_plane_tile(planes[p], ch.bucket, &pp, &tile);
+        const PlaneLayout pl = planes[pp];
+        const uint32_t tu0 = (tile % (uint32_t)pl.ntu) << pl.log2T;
+        const uint32_t tv0 = (tile / (uint32_t)pl.ntu) << pl.log2T;
         const int ncell = pl.T * pl.T;
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) hist[i] = 0;
         __syncthreads();
@@ -347,10 +415,12 @@ __global__ __launch_bounds__(256) void chunk_bbox_kernel(const int64_t *__restri
             if (plane_cfirst[mid] <= c) lo = mid;
             else hi = mid - 1;
         }
-        const PlaneLayout pl = planes[lo];
-        const uint32_t local = ch.bucket - (uint32_t)pl.base;
-        const uint32_t tu0 = (local % (uint32_t)pl.ntu) << pl.log2T;
-        const uint32_t tv0 = (local / (uint32_t)pl.ntu) << pl.log2T;
+        int pp;
+        uint32_t tile;
+        bucket_plane_tile(planes[lo], ch.bucket, &pp, &tile);
+        const PlaneLayout pl = planes[pp];
+        const uint32_t tu0 = (tile % (uint32_t)pl.ntu) << pl.log2T;
+        const uint32_t tv0 = (tile / (uint32_t)pl.ntu) << pl.log2T;
         uint32_t umin = 0xffffffffu, umax = 0, vmin = 0xffffffffu, vmax = 0;
         for (uint32_t i = lane; i < ch.len; i += 64) {
             const RecMeta m = smeta[ch.start + i];
@@ -511,13 +581,16 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         (e = malloc_bytes(P, &P.sperm, sizeof(uint32_t) * (size_t)(nrec + 2), stream)) ||
         (e = malloc_bytes(P, &P.chunks, sizeof(Chunk) * (size_t)P.max_chunks, stream)) ||
         (e = malloc_bytes(P, &P.plane_cfirst, sizeof(uint32_t) * (size_t)(np + 1), stream)) ||
+        (e = malloc_bytes(P, &P.bucket_cfirst, sizeof(uint32_t) * (size_t)(nb + 1), stream)) ||
+        (e = malloc_bytes(P, &P.units, sizeof(uint2) * (size_t)P.max_chunks, stream)) ||
+        (e = malloc_bytes(P, &P.group_nunits, sizeof(uint32_t) * (size_t)np, stream)) ||
         (e = malloc_bytes(P, &P.d_planes, sizeof(PlaneLayout) * (size_t)np, stream)) ||
         (e = malloc_bytes(P, &P.counters, sizeof(int64_t) * 6, stream)))
         return set_error(MG_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
     // temporaries (stream-ordered)
     RecMeta *meta = nullptr;
-    uint32_t *bucket_of = nullptr, *hist = nullptr, *bstart = nullptr, *cursor = nullptr,
-             *cstart = nullptr;
+    uint32_t *bucket_of = nullptr, *hist = nullptr, *bstart = nullptr, *cursor = nullptr;
+    uint32_t *cstart = P.bucket_cfirst;   // kept: first chunk of each bucket
     uint2 *sums = nullptr;
     const int64_t nscan = (nb + kScanBlock - 1) / kScanBlock;
     auto tmp = [&](void **p, size_t bytes) { return hipMallocAsync(p, bytes, stream); };
@@ -526,7 +599,6 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         (e = tmp((void **)&hist, sizeof(uint32_t) * (size_t)nb)) ||
         (e = tmp((void **)&bstart, sizeof(uint32_t) * (size_t)nb)) ||
         (e = tmp((void **)&cursor, sizeof(uint32_t) * (size_t)nb)) ||
-        (e = tmp((void **)&cstart, sizeof(uint32_t) * (size_t)nb)) ||
         (e = tmp((void **)&sums, sizeof(uint2) * (size_t)(nscan + 1))))
         return set_error(MG_ENOMEM, std::string("plan scratch: ") + hipGetErrorString(e));
 
@@ -537,6 +609,8 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
                        (int64_t)12, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_blocks(nb, 256)), dim3(256), 0, stream, hist,
                        nb, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, stream, P.group_nunits,
+                       (int64_t)np, 0u);
     if (nrec > 0) {
         int g1 = grid_blocks(nrec, 256);
         if (uvw_dtype == MG_F32)
@@ -583,6 +657,15 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         hipLaunchKernelGGL(chunk_bbox_kernel, dim3(grid_blocks(P.max_chunks * 64, 256)),
                            dim3(256), 0, stream, P.counters, P.plane_cfirst, np, P.d_planes,
                            P.smeta, P.chunks);
+        // units of the plane groups of supports above 16
+        for (int p = 0; p < np; p += P.planes[p].grp_n) {
+            const PlaneLayout &L = P.planes[p];
+            if (L.cls < 2) continue;
+            const int64_t ntiles = (int64_t)L.ntu * L.ntv;
+            hipLaunchKernelGGL(unit_list_kernel, dim3(grid_blocks(ntiles, 256)), dim3(256), 0,
+                               stream, P.d_planes, p, P.bucket_cfirst, P.chunks, R, P.units,
+                               P.group_nunits);
+        }
     }
     {
         const int sep = P.kind == MG_KERNEL_SEPARABLE ? 1 : 0;
@@ -602,7 +685,6 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
     hipFreeAsync(hist, stream);
     hipFreeAsync(bstart, stream);
     hipFreeAsync(cursor, stream);
-    hipFreeAsync(cstart, stream);
     hipFreeAsync(sums, stream);
     if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("plan kernels: ") + hipGetErrorString(e));
     return MG_OK;
