@@ -19,16 +19,6 @@ namespace mg {
 namespace {
 thread_local std::string g_err;
 
-size_t dtype_size(mg_dtype d) {
-    switch (d) {
-    case MG_F32: return 4;
-    case MG_F64: return 8;
-    case MG_F16: return 2;
-    case MG_BF16: return 2;
-    }
-    return 0;
-}
-
 int ilog2(int x) {
     int l = 0;
     while ((1 << (l + 1)) <= x) ++l;
@@ -179,10 +169,20 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
         L.log2T = ilog2(L.T);
         L.ntu = (g->nu + L.T - 1) / L.T;
         L.ntv = (g->nv + L.T - 1) / L.T;
-        L.rowlen = g->beta * L.S + 1;
-        L.tap_off = (k->kind == MG_KERNEL_WPROJ) ? (uint32_t)k->plane_offset[p] : 0u;
         L.wmax = 0.0f;   // filled on the device by the plan build
     }
+    // the plan's tap table: planes one after another, phase-major
+    int64_t table = 0;
+    for (int p = 0; p < P.nplanes_eff; ++p) {
+        PlaneLayout &L = P.planes[p];
+        const int64_t w = (int64_t)g->beta * L.S;   // entries per axis
+        L.tap_off = (uint32_t)table;
+        L.src_off = (k->kind == MG_KERNEL_WPROJ) ? (uint32_t)k->plane_offset[p] : 0u;
+        P.geom.plane_offset[p] = table;
+        table += (k->kind == MG_KERNEL_WPROJ) ? w * w : w;
+    }
+    P.geom.conj_base = table;
+    if (table >= (1LL << 30)) return set_error(MG_EUNSUPPORTED, "tap table too large");
     // groups: runs of consecutive planes of one class above 1 share their
     // buckets tile-major; every other plane is a group of its own
     int64_t base = 0;
@@ -204,22 +204,8 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
     }
     P.nbuckets = base;
     if (base >= 0x7fffffffLL) return set_error(MG_EUNSUPPORTED, "too many (plane, tile) buckets");
-    // private copy of the tap table(s)
-    const size_t esz = dtype_size(k->tap_dtype) * (k->kind == MG_KERNEL_WPROJ ? 2 : 1);
-    // W-projection: the bank followed by its complex conjugate (the table of
-    // records with w < 0)
-    const size_t copies = (k->kind == MG_KERNEL_WPROJ) ? 2 : 1;
-    P.taps_bytes = esz * (size_t)k->ntaps * copies;
-    hipError_t e = stream_ordered ? hipMallocAsync(&P.taps, P.taps_bytes, stream)
-                                  : hipMalloc(&P.taps, P.taps_bytes);
-    if (e != hipSuccess) return set_error(MG_ENOMEM, "tap table allocation failed");
-    P.bytes += P.taps_bytes;
-    e = hipMemcpyAsync(P.taps, k->taps, esz * (size_t)k->ntaps, hipMemcpyDeviceToDevice, stream);
-    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("tap copy: ") + hipGetErrorString(e));
-    if (copies == 2) {
-        e = launch_conjugate_copy(P.taps, k->tap_dtype, k->ntaps, stream);
-        if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("tap conjugate: ") + hipGetErrorString(e));
-    }
+    const mg_status st = plan_taps(P, k->taps, table, stream);
+    if (st != MG_OK) return st;
     return plan_build(P, uvw, uvw_dtype, stream);
 }
 

@@ -24,19 +24,28 @@ struct DevGeom {
     int32_t support;         // separable S
     double inv_dw;
     int32_t plane_support[kMaxPlanes];
-    int64_t plane_offset[kMaxPlanes];   // element offset of plane p
+    int64_t plane_offset[kMaxPlanes];   // element offset of plane p (in the
+                                        // plan's table once a plan owns it)
     int64_t conj_base;                  // W-projection: element offset of the
                                         // conjugated copy of the bank
 };
 
+// A plan keeps its own copy of the tap table in phase-major order: for each
+// oversampling phase o (0 <= o < beta) the S taps o + 1 + j beta
+// (j = 0 .. S-1) of an axis are stored one after another, so the taps a
+// record needs are contiguous.  W-projection plane p: beta^2 blocks of
+// S x S complex taps, block (o_v, o_u) holding
+// bank[(o_v + 1 + j beta) * (beta S + 1) + (o_u + 1 + i beta)] at j S + i;
+// separable: beta blocks of S taps.
+//
 // Per-record packed index, 8 bytes:
 //   kuv  = k_lo_u | k_lo_v << 16
-//   toff = W-projection: table element of the record's first tap, i.e.
-//            plane offset + (o_v + 1) * rowlen + (o_u + 1), inside the
-//            conjugated copy of the bank for w < 0;
-//          separable: (o_u + 1) | (o_v + 1) << 16.
-// The gridders then address tap (i, j) as toff + (j * rowlen + i) * beta
-// (or toff_u + i * beta, toff_v + j * beta) without decoding anything else.
+//   toff = W-projection: element of the plan's table holding the record's
+//            first tap, plane offset + (o_v beta + o_u) S^2, inside the
+//            conjugated copy of the table for w < 0;
+//          separable: o_u S | (o_v S) << 16.
+// The gridders then address tap (i, j) as toff + j S + i (or toff_u + i,
+// toff_v + j) without decoding anything else.
 struct RecMeta {
     uint32_t kuv;
     uint32_t toff;
@@ -109,11 +118,10 @@ __device__ inline RecMeta pack_meta(const DevGeom &g, const RecIndex &r) {
     RecMeta m;
     m.kuv = (uint32_t)r.ku | ((uint32_t)r.kv << 16);
     if (g.nplanes == 0) {
-        m.toff = (uint32_t)(r.ou + 1) | ((uint32_t)(r.ov + 1) << 16);
+        m.toff = (uint32_t)(r.ou * r.S) | ((uint32_t)(r.ov * r.S) << 16);
     } else {
-        const int64_t rowlen = (int64_t)g.beta * r.S + 1;
         const int64_t p = r.plane < 0 ? 0 : r.plane;
-        m.toff = (uint32_t)(g.plane_offset[p] + (int64_t)(r.ov + 1) * rowlen + (r.ou + 1) +
+        m.toff = (uint32_t)(g.plane_offset[p] + ((int64_t)r.ov * g.beta + r.ou) * r.S * r.S +
                             (r.conj ? g.conj_base : 0));
     }
     return m;

@@ -129,7 +129,6 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
     const int lane = threadIdx.x & 63;
     const int lu = lane & 7, lv = lane >> 3;
     const int npol = prm.npol;
-    const int beta = prm.beta;
     const uint32_t c_begin = plane_cfirst[prm.p_lo];
     const uint32_t c_end = plane_cfirst[prm.p_hi];
     const char *tbase = reinterpret_cast<const char *>(taps);
@@ -152,7 +151,6 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
         const int cv0 = (int)((tile / (uint32_t)pl.ntu) << pl.log2T);
         const int nbx = (pl.T + S - 1 + 7) >> 3;
         const int nblocks = nbx * nbx;
-        const uint32_t rowlen = (uint32_t)pl.rowlen;
 
         uint32_t blo_u = 0xffff0000u, blo_v = 0xffff0000u;
         {
@@ -174,10 +172,10 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
             const uint32_t cv = (uint32_t)(((b / nbx) << 3) + lv);
             cuv[k] = cu | (cv << 16);
             if constexpr (SEP) {
-                voff[k] = cu * (uint32_t)beta * kElem;
-                voffv[k] = cv * (uint32_t)beta * kElem;
+                voff[k] = cu * kElem;
+                voffv[k] = cv * kElem;
             } else {
-                voff[k] = (cv * rowlen + cu) * (uint32_t)beta * kElem;
+                voff[k] = (cv * (uint32_t)S + cu) * kElem;
                 voffv[k] = 0u;
             }
             const int u = cu0 + (int)cu, v = cv0 + (int)cv;
@@ -209,10 +207,10 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
             const char *tb;
             const char *tbv = nullptr;
             if constexpr (SEP) {
-                tb = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a * beta) * (int64_t)kElem;
-                tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq * beta) * (int64_t)kElem;
+                tb = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a) * (int64_t)kElem;
+                tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq) * (int64_t)kElem;
             } else {
-                tb = tbase + ((int64_t)m.toff - (int64_t)(bq * rowlen + a) * beta) * (int64_t)kElem;
+                tb = tbase + ((int64_t)m.toff - (int64_t)(bq * (uint32_t)S + a)) * (int64_t)kElem;
             }
             auto tap = [&](const int k) {
                 uint32_t o = voff[k];
@@ -322,7 +320,6 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int npol = prm.npol;
-    const int beta = prm.beta;
     const uint32_t c_begin = plane_cfirst[prm.p_lo];
     const uint32_t c_end = plane_cfirst[prm.p_hi];
     const char *tbase = reinterpret_cast<const char *>(taps);
@@ -343,7 +340,6 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
         const int cv0 = (int)(((tile / (uint32_t)pl.ntu) << pl.log2T) + ((ch.bbox >> 16) & 0xffu));
         const int RW = (int)((ch.bbox >> 8) & 0xffu) - (int)(ch.bbox & 0xffu) + S;
         const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
-        const int rowlen = pl.rowlen;
 
         // stage the region (cells outside it are never read)
         for (int i = threadIdx.x; i < npol * RH * RW; i += kGroupThreads) {
@@ -370,10 +366,10 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
             const int j = q / S, i = q - (q / S) * S;
             lg[t] = j * kRowStride + i;
             if constexpr (SEP) {
-                lt[t] = (uint32_t)(i * beta) * kElem;
-                ltv[t] = (uint32_t)(j * beta) * kElem;
+                lt[t] = (uint32_t)i * kElem;
+                ltv[t] = (uint32_t)j * kElem;
             } else {
-                lt[t] = (uint32_t)((j * rowlen + i) * beta) * kElem;
+                lt[t] = (uint32_t)(j * S + i) * kElem;
                 ltv[t] = 0u;
             }
         }

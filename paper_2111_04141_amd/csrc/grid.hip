@@ -100,10 +100,11 @@ __device__ inline uint32_t next_chunk(uint32_t *queue, uint32_t *slot) {
 // ---------------------------------------------------------------------------
 // KMAX: slots per lane (S^2 <= 64 KMAX).  The four waves of a workgroup take
 // consecutive quarters of the chunk's records, each with its own window.
-// Each slot keeps its cell and the term cell_v beta rowlen + cell_u beta of
-// its tap offset (bytes, modulo 2^32); a record subtracts its own term, so
-// the slot's tap offset costs one subtraction per record, and only slots
-// whose cell leaves the footprint do more work.
+// Each slot keeps its cell and the term cell_v S + cell_u (W-projection;
+// separable: cell_u and cell_v) of its tap offset (bytes, modulo 2^32); a
+// record subtracts its own term, so the slot's tap offset costs one
+// subtraction per record, and only slots whose cell leaves the footprint do
+// more work.
 template <int KMAX, bool SEP, typename TapT>
 __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
     const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
@@ -119,7 +120,6 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int npol = prm.npol;
-    const uint32_t beta = (uint32_t)prm.beta;
     const uint32_t c_begin = plane_cfirst[prm.p_lo];
     const uint32_t c_end = plane_cfirst[prm.p_hi];
     const char *tbase = reinterpret_cast<const char *>(taps);
@@ -142,11 +142,10 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
         const int RW = (int)((ch.bbox >> 8) & 0xffu) - (int)(ch.bbox & 0xffu) + S;
         const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
         const int plane_cells = RH * RW;
-        const uint32_t rowlen = (uint32_t)pl.rowlen;
         const uint32_t rb0 = ch.start, re0 = ch.start + ch.len;
-        // offset terms per cell step (bytes)
-        const uint32_t su_step = beta * kElem;
-        const uint32_t sv_step = SEP ? beta * kElem : beta * rowlen * kElem;
+        // offset terms per cell step (bytes; phase-major table)
+        const uint32_t su_step = kElem;
+        const uint32_t sv_step = SEP ? kElem : (uint32_t)S * kElem;
 
         // fixed-point scale of this chunk: 2^scale * bound <= 2^30
         int scale = 0;
@@ -408,7 +407,6 @@ void grid_block_kernel(
     const int lane = threadIdx.x & 63;
     const int lu = lane & 7, lv = lane >> 3;
     const int npol = prm.npol;
-    const int beta = prm.beta;
     const char *tbase = reinterpret_cast<const char *>(taps);
 
     // The launch covers one plane group.  Its work comes in units: chunks of
@@ -464,7 +462,6 @@ void grid_block_kernel(
                 const int p = g0.grp_first + (int)((ch.bucket - gbase) % gn);
                 const PlaneLayout pl = planes[p];
                 const int S = pl.S;
-                const uint32_t rowlen = (uint32_t)pl.rowlen;
                 // this lane's tap offset in each block, in bytes relative to
                 // the footprint's first tap
                 uint32_t voff[KMAX], voffv[KMAX];
@@ -472,10 +469,10 @@ void grid_block_kernel(
                 for (int k = 0; k < KMAX; ++k) {
                     const uint32_t cu = cuv[k] & 0xffffu, cv = cuv[k] >> 16;
                     if constexpr (SEP) {
-                        voff[k] = cu * (uint32_t)beta * kElem;
-                        voffv[k] = cv * (uint32_t)beta * kElem;
+                        voff[k] = cu * kElem;
+                        voffv[k] = cv * kElem;
                     } else {
-                        voff[k] = (cv * rowlen + cu) * (uint32_t)beta * kElem;
+                        voff[k] = (cv * (uint32_t)S + cu) * kElem;
                         voffv[k] = 0u;
                     }
                 }
@@ -496,10 +493,10 @@ void grid_block_kernel(
                     const char *tb_;
                     const char *tbv = nullptr;
                     if constexpr (SEP) {
-                        tb_ = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a * beta) * (int64_t)kElem;
-                        tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq * beta) * (int64_t)kElem;
+                        tb_ = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a) * (int64_t)kElem;
+                        tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq) * (int64_t)kElem;
                     } else {
-                        tb_ = tbase + ((int64_t)m.toff - (int64_t)(bq * rowlen + a) * beta) * (int64_t)kElem;
+                        tb_ = tbase + ((int64_t)m.toff - (int64_t)(bq * (uint32_t)S + a)) * (int64_t)kElem;
                     }
                     // tap of lane's cell in block k (uniform base + 32-bit lane offset)
                     auto tap = [&](const int k) {

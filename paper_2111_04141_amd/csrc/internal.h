@@ -24,8 +24,8 @@ struct PlaneLayout {
     int32_t ntu, ntv;   // tiles per axis
     int64_t base;       // first bucket of the plane's group
     int32_t cls;        // gridder class (see grid.hip)
-    int32_t rowlen;     // beta * S + 1: entries per table row
-    uint32_t tap_off;   // first table element of the plane
+    uint32_t tap_off;   // first element of the plane in the plan's (phase-major) table
+    uint32_t src_off;   // first element of the plane in the caller's bank
     float wmax;         // bound on |re|, |im| of one tap weight of the plane
     int32_t grp_first;  // first plane of the group
     int32_t grp_n;      // planes in the group
@@ -87,9 +87,10 @@ mg_status launch_compute_indices(const DevGeom &g, int64_t nrec, const void *uvw
                                  int32_t *o_u, int32_t *o_v, int32_t *plane, uint8_t *valid,
                                  int64_t *d_nskipped, hipStream_t stream);
 
-// Writes the complex conjugate of the ntaps-element bank at taps into the
-// ntaps elements that follow it (plan.hip).
-hipError_t launch_conjugate_copy(void *taps, mg_dtype dt, int64_t ntaps, hipStream_t stream);
+// Uploads the plane layouts and lays out the plan's tap table (table_elems
+// elements per copy) from the caller's bank at src, followed for
+// W-projection by its complex conjugate (plan.hip).
+mg_status plan_taps(PlanState &P, const void *src, int64_t table_elems, hipStream_t stream);
 
 // Hot kernels (grid.hip, degrid.hip).
 mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream_t stream);
@@ -103,6 +104,16 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hip
 // grid.hip); class 3 commits straight to the grid.
 //   class 3: S <= 64  (16 slots per lane, slots split over the 4 waves,
 //                      commits straight to the grid)
+inline size_t dtype_size(mg_dtype d) {
+    switch (d) {
+    case MG_F32: return 4;
+    case MG_F64: return 8;
+    case MG_F16: return 2;
+    case MG_BF16: return 2;
+    }
+    return 0;
+}
+
 inline int support_class(int S) { return S <= 8 ? 0 : S <= 16 ? 1 : S <= 32 ? 2 : 3; }
 
 constexpr int kWavesPerGroup = 4;

@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void plane_wmax_kernel(PlaneLayout *planes, co
                                                          int32_t beta, int32_t separable) {
     __shared__ float s_max[256];
     PlaneLayout &pl = planes[blockIdx.x];
-    const int64_t w = (int64_t)beta * pl.S + 1;
+    const int64_t w = (int64_t)beta * pl.S;   // taps per axis in the plan's table
     const int64_t n = separable ? w : 2 * w * w;       // real values
     const int64_t first = separable ? 0 : 2 * (int64_t)pl.tap_off;
     float m = 0.0f;
@@ -524,30 +524,74 @@ hipError_t malloc_bytes(PlanState &P, T **p, size_t bytes, hipStream_t s) {
     return e;
 }
 
-// bank[n + i] = conj(bank[i]) for complex taps stored as (re, im) pairs of T
+// The plan's tap table, phase-major (see common.h): entry
+// (o_v, o_u, j, i) of plane p takes bank element (o_v + 1 + j beta) *
+// (beta S + 1) + (o_u + 1 + i beta) of the caller's plane; for W-projection
+// (complex entries, (re, im) pairs of T) its conjugate also goes to
+// conj_base + the same index.  Separable: entry (o, i) takes o + 1 + i beta.
 template <typename T>
-__global__ __launch_bounds__(256) void conjugate_copy_kernel(T *taps, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        taps[2 * (n + i)] = taps[2 * i];
-        taps[2 * (n + i) + 1] = -taps[2 * i + 1];
+__global__ __launch_bounds__(256) void tap_layout_kernel(const PlaneLayout *__restrict__ planes,
+                                                         int32_t beta, int32_t wproj,
+                                                         const T *__restrict__ src,
+                                                         T *__restrict__ dst, int64_t conj_base) {
+    const PlaneLayout pl = planes[blockIdx.y];
+    const int64_t S = pl.S;
+    const int64_t ws = (int64_t)beta * S + 1;   // caller's row length
+    const int64_t n = wproj ? (int64_t)beta * beta * S * S : (int64_t)beta * S;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % S;
+        const int64_t d = (int64_t)pl.tap_off + e;
+        if (wproj) {
+            const int64_t blk = e / (S * S);
+            const int64_t j = (e / S) % S;
+            const int64_t ou = blk % beta, ov = blk / beta;
+            const int64_t sidx = (int64_t)pl.src_off + (ov + 1 + j * beta) * ws + (ou + 1 + i * beta);
+            const T re = src[2 * sidx], im = src[2 * sidx + 1];
+            dst[2 * d] = re;
+            dst[2 * d + 1] = im;
+            dst[2 * (conj_base + d)] = re;
+            dst[2 * (conj_base + d) + 1] = -im;
+        } else {
+            const int64_t o = e / S;
+            dst[d] = src[o + 1 + i * beta];
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_conjugate_copy(void *taps, mg_dtype dt, int64_t n, hipStream_t stream) {
-    const int nb = grid_blocks(n, 256);
-    if (dt == MG_F16)
-        hipLaunchKernelGGL(conjugate_copy_kernel<__half>, dim3(nb), dim3(256), 0, stream,
-                           (__half *)taps, n);
-    else if (dt == MG_BF16)
-        hipLaunchKernelGGL(conjugate_copy_kernel<__hip_bfloat16>, dim3(nb), dim3(256), 0, stream,
-                           (__hip_bfloat16 *)taps, n);
+mg_status plan_taps(PlanState &P, const void *src, int64_t table_elems, hipStream_t stream) {
+    const int np = P.nplanes_eff;
+    const bool wproj = P.kind == MG_KERNEL_WPROJ;
+    const size_t esz = dtype_size(P.tap_dtype) * (wproj ? 2 : 1);
+    P.taps_bytes = esz * (size_t)table_elems * (wproj ? 2 : 1);
+    hipError_t e;
+    if ((e = malloc_bytes(P, &P.d_planes, sizeof(PlaneLayout) * (size_t)np, stream)) ||
+        (e = malloc_bytes(P, (char **)&P.taps, P.taps_bytes, stream)))
+        return set_error(MG_ENOMEM, std::string("tap table allocation: ") + hipGetErrorString(e));
+    hipMemcpyAsync(P.d_planes, P.planes.data(), sizeof(PlaneLayout) * np, hipMemcpyHostToDevice,
+                   stream);
+    int64_t most = 0;
+    for (const PlaneLayout &L : P.planes) {
+        const int64_t w = (int64_t)P.geom.beta * L.S;
+        most = std::max<int64_t>(most, wproj ? w * w : w);
+    }
+    const dim3 grid((unsigned)std::min<int64_t>(grid_blocks(most, 256), 1024), (unsigned)np);
+    const int32_t beta = P.geom.beta;
+    if (P.tap_dtype == MG_F16)
+        hipLaunchKernelGGL(tap_layout_kernel<__half>, grid, dim3(256), 0, stream, P.d_planes, beta,
+                           (int32_t)wproj, (const __half *)src, (__half *)P.taps, table_elems);
+    else if (P.tap_dtype == MG_BF16)
+        hipLaunchKernelGGL(tap_layout_kernel<__hip_bfloat16>, grid, dim3(256), 0, stream,
+                           P.d_planes, beta, (int32_t)wproj, (const __hip_bfloat16 *)src,
+                           (__hip_bfloat16 *)P.taps, table_elems);
     else
-        hipLaunchKernelGGL(conjugate_copy_kernel<float>, dim3(nb), dim3(256), 0, stream,
-                           (float *)taps, n);
-    return hipGetLastError();
+        hipLaunchKernelGGL(tap_layout_kernel<float>, grid, dim3(256), 0, stream, P.d_planes, beta,
+                           (int32_t)wproj, (const float *)src, (float *)P.taps, table_elems);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("tap layout: ") + hipGetErrorString(e));
+    return MG_OK;
 }
 
 mg_status launch_compute_indices(const DevGeom &g, int64_t nrec, const void *uvw,
@@ -584,7 +628,6 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         (e = malloc_bytes(P, &P.bucket_cfirst, sizeof(uint32_t) * (size_t)(nb + 1), stream)) ||
         (e = malloc_bytes(P, &P.units, sizeof(uint2) * (size_t)P.max_chunks, stream)) ||
         (e = malloc_bytes(P, &P.group_nunits, sizeof(uint32_t) * (size_t)np, stream)) ||
-        (e = malloc_bytes(P, &P.d_planes, sizeof(PlaneLayout) * (size_t)np, stream)) ||
         (e = malloc_bytes(P, &P.counters, sizeof(int64_t) * 6, stream)))
         return set_error(MG_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
     // temporaries (stream-ordered)
@@ -602,8 +645,6 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         (e = tmp((void **)&sums, sizeof(uint2) * (size_t)(nscan + 1))))
         return set_error(MG_ENOMEM, std::string("plan scratch: ") + hipGetErrorString(e));
 
-    hipMemcpyAsync(P.d_planes, P.planes.data(), sizeof(PlaneLayout) * np, hipMemcpyHostToDevice,
-                   stream);
     // zero-fill with a kernel (no memset nodes, so the calls stay capturable)
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t *)P.counters,
                        (int64_t)12, 0u);
