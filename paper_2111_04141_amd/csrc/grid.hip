@@ -96,103 +96,131 @@ __device__ inline uint32_t next_chunk(uint32_t *queue, uint32_t *slot) {
 }
 
 // ---------------------------------------------------------------------------
-// moving-window gridder (supports up to 16)
+// moving-window gridder (supports up to 32)
 // ---------------------------------------------------------------------------
-// KMAX: slots per lane (S^2 <= 64 KMAX).  The four waves of a workgroup take
-// consecutive quarters of the chunk's records, each with its own window.
+// A footprint's S^2 cells are held by slots, slot (su, sv) owning the cells
+// congruent to it mod S.  TEAM waves share one footprint, each holding a
+// contiguous share of q = ceil(S^2 / TEAM) slots, at most KMAX per lane
+// (q <= 64 KMAX); the workgroup's NW / TEAM teams take consecutive parts of
+// each chunk's records, each team with its own window.
 // Each slot keeps its cell and the term cell_v S + cell_u (W-projection;
 // separable: cell_u and cell_v) of its tap offset (bytes, modulo 2^32); a
 // record subtracts its own term, so the slot's tap offset costs one
 // subtraction per record, and only slots whose cell leaves the footprint do
 // more work.
-template <int KMAX, bool SEP, typename TapT>
-__global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
+// Work items: one chunk (TEAM == 1, supports up to 16), or one unit of
+// chunks of a tile over the planes of a group (TEAM > 1).  An item's sums
+// go to an LDS region covering what its chunks can touch, in fixed point,
+// and from there to the grid once per item.
+// Waves per workgroup: four single-wave teams, or two teams of TEAM waves
+// (two such workgroups share a CU's LDS for supports up to 32).
+constexpr int window_waves(int team) { return team == 1 ? 4 : 2 * team; }
+
+template <int KMAX, int TEAM, bool SEP, typename TapT>
+__global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel(
     const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
-    const uint32_t *__restrict__ plane_cfirst, const PlaneLayout *__restrict__ planes,
-    const uint32_t *__restrict__ nonfinite, uint32_t *__restrict__ queue, GridParams prm) {
+    const uint32_t *__restrict__ plane_cfirst, const uint32_t *__restrict__ bucket_cfirst,
+    const uint2 *__restrict__ units, const uint32_t *__restrict__ group_nunits,
+    const PlaneLayout *__restrict__ planes, const uint32_t *__restrict__ nonfinite,
+    uint32_t *__restrict__ queue, GridParams prm) {
+    constexpr int NW = window_waves(TEAM);
+    constexpr int NTEAMS = NW / TEAM;
     // fixed point cannot hold NaN or Inf: calls whose visibilities are not
     // all finite commit straight to the grid in FP32
     const bool use_lds = uniform_u32(*nonfinite) == 0u;
     extern __shared__ int32_t region[];   // [8][RH][RW]: (pol, re/im) planes
-    __shared__ float s_bound[kWavesPerGroup];
+    __shared__ float s_bound[NW];
+    __shared__ uint32_t s_next;
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);   // bytes per tap
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    const int team = wave / TEAM, member = wave % TEAM;
     const int npol = prm.npol;
-    const uint32_t c_begin = plane_cfirst[prm.p_lo];
-    const uint32_t c_end = plane_cfirst[prm.p_hi];
     const char *tbase = reinterpret_cast<const char *>(taps);
 
-    __shared__ uint32_t s_next;
-    int p = prm.p_lo;   // chunks come in increasing order: the plane only moves forward
-    for (uint32_t c = c_begin + next_chunk(queue, &s_next); c < c_end;
-         c = c_begin + next_chunk(queue, &s_next)) {
-        const Chunk ch = chunks[c];
-        while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
-        const PlaneLayout pl = planes[p];
-        const int S = pl.S;
-        // planes of the window classes form groups of one: the bucket's
-        // offset from the plane's base is its tile
-        const uint32_t local = ch.bucket - (uint32_t)pl.base;
-        const uint32_t tu0 = (local % (uint32_t)pl.ntu) << pl.log2T;
-        const uint32_t tv0 = (local / (uint32_t)pl.ntu) << pl.log2T;
-        const uint32_t cu0 = tu0 + (ch.bbox & 0xffu);
-        const uint32_t cv0 = tv0 + ((ch.bbox >> 16) & 0xffu);
-        const int RW = (int)((ch.bbox >> 8) & 0xffu) - (int)(ch.bbox & 0xffu) + S;
-        const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
+    uint32_t item_begin, item_end;   // chunk indices (TEAM == 1) or unit indices
+    const uint2 *gunits = nullptr;
+    if constexpr (TEAM == 1) {
+        item_begin = plane_cfirst[prm.p_lo];
+        item_end = plane_cfirst[prm.p_hi];
+    } else {
+        gunits = units + bucket_cfirst[planes[prm.p_lo].base];
+        item_begin = 0;
+        item_end = group_nunits[prm.p_lo];
+    }
+    // a plane of the item's group (TEAM == 1: chunks come in increasing
+    // order, so the plane only moves forward)
+    int p = prm.p_lo;
+    for (uint32_t it = item_begin + next_chunk(queue, &s_next); it < item_end;
+         it = item_begin + next_chunk(queue, &s_next)) {
+        uint32_t c0, c1;
+        if constexpr (TEAM == 1) {
+            c0 = it;
+            c1 = it + 1;
+            while (p + 1 < prm.p_hi && it >= plane_cfirst[p + 1]) ++p;
+        } else {
+            const uint2 un = gunits[it];
+            c0 = un.x;
+            c1 = un.x + un.y;
+        }
+        // the item's region: union of its chunks' k_lo ranges (relative to
+        // the tile origin) extended by their supports
+        const PlaneLayout gl = planes[p];
+        uint32_t umin = 0xffu, vmin = 0xffu, uend = 0u, vend = 0u;
+        for (uint32_t c = c0; c < c1; ++c) {
+            const Chunk ch = chunks[c];
+            int pc;
+            uint32_t tile_;
+            bucket_plane_tile(gl, ch.bucket, &pc, &tile_);
+            const uint32_t Sc = (uint32_t)planes[pc].S;
+            umin = min(umin, ch.bbox & 0xffu);
+            vmin = min(vmin, (ch.bbox >> 16) & 0xffu);
+            uend = max(uend, ((ch.bbox >> 8) & 0xffu) + Sc);
+            vend = max(vend, (ch.bbox >> 24) + Sc);
+        }
+        uint32_t tile;
+        {
+            int pc;
+            bucket_plane_tile(gl, chunks[c0].bucket, &pc, &tile);
+        }
+        const uint32_t cu0 = ((tile % (uint32_t)gl.ntu) << gl.log2T) + umin;
+        const uint32_t cv0 = ((tile / (uint32_t)gl.ntu) << gl.log2T) + vmin;
+        const int RW = (int)(uend - umin);
+        const int RH = (int)(vend - vmin);
         const int plane_cells = RH * RW;
-        const uint32_t rb0 = ch.start, re0 = ch.start + ch.len;
-        // offset terms per cell step (bytes; phase-major table)
-        const uint32_t su_step = kElem;
-        const uint32_t sv_step = SEP ? kElem : (uint32_t)S * kElem;
 
-        // fixed-point scale of this chunk: 2^scale * bound <= 2^30
+        // fixed-point scale of this item: 2^scale * bound <= 2^30
         int scale = 0;
         if (use_lds) {
-            for (int i = threadIdx.x; i < 8 * plane_cells; i += kGroupThreads) region[i] = 0;
+            for (int i = threadIdx.x; i < 8 * plane_cells; i += NW * kWave) region[i] = 0;
             float part = 0.0f;
-            for (uint32_t r = rb0 + threadIdx.x; r < re0; r += kGroupThreads) {
-                const float4 a = svis[2 * (size_t)r], b = svis[2 * (size_t)r + 1];
-                const float m = fmaxf(fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))),
-                                      fmaxf(fmaxf(fabsf(b.x), fabsf(b.y)), fmaxf(fabsf(b.z), fabsf(b.w))));
-                part += m;
+            for (uint32_t c = c0; c < c1; ++c) {
+                const Chunk ch = chunks[c];
+                int pc;
+                uint32_t tile_;
+                bucket_plane_tile(gl, ch.bucket, &pc, &tile_);
+                const float wmax = planes[pc].wmax;
+                for (uint32_t r = ch.start + threadIdx.x; r < ch.start + ch.len; r += NW * kWave) {
+                    const float4 a = svis[2 * (size_t)r], b = svis[2 * (size_t)r + 1];
+                    const float m = fmaxf(fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))),
+                                          fmaxf(fmaxf(fabsf(b.x), fabsf(b.y)), fmaxf(fabsf(b.z), fabsf(b.w))));
+                    part += wmax * m;
+                }
             }
             for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
             if (lane == 0) s_bound[wave] = part;
             __syncthreads();
             float bound = 0.0f;
-            for (int w = 0; w < kWavesPerGroup; ++w) bound += s_bound[w];
-            // margin for the rounding of the sum above
-            bound = 2.0f * pl.wmax * bound * 1.0001f + 1e-30f;
+            for (int w = 0; w < NW; ++w) bound += s_bound[w];
+            // margin for the rounding of the sums above
+            bound = 2.0f * bound * 1.0001f + 1e-30f;
             int e;
             frexpf(bound, &e);          // bound < 2^e
             scale = max(-120, min(120, 30 - e));
             scale = (int)uniform_u32((uint32_t)scale);
             __syncthreads();
         }
-
-        // slots of this wave: slot k * 64 + lane; per-lane flags are bit
-        // fields (bit k = slot k)
-        const int nslots = S * S;
-        const int kdyn = (nslots + kWave - 1) / kWave;
-        uint32_t cell[KMAX], lo[KMAX], lov[KMAX], suv[KMAX];
-        uint32_t valid_bits = 0;
-        float acc[KMAX][8];
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            if (k < kdyn && k * kWave + lane < nslots) valid_bits |= 1u << k;
-            // slot (su, sv) owns the cells congruent to it mod S
-            const uint32_t sidx = (uint32_t)(k * kWave + lane);
-            const uint32_t sv = sidx / (uint32_t)S;
-            suv[k] = (sidx - sv * (uint32_t)S) | (sv << 16);
-            cell[k] = kNoCell;
-            lo[k] = 0u;
-            lov[k] = 0u;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-        }
-
         // adds a slot's sums to its cell (fixed point: scaled by the exact
         // power of two 2^scale and truncated, at most one quantum per commit)
         const float fscale = ldexpf(1.0f, scale);
@@ -215,145 +243,181 @@ __global__ __launch_bounds__(kGroupThreads) void grid_window_kernel(
             }
         };
 
-        // window of the current footprint: slots whose cell left it commit
-        // and take the cell congruent to them inside the new footprint
-        uint32_t prev_kuv = 0xffffffffu;
-        uint32_t ru = 0, rv = 0;   // the record's offset terms (bytes, modulo 2^32)
-        auto window_update = [&](const RecMeta m) {
-            const uint32_t kuv = m.kuv;
-            if (kuv == prev_kuv) return;
-            prev_kuv = kuv;
-            const uint32_t ku = meta_ku(m), kv = meta_kv(m);
-            uint32_t moved_bits = 0;
+        for (uint32_t c = c0; c < c1; ++c) {
+            const Chunk ch = chunks[c];
+            int pc;
+            uint32_t tile_;
+            bucket_plane_tile(gl, ch.bucket, &pc, &tile_);
+            const int S = planes[pc].S;
+            // offset terms per cell step (bytes; phase-major table)
+            const uint32_t su_step = kElem;
+            const uint32_t sv_step = SEP ? kElem : (uint32_t)S * kElem;
+
+            // this wave's slots: member * q + k * 64 + lane; per-lane flags
+            // are bit fields (bit k = slot k)
+            const int nslots = S * S;
+            const int q_ = (nslots + TEAM - 1) / TEAM;
+            const int kdyn = (q_ + kWave - 1) / kWave;
+            uint32_t cell[KMAX], lo[KMAX], lov[KMAX], suv[KMAX];
+            uint32_t valid_bits = 0;
+            float acc[KMAX][8];
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                if (k < kdyn) {
-                    const uint32_t d = cell[k] - kuv;   // a borrow only where du < 0
-                    if (max(d & 0xffffu, d >> 16) >= (uint32_t)S) moved_bits |= 1u << k;
-                }
+                const int j = k * kWave + lane;
+                const uint32_t sidx = (uint32_t)(member * q_ + j);
+                if (k < kdyn && j < q_ && sidx < (uint32_t)nslots) valid_bits |= 1u << k;
+                // slot (su, sv) owns the cells congruent to it mod S
+                const uint32_t sv = sidx / (uint32_t)S;
+                suv[k] = (sidx - sv * (uint32_t)S) | (sv << 16);
+                cell[k] = kNoCell;
+                lo[k] = 0u;
+                lov[k] = 0u;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
             }
-            moved_bits &= valid_bits;
-            if (__ballot(moved_bits != 0) != 0) {
-                const uint32_t kmu = ku % (uint32_t)S, kmv = kv % (uint32_t)S;
+
+            // window of the current footprint: slots whose cell left it commit
+            // and take the cell congruent to them inside the new footprint
+            uint32_t prev_kuv = 0xffffffffu;
+            uint32_t ru = 0, rv = 0;   // the record's offset terms (bytes, modulo 2^32)
+            auto window_update = [&](const RecMeta m) {
+                const uint32_t kuv = m.kuv;
+                if (kuv == prev_kuv) return;
+                prev_kuv = kuv;
+                const uint32_t ku = meta_ku(m), kv = meta_kv(m);
+                uint32_t moved_bits = 0;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k) {
-                    if (k < kdyn && ((moved_bits >> k) & 1u)) {
-                        if (cell[k] != kNoCell) commit(acc[k], cell[k]);
+                    if (k < kdyn) {
+                        const uint32_t d = cell[k] - kuv;   // a borrow only where du < 0
+                        if (max(d & 0xffffu, d >> 16) >= (uint32_t)S) moved_bits |= 1u << k;
+                    }
+                }
+                moved_bits &= valid_bits;
+                if (__ballot(moved_bits != 0) != 0) {
+                    const uint32_t kmu = ku % (uint32_t)S, kmv = kv % (uint32_t)S;
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-                        int du = (int)(suv[k] & 0xffffu) - (int)kmu;
-                        int dv = (int)(suv[k] >> 16) - (int)kmv;
-                        du += (du < 0) ? S : 0;
-                        dv += (dv < 0) ? S : 0;
-                        const uint32_t nu_ = ku + (uint32_t)du, nv_ = kv + (uint32_t)dv;
-                        cell[k] = nu_ | (nv_ << 16);
-                        if constexpr (SEP) {
-                            lo[k] = nu_ * su_step;
-                            lov[k] = nv_ * sv_step;
-                        } else {
-                            lo[k] = nv_ * sv_step + nu_ * su_step;
+                    for (int k = 0; k < KMAX; ++k) {
+                        if (k < kdyn && ((moved_bits >> k) & 1u)) {
+                            if (cell[k] != kNoCell) commit(acc[k], cell[k]);
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
+                            int du = (int)(suv[k] & 0xffffu) - (int)kmu;
+                            int dv = (int)(suv[k] >> 16) - (int)kmv;
+                            du += (du < 0) ? S : 0;
+                            dv += (dv < 0) ? S : 0;
+                            const uint32_t nu_ = ku + (uint32_t)du, nv_ = kv + (uint32_t)dv;
+                            cell[k] = nu_ | (nv_ << 16);
+                            if constexpr (SEP) {
+                                lo[k] = nu_ * su_step;
+                                lov[k] = nv_ * sv_step;
+                            } else {
+                                lo[k] = nv_ * sv_step + nu_ * su_step;
+                            }
                         }
                     }
                 }
-            }
-            if constexpr (SEP) {
-                ru = ku * su_step;
-                rv = kv * sv_step;
-            } else {
-                ru = kv * sv_step + ku * su_step;
-            }
-            // lanes without a slot (S^2 not a multiple of 64) read the
-            // footprint's first tap: their offset term follows the record's
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                if (k < kdyn && !((valid_bits >> k) & 1u)) {
-                    lo[k] = ru;
-                    lov[k] = rv;
+                if constexpr (SEP) {
+                    ru = ku * su_step;
+                    rv = kv * sv_step;
+                } else {
+                    ru = kv * sv_step + ku * su_step;
                 }
-            }
-        };
-
-        // tap of slot k for a record (uniform base + 32-bit lane offset)
-        auto tap = [&](const RecMeta m, const int k) {
-            if constexpr (SEP) {
-                const char *tu = tbase + (size_t)(m.toff & 0xffffu) * kElem;
-                const char *tv = tbase + (size_t)(m.toff >> 16) * kElem;
-                const uint32_t ou = lo[k] - ru, ov = lov[k] - rv;
-                return make_float2(TapTraits<TapT>::real((const TapT *)(tu + ou), 0) *
-                                       TapTraits<TapT>::real((const TapT *)(tv + ov), 0),
-                                   0.0f);
-            } else {
-                const char *tb = tbase + (size_t)m.toff * kElem;
-                return TapTraits<TapT>::cplx((const TapT *)(tb + (lo[k] - ru)), 0);
-            }
-        };
-        auto madd = [&](const int k, const float2 w, const RecVis &f) {
-            if constexpr (SEP)
-                fma_real(acc[k], w.x, f);
-            else
-                fma_complex(acc[k], w, f);
-        };
-
-        const uint32_t len = ch.len;
-        const uint32_t rb = ch.start + (uint32_t)(((uint64_t)len * wave) / kWavesPerGroup);
-        const uint32_t re = ch.start + (uint32_t)(((uint64_t)len * (wave + 1)) / kWavesPerGroup);
-        if (rb < re) {
-            // records are read in batches on the scalar unit; the next batch's
-            // loads are issued after the current batch has been consumed
-            // (scalar loads complete out of order: waiting for one is waiting
-            // for all), so they overlap the current batch's multiply-adds
-            RecMeta nm[kBatch];
-            float4 na4[kBatch], nb4[kBatch];
-            // the record arrays are padded by kBatch entries, so a batch may
-            // run past the chunk's end (those records are not used)
-            const RecMeta *pm = smeta + rb;
-            const float4 *pv = svis + 2 * (size_t)rb;
-            auto load_batch = [&]() {
+                // lanes without a slot read the footprint's first tap: their
+                // offset term follows the record's
 #pragma unroll
-                for (int i = 0; i < kBatch; ++i) {
-                    nm[i] = pm[i];
-                    na4[i] = pv[2 * i];
-                    nb4[i] = pv[2 * i + 1];
-                }
-                pm += kBatch;
-                pv += 2 * kBatch;
-            };
-            load_batch();
-            for (uint32_t r = rb; r < re; r += kBatch) {
-                RecMeta mm[kBatch];
-                float4 va4[kBatch], vb4[kBatch];
-#pragma unroll
-                for (int i = 0; i < kBatch; ++i) {
-                    mm[i] = nm[i];
-                    va4[i] = na4[i];
-                    vb4[i] = nb4[i];
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                load_batch();
-#pragma unroll
-                for (int i = 0; i < kBatch; ++i) {
-                    if (r + (uint32_t)i < re) {
-                        window_update(mm[i]);
-                        const RecVis f = unpack_vis(va4[i], vb4[i]);
-                        float2 w[KMAX];
-#pragma unroll
-                        for (int k = 0; k < KMAX; ++k)
-                            if (k < kdyn) w[k] = tap(mm[i], k);
-#pragma unroll
-                        for (int k = 0; k < KMAX; ++k)
-                            if (k < kdyn) madd(k, w[k], f);
+                for (int k = 0; k < KMAX; ++k) {
+                    if (k < kdyn && !((valid_bits >> k) & 1u)) {
+                        lo[k] = ru;
+                        lov[k] = rv;
                     }
                 }
-            }
+            };
+
+            // tap of slot k for a record (uniform base + 32-bit lane offset)
+            auto tap = [&](const RecMeta m, const int k) {
+                if constexpr (SEP) {
+                    const char *tu = tbase + (size_t)(m.toff & 0xffffu) * kElem;
+                    const char *tv = tbase + (size_t)(m.toff >> 16) * kElem;
+                    const uint32_t ou = lo[k] - ru, ov = lov[k] - rv;
+                    return make_float2(TapTraits<TapT>::real((const TapT *)(tu + ou), 0) *
+                                           TapTraits<TapT>::real((const TapT *)(tv + ov), 0),
+                                       0.0f);
+                } else {
+                    const char *tb = tbase + (size_t)m.toff * kElem;
+                    return TapTraits<TapT>::cplx((const TapT *)(tb + (lo[k] - ru)), 0);
+                }
+            };
+            auto madd = [&](const int k, const float2 w, const RecVis &f) {
+                if constexpr (SEP)
+                    fma_real(acc[k], w.x, f);
+                else
+                    fma_complex(acc[k], w, f);
+            };
+
+            const uint32_t len = ch.len;
+            const uint32_t rb = ch.start + (uint32_t)(((uint64_t)len * team) / NTEAMS);
+            const uint32_t re = ch.start + (uint32_t)(((uint64_t)len * (team + 1)) / NTEAMS);
+            if (rb < re) {
+                // records are read in batches on the scalar unit; the next
+                // batch's loads are issued after the current batch has been
+                // consumed (scalar loads complete out of order: waiting for
+                // one is waiting for all), so they overlap the current
+                // batch's multiply-adds
+                RecMeta nm[kBatch];
+                float4 na4[kBatch], nb4[kBatch];
+                // the record arrays are padded by kBatch entries, so a batch
+                // may run past the chunk's end (those records are not used)
+                const RecMeta *pm = smeta + rb;
+                const float4 *pv = svis + 2 * (size_t)rb;
+                auto load_batch = [&]() {
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < kdyn && ((valid_bits >> k) & 1u) && cell[k] != kNoCell) commit(acc[k], cell[k]);
+                    for (int i = 0; i < kBatch; ++i) {
+                        nm[i] = pm[i];
+                        na4[i] = pv[2 * i];
+                        nb4[i] = pv[2 * i + 1];
+                    }
+                    pm += kBatch;
+                    pv += 2 * kBatch;
+                };
+                load_batch();
+                for (uint32_t r = rb; r < re; r += kBatch) {
+                    RecMeta mm[kBatch];
+                    float4 va4[kBatch], vb4[kBatch];
+#pragma unroll
+                    for (int i = 0; i < kBatch; ++i) {
+                        mm[i] = nm[i];
+                        va4[i] = na4[i];
+                        vb4[i] = nb4[i];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_batch();
+#pragma unroll
+                    for (int i = 0; i < kBatch; ++i) {
+                        if (r + (uint32_t)i < re) {
+                            window_update(mm[i]);
+                            const RecVis f = unpack_vis(va4[i], vb4[i]);
+                            float2 w[KMAX];
+#pragma unroll
+                            for (int k = 0; k < KMAX; ++k)
+                                if (k < kdyn) w[k] = tap(mm[i], k);
+#pragma unroll
+                            for (int k = 0; k < KMAX; ++k)
+                                if (k < kdyn) madd(k, w[k], f);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if (k < kdyn && ((valid_bits >> k) & 1u) && cell[k] != kNoCell)
+                        commit(acc[k], cell[k]);
+            }
         }
 
         if (use_lds) {
             __syncthreads();
             const int n = npol * plane_cells;
-            for (int i = threadIdx.x; i < n; i += kGroupThreads) {
+            for (int i = threadIdx.x; i < n; i += NW * kWave) {
                 const int ru_ = i % RW;
                 const int t = i / RW;
                 const int rv_ = t % RH;
@@ -658,13 +722,14 @@ int resident_groups(Kern kernel, int threads, size_t lds) {
     return std::max(1, per) * std::max(1, cus);
 }
 
-template <int KMAX, bool SEP, typename TapT>
-void launch_one(const GridPtrs &a, const GridParams &prm, size_t lds, hipStream_t stream) {
-    auto kern = grid_window_kernel<KMAX, SEP, TapT>;
-    hipLaunchKernelGGL(kern, dim3(resident_groups(kern, kGroupThreads, lds)),
-                       dim3(kGroupThreads), lds, stream, a.smeta, a.svis, a.grid,
-                       (const TapT *)a.taps, a.chunks, a.plane_cfirst, a.planes, a.nonfinite,
-                       a.queue, prm);
+template <int KMAX, int TEAM, bool SEP, typename TapT>
+void launch_window(const GridPtrs &a, const GridParams &prm, size_t lds, hipStream_t stream) {
+    auto kern = grid_window_kernel<KMAX, TEAM, SEP, TapT>;
+    const int threads = kWave * window_waves(TEAM);
+    hipLaunchKernelGGL(kern, dim3(resident_groups(kern, threads, lds)), dim3(threads), lds,
+                       stream, a.smeta, a.svis, a.grid, (const TapT *)a.taps, a.chunks,
+                       a.plane_cfirst, a.bucket_cfirst, a.units, a.group_nunits, a.planes,
+                       a.nonfinite, a.queue, prm);
 }
 
 template <int KMAX, int NW, bool SEP, typename TapT>
@@ -685,17 +750,15 @@ inline int region_blocks(int T, int S) {
 template <bool SEP, typename TapT>
 hipError_t launch_class(int cls, const GridPtrs &a, const GridParams &prm, int smax, int tile,
                         hipStream_t stream) {
-    const size_t lds = (cls <= 1) ? sizeof(int32_t) * 8 * (size_t)(tile + smax - 1) *
+    // LDS region of the window gridders: 8 words per cell of the largest
+    // region (tile plus halo)
+    const size_t lds = (cls <= 2) ? sizeof(int32_t) * 8 * (size_t)(tile + smax - 1) *
                                         (size_t)(tile + smax - 1)
                                   : 0;
     switch (cls) {
-    case 0: launch_one<1, SEP, TapT>(a, prm, lds, stream); break;
-    case 1: launch_one<4, SEP, TapT>(a, prm, lds, stream); break;
-    case 2:
-        // every block of the largest region has an owner
-        if (region_blocks(tile, smax) > 9 * 4) return hipErrorInvalidValue;
-        launch_block<9, 4, SEP, TapT>(a, prm, stream);
-        break;
+    case 0: launch_window<1, 1, SEP, TapT>(a, prm, lds, stream); break;
+    case 1: launch_window<4, 1, SEP, TapT>(a, prm, lds, stream); break;
+    case 2: launch_window<4, 4, SEP, TapT>(a, prm, lds, stream); break;
     default:
         if (region_blocks(tile, smax) > 7 * 16) return hipErrorInvalidValue;
         launch_block<7, 16, SEP, TapT>(a, prm, stream);

@@ -338,8 +338,8 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restr
     __shared__ uint32_t hist[1024];
     __shared__ RecMeta m_in[kMaxR];
     __shared__ uint32_t p_in[kMaxR];
-    // only the planes before p_split (supports up to 16) are cell-sorted; the
-    // kernels of the larger supports take the records in any order
+    // only the planes before p_split (supports up to 32) are cell-sorted; the
+    // blocked kernels of the larger supports take the records in any order
     const uint32_t c_end = plane_cfirst[p_split];
     int p = 0;   // chunks come in increasing order: the plane only moves forward
     for (uint32_t c = blockIdx.x; c < c_end; c += gridDim.x) {
@@ -677,11 +677,11 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
     hipLaunchKernelGGL(plane_ranges_kernel, dim3(1), dim3(256), 0, stream, np, P.d_planes, nb,
                        cstart, sums + nscan, P.plane_cfirst, P.counters);
     {
-        // cell sort of the chunks of supports up to 16 (planes before p_split),
-        // then the bounding box of every chunk
+        // cell sort of the chunks of the window gridders' supports (up to
+        // 32; planes before p_split), then the bounding box of every chunk
         int p_split = np;
         for (int p = 0; p < np; ++p)
-            if (P.planes[p].cls >= 2) {
+            if (P.planes[p].cls >= 3) {
                 p_split = p;
                 break;
             }
