@@ -183,13 +183,12 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
     }
     P.geom.conj_base = table;
     if (table >= (1LL << 30)) return set_error(MG_EUNSUPPORTED, "tap table too large");
-    // groups: runs of consecutive planes of one class above 1 share their
-    // buckets tile-major; every other plane is a group of its own
+    // groups: runs of consecutive planes of one class share their buckets,
+    // numbered tile-major
     int64_t base = 0;
     for (int p0 = 0; p0 < P.nplanes_eff;) {
         int p1 = p0 + 1;
-        if (P.planes[p0].cls >= 2)
-            while (p1 < P.nplanes_eff && P.planes[p1].cls == P.planes[p0].cls) ++p1;
+        while (p1 < P.nplanes_eff && P.planes[p1].cls == P.planes[p0].cls) ++p1;
         int smax = 0;
         for (int p = p0; p < p1; ++p) smax = std::max(smax, P.planes[p].S);
         for (int p = p0; p < p1; ++p) {

@@ -108,10 +108,9 @@ __device__ inline uint32_t next_chunk(uint32_t *queue, uint32_t *slot) {
 // record subtracts its own term, so the slot's tap offset costs one
 // subtraction per record, and only slots whose cell leaves the footprint do
 // more work.
-// Work items: one chunk (TEAM == 1, supports up to 16), or one unit of
-// chunks of a tile over the planes of a group (TEAM > 1).  An item's sums
-// go to an LDS region covering what its chunks can touch, in fixed point,
-// and from there to the grid once per item.
+// Work items are units: chunks of one tile over the planes of the launch's
+// group.  An item's sums go to an LDS region covering what its chunks can
+// touch, in fixed point, and from there to the grid once per item.
 // Waves per workgroup: four single-wave teams, or two teams of TEAM waves
 // (two such workgroups share a CU's LDS for supports up to 32).
 constexpr int window_waves(int team) { return team == 1 ? 4 : 2 * team; }
@@ -120,8 +119,7 @@ template <int KMAX, int TEAM, bool SEP, typename TapT>
 __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel(
     const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
-    const uint32_t *__restrict__ plane_cfirst, const uint32_t *__restrict__ bucket_cfirst,
-    const uint2 *__restrict__ units, const uint32_t *__restrict__ group_nunits,
+    const uint32_t *__restrict__ bucket_cfirst, const uint2 *__restrict__ units, const uint32_t *__restrict__ group_nunits,
     const PlaneLayout *__restrict__ planes, const uint32_t *__restrict__ nonfinite,
     uint32_t *__restrict__ queue, GridParams prm) {
     constexpr int NW = window_waves(TEAM);
@@ -139,34 +137,15 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
     const int npol = prm.npol;
     const char *tbase = reinterpret_cast<const char *>(taps);
 
-    uint32_t item_begin, item_end;   // chunk indices (TEAM == 1) or unit indices
-    const uint2 *gunits = nullptr;
-    if constexpr (TEAM == 1) {
-        item_begin = plane_cfirst[prm.p_lo];
-        item_end = plane_cfirst[prm.p_hi];
-    } else {
-        gunits = units + bucket_cfirst[planes[prm.p_lo].base];
-        item_begin = 0;
-        item_end = group_nunits[prm.p_lo];
-    }
-    // a plane of the item's group (TEAM == 1: chunks come in increasing
-    // order, so the plane only moves forward)
-    int p = prm.p_lo;
-    for (uint32_t it = item_begin + next_chunk(queue, &s_next); it < item_end;
-         it = item_begin + next_chunk(queue, &s_next)) {
-        uint32_t c0, c1;
-        if constexpr (TEAM == 1) {
-            c0 = it;
-            c1 = it + 1;
-            while (p + 1 < prm.p_hi && it >= plane_cfirst[p + 1]) ++p;
-        } else {
-            const uint2 un = gunits[it];
-            c0 = un.x;
-            c1 = un.x + un.y;
-        }
+    // the launch covers one plane group; its work items are the group's units
+    const PlaneLayout gl = planes[prm.p_lo];
+    const uint2 *gunits = units + bucket_cfirst[gl.base];
+    const uint32_t nunits = group_nunits[prm.p_lo];
+    for (uint32_t it = next_chunk(queue, &s_next); it < nunits; it = next_chunk(queue, &s_next)) {
+        const uint2 un = gunits[it];
+        const uint32_t c0 = un.x, c1 = un.x + un.y;
         // the item's region: union of its chunks' k_lo ranges (relative to
         // the tile origin) extended by their supports
-        const PlaneLayout gl = planes[p];
         uint32_t umin = 0xffu, vmin = 0xffu, uend = 0u, vend = 0u;
         for (uint32_t c = c0; c < c1; ++c) {
             const Chunk ch = chunks[c];
@@ -702,7 +681,6 @@ struct GridPtrs {
     float *grid;
     const void *taps;
     const Chunk *chunks;
-    const uint32_t *plane_cfirst;
     const uint32_t *bucket_cfirst;
     const uint2 *units;
     const uint32_t *group_nunits;
@@ -728,7 +706,7 @@ void launch_window(const GridPtrs &a, const GridParams &prm, size_t lds, hipStre
     const int threads = kWave * window_waves(TEAM);
     hipLaunchKernelGGL(kern, dim3(resident_groups(kern, threads, lds)), dim3(threads), lds,
                        stream, a.smeta, a.svis, a.grid, (const TapT *)a.taps, a.chunks,
-                       a.plane_cfirst, a.bucket_cfirst, a.units, a.group_nunits, a.planes,
+                       a.bucket_cfirst, a.units, a.group_nunits, a.planes,
                        a.nonfinite, a.queue, prm);
 }
 
@@ -798,8 +776,8 @@ mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream
                            P.counters, P.nrec, P.sperm, (const float2 *)vis, P.geom.npol, svis,
                            nonfinite);
     }
-    GridPtrs a{P.smeta,          svis,    (float *)grid,  P.taps,     P.chunks,  P.plane_cfirst,
-               P.bucket_cfirst, P.units, P.group_nunits, P.d_planes, nonfinite, nullptr};
+    GridPtrs a{P.smeta,   svis,           (float *)grid, P.taps,    P.chunks, P.bucket_cfirst,
+               P.units,   P.group_nunits, P.d_planes,   nonfinite, nullptr};
     GridParams prm{P.geom.npol, P.geom.nu, P.geom.nv, P.geom.beta, 0, 0};
     const bool sep = P.kind == MG_KERNEL_SEPARABLE;
     // one launch per run of consecutive planes of the same class

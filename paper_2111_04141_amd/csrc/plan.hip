@@ -257,11 +257,10 @@ __global__ void plane_ranges_kernel(int32_t nplanes, const PlaneLayout *__restri
 }
 
 // ---------------------------------------------------------------------------
-// units of a plane group (supports above 16): the chunks of one tile, over
+// units of a plane group: the chunks of one tile, over
 // all planes of the group, split greedily into runs of at most `cap`
-// records (a chunk is never split).  The block gridder takes a unit at a
-// time and commits the tile's region once per unit rather than once per
-// chunk.  units[first chunk of the group + k] = (first chunk, chunk count)
+// records (a chunk is never split).  The gridders take a unit at a time
+// and commit the tile's region once per unit rather than once per chunk.  units[first chunk of the group + k] = (first chunk, chunk count)
 // of the group's unit k; group_nunits[g] = unit count (cleared beforehand).
 // A wave's units are consecutive and in tile order.
 // ---------------------------------------------------------------------------
@@ -698,10 +697,9 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         hipLaunchKernelGGL(chunk_bbox_kernel, dim3(grid_blocks(P.max_chunks * 64, 256)),
                            dim3(256), 0, stream, P.counters, P.plane_cfirst, np, P.d_planes,
                            P.smeta, P.chunks);
-        // units of the plane groups of supports above 16
+        // units of every plane group
         for (int p = 0; p < np; p += P.planes[p].grp_n) {
             const PlaneLayout &L = P.planes[p];
-            if (L.cls < 2) continue;
             const int64_t ntiles = (int64_t)L.ntu * L.ntv;
             hipLaunchKernelGGL(unit_list_kernel, dim3(grid_blocks(ntiles, 256)), dim3(256), 0,
                                stream, P.d_planes, p, P.bucket_cfirst, P.chunks, R, P.units,
