@@ -47,6 +47,7 @@ namespace {
 
 constexpr uint32_t kNoCell = 0xffffffffu;
 constexpr int kBatch = 2;   // records per batch of scalar loads
+static_assert(kBatch + 1 <= kRecPad, "the sorted arrays are padded for one batch of read-ahead");
 
 struct GridParams {
     int32_t npol, nu, nv, beta;
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
                 // batch's multiply-adds
                 RecMeta nm[kBatch];
                 float4 na4[kBatch], nb4[kBatch];
-                // the record arrays are padded by kBatch entries, so a batch
+                // the record arrays are padded (kRecPad entries), so a batch
                 // may run past the chunk's end (those records are not used)
                 const RecMeta *pm = smeta + rb;
                 const float4 *pv = svis + 2 * (size_t)rb;
@@ -591,7 +592,7 @@ void grid_block_kernel(
                     const uint32_t rb = ch.start, re = ch.start + ch.len;
                     RecMeta nm[kBatch];
                     float4 na4[kBatch], nb4[kBatch];
-                    // the record arrays are padded by kBatch entries, so a
+                    // the record arrays are padded (kRecPad entries), so a
                     // batch may run past the chunk's end (those are not used)
                     const RecMeta *pm = smeta + rb;
                     const float4 *pv = svis + 2 * (size_t)rb;
@@ -760,9 +761,9 @@ hipError_t launch_class_t(mg_dtype dt, int cls, const GridPtrs &a, const GridPar
 mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream_t stream) {
     if (P.nrec == 0) return MG_OK;
     float4 *svis = nullptr;
-    // sorted visibilities (padded by kBatch records), then the non-finite
+    // sorted visibilities (padded like the sorted metadata), then the non-finite
     // flag and one chunk counter per launch (at most one per plane)
-    const size_t nsv = 2 * (size_t)(P.nrec + kBatch);
+    const size_t nsv = 2 * (size_t)(P.nrec + kRecPad);
     const int nwords = 1 + P.nplanes_eff;
     hipError_t e = hipMallocAsync((void **)&svis,
                                   sizeof(float4) * nsv + sizeof(uint32_t) * (size_t)nwords, stream);

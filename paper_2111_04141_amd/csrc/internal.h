@@ -104,6 +104,12 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hip
 // grid.hip); class 3 commits straight to the grid.
 //   class 3: S <= 64  (16 slots per lane, slots split over the 4 waves,
 //                      commits straight to the grid)
+// Entries of padding after the sorted record arrays (metadata, and the
+// gridder's sorted visibilities): the gridders load records in batches of
+// two, one batch ahead, so their reads reach 3 entries past the last record
+// of a range.
+constexpr int kRecPad = 4;
+
 inline size_t dtype_size(mg_dtype d) {
     switch (d) {
     case MG_F32: return 4;

@@ -619,9 +619,9 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
     hipError_t e = hipSuccess;
     // persistent plan arrays
     P.max_chunks = nb + nrec / R + 1;
-    // +2: the gridders read records in pairs and may read one past the end
-    if ((e = malloc_bytes(P, &P.smeta, sizeof(RecMeta) * (size_t)(nrec + 2), stream)) ||
-        (e = malloc_bytes(P, &P.sperm, sizeof(uint32_t) * (size_t)(nrec + 2), stream)) ||
+    // padded: the gridders read ahead of the records they use
+    if ((e = malloc_bytes(P, &P.smeta, sizeof(RecMeta) * (size_t)(nrec + kRecPad), stream)) ||
+        (e = malloc_bytes(P, &P.sperm, sizeof(uint32_t) * (size_t)(nrec + kRecPad), stream)) ||
         (e = malloc_bytes(P, &P.chunks, sizeof(Chunk) * (size_t)P.max_chunks, stream)) ||
         (e = malloc_bytes(P, &P.plane_cfirst, sizeof(uint32_t) * (size_t)(np + 1), stream)) ||
         (e = malloc_bytes(P, &P.bucket_cfirst, sizeof(uint32_t) * (size_t)(nb + 1), stream)) ||

@@ -75,7 +75,7 @@ size_t dtype_bytes(mg_dtype d) { return d == MG_F64 ? 8 : d == MG_F32 ? 4 : 2; }
 // visibilities, private tap table).
 size_t job_footprint(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
                      mg_dtype uvw_dtype) {
-    const size_t n = (size_t)nrec + 2;
+    const size_t n = (size_t)nrec + kRecPad;
     const int np = k->kind == MG_KERNEL_WPROJ ? k->nplanes : 1;
     const size_t tiles8 = (size_t)((g->nu + 7) / 8) * (size_t)((g->nv + 7) / 8);
     const size_t nb = (size_t)np * tiles8;                      // buckets (tiles >= 8)
