@@ -169,7 +169,7 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
         L.log2T = ilog2(L.T);
         L.ntu = (g->nu + L.T - 1) / L.T;
         L.ntv = (g->nv + L.T - 1) / L.T;
-        L.wmax = 0.0f;   // filled on the device by the plan build
+        L.tmax = 0.0f;   // raised on the device by the tap layout
     }
     // the plan's tap table: planes one after another, phase-major
     int64_t table = 0;

@@ -180,7 +180,8 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
                 int pc;
                 uint32_t tile_;
                 bucket_plane_tile(gl, ch.bucket, &pc, &tile_);
-                const float wmax = planes[pc].wmax;
+                const float tmax = planes[pc].tmax;
+                const float wmax = SEP ? tmax * tmax : tmax;   // bound on a weight component
                 for (uint32_t r = ch.start + threadIdx.x; r < ch.start + ch.len; r += NW * kWave) {
                     const float4 a = svis[2 * (size_t)r], b = svis[2 * (size_t)r + 1];
                     const float m = fmaxf(fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))),

@@ -26,7 +26,8 @@ struct PlaneLayout {
     int32_t cls;        // gridder class (see grid.hip)
     uint32_t tap_off;   // first element of the plane in the plan's (phase-major) table
     uint32_t src_off;   // first element of the plane in the caller's bank
-    float wmax;         // bound on |re|, |im| of one tap weight of the plane
+    float tmax;         // largest |re|, |im| of the plane's taps (a separable
+                        // weight, a product of two taps, is bounded by tmax^2)
     int32_t grp_first;  // first plane of the group
     int32_t grp_n;      // planes in the group
     int32_t grp_smax;   // largest support in the group

@@ -281,17 +281,36 @@ __global__ __launch_bounds__(256) void unit_list_kernel(const PlaneLayout *__res
         cs = bucket_cfirst[base + (int64_t)t * n];
         ce = bucket_cfirst[base + (int64_t)(t + 1) * n];
     }
-    // pass 1: unit count of this tile (acc = cap opens a unit at the first chunk)
-    uint32_t cnt = 0;
-    for (uint32_t c = cs, acc = cap; c < ce; ++c) {
-        const uint32_t len = chunks[c].len;
-        if (acc + len > cap) {
-            ++cnt;
-            acc = len;
-        } else {
-            acc += len;
+    // A bucket's chunks are full (cap records) but for its last one, so the
+    // greedy split only has to look at each bucket's chunk count and last
+    // length: full chunks are units of their own, and a bucket's last chunk
+    // joins the open unit if it fits (acc = cap opens a unit at the first
+    // chunk).
+    auto walk = [&](auto emit) {
+        uint32_t acc = cap, head = cs;
+        for (uint32_t j = 0; j < n && cs < ce; ++j) {
+            const int64_t b = base + (int64_t)t * n + j;
+            const uint32_t b0 = bucket_cfirst[b], b1 = bucket_cfirst[b + 1];
+            if (b0 == b1) continue;
+            const uint32_t last_len = chunks[b1 - 1].len;
+            for (uint32_t c = b0; c + 1 < b1; ++c) {   // full chunks
+                if (c > head) emit(head, c);
+                head = c;
+                acc = cap;
+            }
+            if (acc + last_len > cap) {
+                if (b1 - 1 > head) emit(head, b1 - 1);
+                head = b1 - 1;
+                acc = last_len;
+            } else {
+                acc += last_len;
+            }
         }
-    }
+        if (ce > cs) emit(head, ce);
+    };
+    // pass 1: unit count of this tile
+    uint32_t cnt = 0;
+    walk([&](uint32_t, uint32_t) { ++cnt; });
     // wave prefix sum; one lane reserves the wave's units
     uint32_t incl = cnt;
 #pragma unroll
@@ -305,18 +324,7 @@ __global__ __launch_bounds__(256) void unit_list_kernel(const PlaneLayout *__res
     wbase = __shfl(wbase, 63, 64);
     // pass 2: write them
     uint2 *out = units + bucket_cfirst[base] + wbase + (incl - cnt);
-    uint32_t head = cs;
-    for (uint32_t c = cs, acc = cap; c < ce; ++c) {
-        const uint32_t len = chunks[c].len;
-        if (acc + len > cap) {
-            if (c > cs) *out++ = make_uint2(head, c - head);
-            head = c;
-            acc = len;
-        } else {
-            acc += len;
-        }
-    }
-    if (ce > cs) *out = make_uint2(head, ce - head);
+    walk([&](uint32_t h, uint32_t e) { *out++ = make_uint2(h, e - h); });
 }
 
 // ---------------------------------------------------------------------------
@@ -441,35 +449,6 @@ __global__ __launch_bounds__(256) void chunk_bbox_kernel(const int64_t *__restri
 }
 
 // ---------------------------------------------------------------------------
-// per-plane bound on one tap weight's real and imaginary parts: max |tap
-// component| of the plane (W-projection), or max |tap|^2 (separable, whose
-// weight is the product of two taps)
-// ---------------------------------------------------------------------------
-template <typename TapT>
-__device__ inline float tap_abs(const TapT *t, int64_t i) {
-    return fabsf(TapTraits<TapT>::real(t, i));
-}
-
-template <typename TapT>
-__global__ __launch_bounds__(256) void plane_wmax_kernel(PlaneLayout *planes, const TapT *taps,
-                                                         int32_t beta, int32_t separable) {
-    __shared__ float s_max[256];
-    PlaneLayout &pl = planes[blockIdx.x];
-    const int64_t w = (int64_t)beta * pl.S;   // taps per axis in the plan's table
-    const int64_t n = separable ? w : 2 * w * w;       // real values
-    const int64_t first = separable ? 0 : 2 * (int64_t)pl.tap_off;
-    float m = 0.0f;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, tap_abs(taps, first + i));
-    s_max[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) s_max[threadIdx.x] = fmaxf(s_max[threadIdx.x], s_max[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) pl.wmax = separable ? s_max[0] * s_max[0] : s_max[0];
-}
-
-// ---------------------------------------------------------------------------
 // compute_indices: the index rule written out per record (parity/debug)
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -528,8 +507,10 @@ hipError_t malloc_bytes(PlanState &P, T **p, size_t bytes, hipStream_t s) {
 // (beta S + 1) + (o_u + 1 + i beta) of the caller's plane; for W-projection
 // (complex entries, (re, im) pairs of T) its conjugate also goes to
 // conj_base + the same index.  Separable: entry (o, i) takes o + 1 + i beta.
+// Also raises planes[p].tmax to the largest |component| copied (the plane
+// layouts arrive with tmax = 0; non-negative floats order like their bits).
 template <typename T>
-__global__ __launch_bounds__(256) void tap_layout_kernel(const PlaneLayout *__restrict__ planes,
+__global__ __launch_bounds__(256) void tap_layout_kernel(PlaneLayout *__restrict__ planes,
                                                          int32_t beta, int32_t wproj,
                                                          const T *__restrict__ src,
                                                          T *__restrict__ dst, int64_t conj_base) {
@@ -537,6 +518,7 @@ __global__ __launch_bounds__(256) void tap_layout_kernel(const PlaneLayout *__re
     const int64_t S = pl.S;
     const int64_t ws = (int64_t)beta * S + 1;   // caller's row length
     const int64_t n = wproj ? (int64_t)beta * beta * S * S : (int64_t)beta * S;
+    float m = 0.0f;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e % S;
@@ -551,11 +533,17 @@ __global__ __launch_bounds__(256) void tap_layout_kernel(const PlaneLayout *__re
             dst[2 * d + 1] = im;
             dst[2 * (conj_base + d)] = re;
             dst[2 * (conj_base + d) + 1] = -im;
+            m = fmaxf(m, fmaxf(fabsf(TapTraits<T>::real(&re, 0)), fabsf(TapTraits<T>::real(&im, 0))));
         } else {
             const int64_t o = e / S;
-            dst[d] = src[o + 1 + i * beta];
+            const T t = src[o + 1 + i * beta];
+            dst[d] = t;
+            m = fmaxf(m, fabsf(TapTraits<T>::real(&t, 0)));
         }
     }
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0 && m > 0.0f)
+        atomicMax(reinterpret_cast<unsigned int *>(&planes[blockIdx.y].tmax), __float_as_uint(m));
 }
 
 }  // namespace
@@ -705,18 +693,6 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
                                stream, P.d_planes, p, P.bucket_cfirst, P.chunks, R, P.units,
                                P.group_nunits);
         }
-    }
-    {
-        const int sep = P.kind == MG_KERNEL_SEPARABLE ? 1 : 0;
-        if (P.tap_dtype == MG_F16)
-            hipLaunchKernelGGL(plane_wmax_kernel<__half>, dim3(np), dim3(256), 0, stream,
-                               P.d_planes, (const __half *)P.taps, P.geom.beta, sep);
-        else if (P.tap_dtype == MG_BF16)
-            hipLaunchKernelGGL(plane_wmax_kernel<__hip_bfloat16>, dim3(np), dim3(256), 0, stream,
-                               P.d_planes, (const __hip_bfloat16 *)P.taps, P.geom.beta, sep);
-        else
-            hipLaunchKernelGGL(plane_wmax_kernel<float>, dim3(np), dim3(256), 0, stream,
-                               P.d_planes, (const float *)P.taps, P.geom.beta, sep);
     }
     e = hipGetLastError();
     hipFreeAsync(meta, stream);
