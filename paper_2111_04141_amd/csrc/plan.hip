@@ -52,13 +52,31 @@ __device__ inline uint32_t wave_counter_add(uint32_t *counters, uint32_t key, bo
 }
 
 // ---------------------------------------------------------------------------
-// index rule -> packed meta, bucket id, bucket histogram, skipped count
+// index rule -> bucket histogram and skipped count; the scatter evaluates the
+// rule again (reading uvw costs what storing and re-reading its results
+// would, and saves writing them)
 // ---------------------------------------------------------------------------
+// Packed meta and bucket of record r (bucket kInvalidBucket if skipped).
+template <typename T>
+__device__ inline RecIndex index_bucket(const DevGeom &g, const PlaneLayout *planes,
+                                        const T *uvw, int64_t r, uint32_t *bucket) {
+    const RecIndex ix = index_record<T>(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2]);
+    uint32_t b = kInvalidBucket;
+    if (ix.valid) {
+        const int p = ix.plane < 0 ? 0 : ix.plane;
+        const PlaneLayout pl = planes[p];
+        const uint32_t tu = (uint32_t)ix.ku >> pl.log2T;
+        const uint32_t tv = (uint32_t)ix.kv >> pl.log2T;
+        b = (uint32_t)(pl.base + ((int64_t)tv * pl.ntu + tu) * pl.grp_n + (p - pl.grp_first));
+    }
+    *bucket = b;
+    return ix;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void index_bucket_kernel(
     DevGeom g, const PlaneLayout *__restrict__ planes, int64_t nrec, const T *__restrict__ uvw,
-    RecMeta *__restrict__ meta, uint32_t *__restrict__ bucket_of, uint32_t *__restrict__ hist,
-    int64_t *__restrict__ counters) {
+    uint32_t *__restrict__ hist, int64_t *__restrict__ counters) {
     __shared__ uint32_t s_skip;
     if (threadIdx.x == 0) s_skip = 0;
     __syncthreads();
@@ -70,24 +88,10 @@ __global__ __launch_bounds__(256) void index_bucket_kernel(
     for (int64_t r0 = first; r0 < nrec; r0 += stride) {
         const int64_t r = r0 + (threadIdx.x & 63);
         const bool in = r < nrec;
-        RecIndex ix;
-        ix.valid = 0;
-        if (in) ix = index_record<T>(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2]);
         uint32_t b = kInvalidBucket;
-        if (ix.valid) {
-            const int p = ix.plane < 0 ? 0 : ix.plane;
-            const PlaneLayout pl = planes[p];
-            uint32_t tu = (uint32_t)ix.ku >> pl.log2T;
-            uint32_t tv = (uint32_t)ix.kv >> pl.log2T;
-            b = (uint32_t)(pl.base + ((int64_t)tv * pl.ntu + tu) * pl.grp_n + (p - pl.grp_first));
-        } else if (in) {
-            ++skipped;
-        }
-        wave_counter_add(hist, b, ix.valid != 0, false);
-        if (in) {
-            meta[r] = pack_meta(g, ix);
-            bucket_of[r] = b;
-        }
+        if (in) index_bucket<T>(g, planes, uvw, r, &b);
+        if (in && b == kInvalidBucket) ++skipped;
+        wave_counter_add(hist, b, b != kInvalidBucket, false);
     }
     if (skipped) atomicAdd(&s_skip, skipped);
     __syncthreads();
@@ -188,9 +192,10 @@ __global__ __launch_bounds__(256) void scan_down_kernel(const uint32_t *__restri
 // ---------------------------------------------------------------------------
 // Valid records go to their bucket's slots; skipped records follow all valid
 // ones (sperm only: their outputs are zeroed by the degridder).
-__global__ __launch_bounds__(256) void scatter_kernel(int64_t nrec,
-                                                      const RecMeta *__restrict__ meta,
-                                                      const uint32_t *__restrict__ bucket_of,
+template <typename T>
+__global__ __launch_bounds__(256) void scatter_kernel(DevGeom g,
+                                                      const PlaneLayout *__restrict__ planes,
+                                                      int64_t nrec, const T *__restrict__ uvw,
                                                       uint32_t *__restrict__ cursor,
                                                       const uint2 *__restrict__ total,
                                                       int64_t *__restrict__ counters,
@@ -201,11 +206,13 @@ __global__ __launch_bounds__(256) void scatter_kernel(int64_t nrec,
     const int64_t nvalid = (int64_t)total->x;
     for (int64_t r0 = first; r0 < nrec; r0 += stride) {
         const int64_t r = r0 + (threadIdx.x & 63);
-        const uint32_t b = (r < nrec) ? bucket_of[r] : kInvalidBucket;
+        uint32_t b = kInvalidBucket;
+        RecIndex ix;
+        if (r < nrec) ix = index_bucket<T>(g, planes, uvw, r, &b);
         const bool act = b != kInvalidBucket;
         const uint32_t pos = wave_counter_add(cursor, b, act, true);
         if (act) {
-            smeta[pos] = meta[r];
+            smeta[pos] = pack_meta(g, ix);
             sperm[pos] = (uint32_t)r;
         } else if (r < nrec) {
             const int64_t q = nvalid + (int64_t)atomicAdd((unsigned long long *)&counters[3], 1ull);
@@ -618,15 +625,12 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         (e = malloc_bytes(P, &P.counters, sizeof(int64_t) * 6, stream)))
         return set_error(MG_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
     // temporaries (stream-ordered)
-    RecMeta *meta = nullptr;
-    uint32_t *bucket_of = nullptr, *hist = nullptr, *bstart = nullptr, *cursor = nullptr;
+    uint32_t *hist = nullptr, *bstart = nullptr, *cursor = nullptr;
     uint32_t *cstart = P.bucket_cfirst;   // kept: first chunk of each bucket
     uint2 *sums = nullptr;
     const int64_t nscan = (nb + kScanBlock - 1) / kScanBlock;
     auto tmp = [&](void **p, size_t bytes) { return hipMallocAsync(p, bytes, stream); };
-    if ((e = tmp((void **)&meta, sizeof(RecMeta) * (size_t)(nrec + 1))) ||
-        (e = tmp((void **)&bucket_of, sizeof(uint32_t) * (size_t)(nrec + 1))) ||
-        (e = tmp((void **)&hist, sizeof(uint32_t) * (size_t)nb)) ||
+    if ((e = tmp((void **)&hist, sizeof(uint32_t) * (size_t)nb)) ||
         (e = tmp((void **)&bstart, sizeof(uint32_t) * (size_t)nb)) ||
         (e = tmp((void **)&cursor, sizeof(uint32_t) * (size_t)nb)) ||
         (e = tmp((void **)&sums, sizeof(uint2) * (size_t)(nscan + 1))))
@@ -643,22 +647,27 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         int g1 = grid_blocks(nrec, 256);
         if (uvw_dtype == MG_F32)
             hipLaunchKernelGGL(index_bucket_kernel<float>, dim3(g1), dim3(256), 0, stream, P.geom,
-                               P.d_planes, nrec, (const float *)uvw, meta, bucket_of, hist,
-                               P.counters);
+                               P.d_planes, nrec, (const float *)uvw, hist, P.counters);
         else
             hipLaunchKernelGGL(index_bucket_kernel<double>, dim3(g1), dim3(256), 0, stream,
-                               P.geom, P.d_planes, nrec, (const double *)uvw, meta, bucket_of,
-                               hist, P.counters);
+                               P.geom, P.d_planes, nrec, (const double *)uvw, hist, P.counters);
     }
     hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nscan), dim3(256), 0, stream, hist, nb,
                        R, sums);
     hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, stream, sums, nscan, sums + nscan);
     hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nscan), dim3(256), 0, stream, hist, nb, R,
                        sums, bstart, cursor, cstart);
-    if (nrec > 0)
-        hipLaunchKernelGGL(scatter_kernel, dim3(grid_blocks(nrec, 256)), dim3(256), 0, stream,
-                           nrec, meta, bucket_of, cursor, sums + nscan, P.counters, P.smeta,
-                           P.sperm);
+    if (nrec > 0) {
+        const dim3 g1(grid_blocks(nrec, 256));
+        if (uvw_dtype == MG_F32)
+            hipLaunchKernelGGL(scatter_kernel<float>, g1, dim3(256), 0, stream, P.geom, P.d_planes,
+                               nrec, (const float *)uvw, cursor, sums + nscan, P.counters, P.smeta,
+                               P.sperm);
+        else
+            hipLaunchKernelGGL(scatter_kernel<double>, g1, dim3(256), 0, stream, P.geom,
+                               P.d_planes, nrec, (const double *)uvw, cursor, sums + nscan,
+                               P.counters, P.smeta, P.sperm);
+    }
     hipLaunchKernelGGL(chunk_list_kernel, dim3(grid_blocks(nb, 256)), dim3(256), 0, stream, nb, R,
                        hist, bstart, cstart, P.chunks);
     hipLaunchKernelGGL(plane_ranges_kernel, dim3(1), dim3(256), 0, stream, np, P.d_planes, nb,
@@ -695,8 +704,6 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         }
     }
     e = hipGetLastError();
-    hipFreeAsync(meta, stream);
-    hipFreeAsync(bucket_of, stream);
     hipFreeAsync(hist, stream);
     hipFreeAsync(bstart, stream);
     hipFreeAsync(cursor, stream);

@@ -84,10 +84,10 @@ size_t job_footprint(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nre
     // the plan's table (no larger than the caller's) and its conjugate copy
     const size_t taps = (size_t)k->ntaps * dtype_bytes(k->tap_dtype) *
                         (k->kind == MG_KERNEL_WPROJ ? 4 : 1);
-    // per record: meta, bucket, sorted meta, permutation, sorted visibilities;
-    // per bucket: count, start, cursor, first chunk, chunk, unit; per R-chunk
-    // (R >= 64): chunk, unit
-    const size_t scratch = n * (8 + 4 + 8 + 4 + 32) + nb * (4 * 4 + 16 + 8) +
+    // per record: sorted meta, permutation, sorted visibilities; per bucket:
+    // count, start, cursor, first chunk, chunk, unit; per R-chunk (R >= 64):
+    // chunk, unit
+    const size_t scratch = n * (8 + 4 + 32) + nb * (4 * 4 + 16 + 8) +
                            (n / 64 + 1) * 24 + (1u << 20);
     return caller + taps + scratch;
 }
