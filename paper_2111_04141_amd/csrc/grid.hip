@@ -234,164 +234,178 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
             const uint32_t su_step = kElem;
             const uint32_t sv_step = SEP ? kElem : (uint32_t)S * kElem;
 
-            // this wave's slots: member * q + k * 64 + lane; per-lane flags
-            // are bit fields (bit k = slot k)
+            // this wave's slots: member * q + k * 64 + lane (q = ceil(S^2 / TEAM));
+            // per-lane flags are bit fields (bit k = slot k).  The slot count
+            // per lane, KD = ceil(q / 64), is a compile-time constant of each
+            // instance of the chunk's loop.
             const int nslots = S * S;
             const int q_ = (nslots + TEAM - 1) / TEAM;
-            const int kdyn = (q_ + kWave - 1) / kWave;
-            uint32_t cell[KMAX], lo[KMAX], lov[KMAX], suv[KMAX];
-            uint32_t valid_bits = 0;
-            float acc[KMAX][8];
+            auto run = [&](auto kd_t) {
+                constexpr int KD = decltype(kd_t)::value;
+                uint32_t cell[KD], lo[KD], lov[KD], suv[KD];
+                uint32_t valid_bits = 0;
+                float acc[KD][8];
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                const int j = k * kWave + lane;
-                const uint32_t sidx = (uint32_t)(member * q_ + j);
-                if (k < kdyn && j < q_ && sidx < (uint32_t)nslots) valid_bits |= 1u << k;
-                // slot (su, sv) owns the cells congruent to it mod S
-                const uint32_t sv = sidx / (uint32_t)S;
-                suv[k] = (sidx - sv * (uint32_t)S) | (sv << 16);
-                cell[k] = kNoCell;
-                lo[k] = 0u;
-                lov[k] = 0u;
+                for (int k = 0; k < KD; ++k) {
+                    const int j = k * kWave + lane;
+                    const uint32_t sidx = (uint32_t)(member * q_ + j);
+                    if (j < q_ && sidx < (uint32_t)nslots) valid_bits |= 1u << k;
+                    // slot (su, sv) owns the cells congruent to it mod S
+                    const uint32_t sv = sidx / (uint32_t)S;
+                    suv[k] = (sidx - sv * (uint32_t)S) | (sv << 16);
+                    cell[k] = kNoCell;
+                    lo[k] = 0u;
+                    lov[k] = 0u;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-            }
+                    for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
+                }
 
-            // window of the current footprint: slots whose cell left it commit
-            // and take the cell congruent to them inside the new footprint
-            uint32_t prev_kuv = 0xffffffffu;
-            uint32_t ru = 0, rv = 0;   // the record's offset terms (bytes, modulo 2^32)
-            auto window_update = [&](const RecMeta m) {
-                const uint32_t kuv = m.kuv;
-                if (kuv == prev_kuv) return;
-                prev_kuv = kuv;
-                const uint32_t ku = meta_ku(m), kv = meta_kv(m);
-                uint32_t moved_bits = 0;
+                // window of the current footprint: slots whose cell left it commit
+                // and take the cell congruent to them inside the new footprint
+                uint32_t prev_kuv = 0xffffffffu;
+                uint32_t ru = 0, rv = 0;   // the record's offset terms (bytes, modulo 2^32)
+                auto window_update = [&](const RecMeta m) {
+                    const uint32_t kuv = m.kuv;
+                    if (kuv == prev_kuv) return;
+                    prev_kuv = kuv;
+                    const uint32_t ku = meta_ku(m), kv = meta_kv(m);
+                    uint32_t moved_bits = 0;
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (k < kdyn) {
+                    for (int k = 0; k < KD; ++k) {
                         const uint32_t d = cell[k] - kuv;   // a borrow only where du < 0
                         if (max(d & 0xffffu, d >> 16) >= (uint32_t)S) moved_bits |= 1u << k;
                     }
-                }
-                moved_bits &= valid_bits;
-                if (__ballot(moved_bits != 0) != 0) {
-                    const uint32_t kmu = ku % (uint32_t)S, kmv = kv % (uint32_t)S;
+                    moved_bits &= valid_bits;
+                    if (__ballot(moved_bits != 0) != 0) {
+                        const uint32_t kmu = ku % (uint32_t)S, kmv = kv % (uint32_t)S;
 #pragma unroll
-                    for (int k = 0; k < KMAX; ++k) {
-                        if (k < kdyn && ((moved_bits >> k) & 1u)) {
-                            if (cell[k] != kNoCell) commit(acc[k], cell[k]);
+                        for (int k = 0; k < KD; ++k) {
+                            if ((moved_bits >> k) & 1u) {
+                                if (cell[k] != kNoCell) commit(acc[k], cell[k]);
 #pragma unroll
-                            for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-                            int du = (int)(suv[k] & 0xffffu) - (int)kmu;
-                            int dv = (int)(suv[k] >> 16) - (int)kmv;
-                            du += (du < 0) ? S : 0;
-                            dv += (dv < 0) ? S : 0;
-                            const uint32_t nu_ = ku + (uint32_t)du, nv_ = kv + (uint32_t)dv;
-                            cell[k] = nu_ | (nv_ << 16);
-                            if constexpr (SEP) {
-                                lo[k] = nu_ * su_step;
-                                lov[k] = nv_ * sv_step;
-                            } else {
-                                lo[k] = nv_ * sv_step + nu_ * su_step;
+                                for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
+                                int du = (int)(suv[k] & 0xffffu) - (int)kmu;
+                                int dv = (int)(suv[k] >> 16) - (int)kmv;
+                                du += (du < 0) ? S : 0;
+                                dv += (dv < 0) ? S : 0;
+                                const uint32_t nu_ = ku + (uint32_t)du, nv_ = kv + (uint32_t)dv;
+                                cell[k] = nu_ | (nv_ << 16);
+                                if constexpr (SEP) {
+                                    lo[k] = nu_ * su_step;
+                                    lov[k] = nv_ * sv_step;
+                                } else {
+                                    lo[k] = nv_ * sv_step + nu_ * su_step;
+                                }
                             }
                         }
                     }
-                }
-                if constexpr (SEP) {
-                    ru = ku * su_step;
-                    rv = kv * sv_step;
-                } else {
-                    ru = kv * sv_step + ku * su_step;
-                }
-                // lanes without a slot read the footprint's first tap: their
-                // offset term follows the record's
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (k < kdyn && !((valid_bits >> k) & 1u)) {
-                        lo[k] = ru;
-                        lov[k] = rv;
+                    if constexpr (SEP) {
+                        ru = ku * su_step;
+                        rv = kv * sv_step;
+                    } else {
+                        ru = kv * sv_step + ku * su_step;
                     }
-                }
-            };
-
-            // tap of slot k for a record (uniform base + 32-bit lane offset)
-            auto tap = [&](const RecMeta m, const int k) {
-                if constexpr (SEP) {
-                    const char *tu = tbase + (size_t)(m.toff & 0xffffu) * kElem;
-                    const char *tv = tbase + (size_t)(m.toff >> 16) * kElem;
-                    const uint32_t ou = lo[k] - ru, ov = lov[k] - rv;
-                    return make_float2(TapTraits<TapT>::real((const TapT *)(tu + ou), 0) *
-                                           TapTraits<TapT>::real((const TapT *)(tv + ov), 0),
-                                       0.0f);
-                } else {
-                    const char *tb = tbase + (size_t)m.toff * kElem;
-                    return TapTraits<TapT>::cplx((const TapT *)(tb + (lo[k] - ru)), 0);
-                }
-            };
-            auto madd = [&](const int k, const float2 w, const RecVis &f) {
-                if constexpr (SEP)
-                    fma_real(acc[k], w.x, f);
-                else
-                    fma_complex(acc[k], w, f);
-            };
-
-            const uint32_t len = ch.len;
-            const uint32_t rb = ch.start + (uint32_t)(((uint64_t)len * team) / NTEAMS);
-            const uint32_t re = ch.start + (uint32_t)(((uint64_t)len * (team + 1)) / NTEAMS);
-            if (rb < re) {
-                // records are read in batches on the scalar unit; the next
-                // batch's loads are issued after the current batch has been
-                // consumed (scalar loads complete out of order: waiting for
-                // one is waiting for all), so they overlap the current
-                // batch's multiply-adds
-                RecMeta nm[kBatch];
-                float4 na4[kBatch], nb4[kBatch];
-                // the record arrays are padded (kRecPad entries), so a batch
-                // may run past the chunk's end (those records are not used)
-                const RecMeta *pm = smeta + rb;
-                const float4 *pv = svis + 2 * (size_t)rb;
-                auto load_batch = [&]() {
+                    // lanes without a slot read the footprint's first tap: their
+                    // offset term follows the record's
 #pragma unroll
-                    for (int i = 0; i < kBatch; ++i) {
-                        nm[i] = pm[i];
-                        na4[i] = pv[2 * i];
-                        nb4[i] = pv[2 * i + 1];
-                    }
-                    pm += kBatch;
-                    pv += 2 * kBatch;
-                };
-                load_batch();
-                for (uint32_t r = rb; r < re; r += kBatch) {
-                    RecMeta mm[kBatch];
-                    float4 va4[kBatch], vb4[kBatch];
-#pragma unroll
-                    for (int i = 0; i < kBatch; ++i) {
-                        mm[i] = nm[i];
-                        va4[i] = na4[i];
-                        vb4[i] = nb4[i];
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                    load_batch();
-#pragma unroll
-                    for (int i = 0; i < kBatch; ++i) {
-                        if (r + (uint32_t)i < re) {
-                            window_update(mm[i]);
-                            const RecVis f = unpack_vis(va4[i], vb4[i]);
-                            float2 w[KMAX];
-#pragma unroll
-                            for (int k = 0; k < KMAX; ++k)
-                                if (k < kdyn) w[k] = tap(mm[i], k);
-#pragma unroll
-                            for (int k = 0; k < KMAX; ++k)
-                                if (k < kdyn) madd(k, w[k], f);
+                    for (int k = 0; k < KD; ++k) {
+                        if (!((valid_bits >> k) & 1u)) {
+                            lo[k] = ru;
+                            lov[k] = rv;
                         }
                     }
-                }
+                };
+
+                // tap of slot k for a record (uniform base + 32-bit lane offset)
+                auto tap = [&](const RecMeta m, const int k) {
+                    if constexpr (SEP) {
+                        const char *tu = tbase + (size_t)(m.toff & 0xffffu) * kElem;
+                        const char *tv = tbase + (size_t)(m.toff >> 16) * kElem;
+                        const uint32_t ou = lo[k] - ru, ov = lov[k] - rv;
+                        return make_float2(TapTraits<TapT>::real((const TapT *)(tu + ou), 0) *
+                                               TapTraits<TapT>::real((const TapT *)(tv + ov), 0),
+                                           0.0f);
+                    } else {
+                        const char *tb = tbase + (size_t)m.toff * kElem;
+                        return TapTraits<TapT>::cplx((const TapT *)(tb + (lo[k] - ru)), 0);
+                    }
+                };
+                auto madd = [&](const int k, const float2 w, const RecVis &f) {
+                    if constexpr (SEP)
+                        fma_real(acc[k], w.x, f);
+                    else
+                        fma_complex(acc[k], w, f);
+                };
+
+                const uint32_t len = ch.len;
+                const uint32_t rb = ch.start + (uint32_t)(((uint64_t)len * team) / NTEAMS);
+                const uint32_t re = ch.start + (uint32_t)(((uint64_t)len * (team + 1)) / NTEAMS);
+                if (rb < re) {
+                    // records are read in batches on the scalar unit; the next
+                    // batch's loads are issued after the current batch has been
+                    // consumed (scalar loads complete out of order: waiting for
+                    // one is waiting for all), so they overlap the current
+                    // batch's multiply-adds
+                    RecMeta nm[kBatch];
+                    float4 na4[kBatch], nb4[kBatch];
+                    // the record arrays are padded (kRecPad entries), so a batch
+                    // may run past the chunk's end (those records are not used)
+                    const RecMeta *pm = smeta + rb;
+                    const float4 *pv = svis + 2 * (size_t)rb;
+                    auto load_batch = [&]() {
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    if (k < kdyn && ((valid_bits >> k) & 1u) && cell[k] != kNoCell)
-                        commit(acc[k], cell[k]);
+                        for (int i = 0; i < kBatch; ++i) {
+                            nm[i] = pm[i];
+                            na4[i] = pv[2 * i];
+                            nb4[i] = pv[2 * i + 1];
+                        }
+                        pm += kBatch;
+                        pv += 2 * kBatch;
+                    };
+                    load_batch();
+                    for (uint32_t r = rb; r < re; r += kBatch) {
+                        RecMeta mm[kBatch];
+                        float4 va4[kBatch], vb4[kBatch];
+#pragma unroll
+                        for (int i = 0; i < kBatch; ++i) {
+                            mm[i] = nm[i];
+                            va4[i] = na4[i];
+                            vb4[i] = nb4[i];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                        load_batch();
+#pragma unroll
+                        for (int i = 0; i < kBatch; ++i) {
+                            if (r + (uint32_t)i < re) {
+                                window_update(mm[i]);
+                                const RecVis f = unpack_vis(va4[i], vb4[i]);
+                                float2 w[KD];
+#pragma unroll
+                                for (int k = 0; k < KD; ++k)
+                                    w[k] = tap(mm[i], k);
+#pragma unroll
+                                for (int k = 0; k < KD; ++k)
+                                    madd(k, w[k], f);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < KD; ++k)
+                        if (((valid_bits >> k) & 1u) && cell[k] != kNoCell)
+                            commit(acc[k], cell[k]);
+                }
+            };
+            const int kdyn = (q_ + kWave - 1) / kWave;
+            if constexpr (KMAX == 1) {
+                run(std::integral_constant<int, 1>{});
+            } else {
+                static_assert(KMAX == 4, "slot counts 1..4");
+                switch (kdyn) {
+                case 1: run(std::integral_constant<int, 1>{}); break;
+                case 2: run(std::integral_constant<int, 2>{}); break;
+                case 3: run(std::integral_constant<int, 3>{}); break;
+                default: run(std::integral_constant<int, 4>{}); break;
+                }
             }
         }
 
