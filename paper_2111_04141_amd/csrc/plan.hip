@@ -335,12 +335,18 @@ __global__ __launch_bounds__(256) void unit_list_kernel(const PlaneLayout *__res
 }
 
 // ---------------------------------------------------------------------------
-// per-chunk counting sort by cell inside the tile, column-major (u outer,
-// v inner: consecutive records step along v, so a moving window retires one
-// row of slots at a time), in LDS;
-// also records the chunk's k_lo bounding box
+// per-chunk counting sort by cell inside the tile, in LDS: column by column
+// (u outer), v running up and down in alternate columns, so consecutive
+// records step by one cell and a moving window retires one row or column of
+// slots at a time (a plain column-major order would retire most slots at
+// every column change)
 // ---------------------------------------------------------------------------
 constexpr int kMaxR = 2048;
+
+__device__ inline uint32_t cell_key(uint32_t du, uint32_t dv, int log2T) {
+    const uint32_t vv = (du & 1u) ? ((1u << log2T) - 1u - dv) : dv;
+    return (du << log2T) | vv;
+}
 
 
 __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restrict__ plane_cfirst,
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restr
             m_in[i] = m;
             p_in[i] = sperm[ch.start + i];
             uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
-            atomicAdd(&hist[(du << pl.log2T) | dv], 1u);
+            atomicAdd(&hist[cell_key(du, dv, pl.log2T)], 1u);
         }
         __syncthreads();
         {
@@ -398,7 +404,7 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restr
         for (uint32_t i = threadIdx.x; i < ch.len; i += blockDim.x) {
             RecMeta m = m_in[i];
             uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
-            uint32_t pos = atomicAdd(&hist[(du << pl.log2T) | dv], 1u);
+            uint32_t pos = atomicAdd(&hist[cell_key(du, dv, pl.log2T)], 1u);
             smeta[ch.start + pos] = m;
             sperm[ch.start + pos] = p_in[i];
         }
