@@ -355,6 +355,59 @@ __device__ inline uint32_t cell_key(uint32_t du, uint32_t dv, int log2T) {
 }
 
 
+// Chunks of at most kWaveSortMax records: one wave per chunk sorts the
+// (cell key, lane) pairs with a bitonic network across its lanes, then each
+// lane fetches the record of its rank; no LDS and no barriers.  Larger
+// chunks take the workgroup counting sort below.
+constexpr uint32_t kWaveSortMax = 64;
+
+__global__ __launch_bounds__(256) void chunk_sort_small_kernel(
+    const uint32_t *__restrict__ plane_cfirst, int32_t p_split,
+    const PlaneLayout *__restrict__ planes, const Chunk *__restrict__ chunks,
+    RecMeta *__restrict__ smeta, uint32_t *__restrict__ sperm) {
+    const uint32_t c_end = plane_cfirst[p_split];
+    const int lane = threadIdx.x & 63;
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    int p = 0;   // chunks come in increasing order: the plane only moves forward
+    for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < c_end;
+         c += nwaves) {
+        const Chunk ch = chunks[c];
+        if (ch.len < 2 || ch.len > kWaveSortMax) continue;
+        while (p + 1 < p_split && c >= plane_cfirst[p + 1]) ++p;
+        int pp;
+        uint32_t tile;
+        bucket_plane_tile(planes[p], ch.bucket, &pp, &tile);
+        const PlaneLayout pl = planes[pp];
+        const uint32_t tu0 = (tile % (uint32_t)pl.ntu) << pl.log2T;
+        const uint32_t tv0 = (tile / (uint32_t)pl.ntu) << pl.log2T;
+        RecMeta m{0u, 0u};
+        uint32_t perm = 0u;
+        uint32_t v = 0xffffffffu;   // lanes past the chunk sort last
+        if ((uint32_t)lane < ch.len) {
+            m = smeta[ch.start + lane];
+            perm = sperm[ch.start + lane];
+            v = (cell_key(meta_ku(m) - tu0, meta_kv(m) - tv0, pl.log2T) << 6) | (uint32_t)lane;
+        }
+#pragma unroll
+        for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const uint32_t o = (uint32_t)__shfl_xor((int)v, j, 64);
+                const bool take_min = ((lane & j) == 0) == ((lane & k) == 0);
+                v = take_min ? min(v, o) : max(v, o);
+            }
+        }
+        const int src = (int)(v & 63u);
+        const uint32_t kuv = (uint32_t)__shfl((int)m.kuv, src, 64);
+        const uint32_t toff = (uint32_t)__shfl((int)m.toff, src, 64);
+        const uint32_t pr = (uint32_t)__shfl((int)perm, src, 64);
+        if ((uint32_t)lane < ch.len) {
+            smeta[ch.start + lane] = RecMeta{kuv, toff};
+            sperm[ch.start + lane] = pr;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restrict__ plane_cfirst,
                                                          int32_t p_split,
                                                          const PlaneLayout *__restrict__ planes,
@@ -370,6 +423,7 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restr
     int p = 0;   // chunks come in increasing order: the plane only moves forward
     for (uint32_t c = blockIdx.x; c < c_end; c += gridDim.x) {
         const Chunk ch = chunks[c];
+        if (ch.len <= kWaveSortMax) continue;   // the wave sort's chunks
         while (p + 1 < p_split && c >= plane_cfirst[p + 1]) ++p;
         int pp;
         uint32_t tile;
@@ -699,10 +753,14 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, chunk_sort_kernel, 256, 0) !=
             hipSuccess)
             per = 1;
-        if (p_split > 0)
+        if (p_split > 0) {
+            hipLaunchKernelGGL(chunk_sort_small_kernel, dim3(8 * std::max(1, cus)), dim3(256), 0,
+                               stream, P.plane_cfirst, p_split, P.d_planes, P.chunks, P.smeta,
+                               P.sperm);
             hipLaunchKernelGGL(chunk_sort_kernel, dim3(std::max(1, per) * std::max(1, cus)),
                                dim3(256), 0, stream, P.plane_cfirst, p_split, P.d_planes,
                                P.chunks, P.smeta, P.sperm);
+        }
         hipLaunchKernelGGL(chunk_bbox_kernel, dim3(grid_blocks(P.max_chunks * 64, 256)),
                            dim3(256), 0, stream, P.counters, P.plane_cfirst, np, P.d_planes,
                            P.smeta, P.chunks);
