@@ -296,12 +296,13 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
 }
 
 // Supports up to 32: the lanes of a wave take the taps of one record (tap
-// q = t * 64 + lane, q < S^2), so no lane sits outside a footprint.  The
-// chunk's grid region is staged once in LDS as [row][pol][col] float2 rows
-// of PITCH columns (a row stride of 4 PITCH + 8 float2, 16 banks modulo 64,
-// spreads the rows of a footprint over the LDS banks); the four waves of
-// the workgroup take groups of B records in turn, and each group's sums are
-// reduced across the wave's lanes only.
+// q = t * 64 + lane, q < S^2), so no lane sits outside a footprint.  A
+// workgroup takes a unit (chunks of one tile over the planes of the group);
+// the unit's grid region is staged once in LDS as [row][pol][col] float2
+// rows of PITCH columns (a row stride of 4 PITCH + 8 float2, 16 banks
+// modulo 64, spreads the rows of a footprint over the LDS banks); the four
+// waves of the workgroup take groups of B records in turn, and each group's
+// sums are reduced across the wave's lanes only.
 template <int PITCH>
 constexpr int row_stride() { return 4 * PITCH + 8; }
 
@@ -309,7 +310,8 @@ template <int NTAP, int PITCH, int B, bool SEP, typename TapT>
 __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
     const RecMeta *__restrict__ smeta, const uint32_t *__restrict__ sperm,
     const float *__restrict__ grid, float *__restrict__ vis_out, const TapT *__restrict__ taps,
-    const Chunk *__restrict__ chunks, const uint32_t *__restrict__ plane_cfirst,
+    const Chunk *__restrict__ chunks, const uint32_t *__restrict__ bucket_cfirst,
+    const uint2 *__restrict__ units, const uint32_t *__restrict__ group_nunits,
     const PlaneLayout *__restrict__ planes, uint32_t *__restrict__ queue, DegridParams prm) {
     constexpr int NV = B * 8;
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);
@@ -320,26 +322,42 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int npol = prm.npol;
-    const uint32_t c_begin = plane_cfirst[prm.p_lo];
-    const uint32_t c_end = plane_cfirst[prm.p_hi];
     const char *tbase = reinterpret_cast<const char *>(taps);
     const int my_idx = reduce_index<NV>(lane);
     const bool writer = reduce_writer<NV>(lane);
-    int p = prm.p_lo;
+    // the launch covers one plane group; its work items are the group's
+    // units (chunks of one tile over the group's planes), whose region is
+    // staged once for all their chunks
+    const PlaneLayout gl = planes[prm.p_lo];
+    const uint2 *gunits = units + bucket_cfirst[gl.base];
+    const uint32_t nunits = group_nunits[prm.p_lo];
 
-    for (uint32_t c = c_begin + next_chunk_dg(queue, &s_next); c < c_end;
-         c = c_begin + next_chunk_dg(queue, &s_next)) {
-        const Chunk ch = chunks[c];
-        while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
-        int pc;
+    for (uint32_t it = next_chunk_dg(queue, &s_next); it < nunits;
+         it = next_chunk_dg(queue, &s_next)) {
+        const uint2 un = gunits[it];
+        const uint32_t c0 = un.x, c1 = un.x + un.y;
+        // region: union of the chunks' k_lo ranges extended by their supports
+        uint32_t umin = 0xffu, vmin = 0xffu, uend = 0u, vend = 0u;
+        for (uint32_t c = c0; c < c1; ++c) {
+            const Chunk ch = chunks[c];
+            int pc;
+            uint32_t tile_;
+            bucket_plane_tile(gl, ch.bucket, &pc, &tile_);
+            const uint32_t Sc = (uint32_t)planes[pc].S;
+            umin = min(umin, ch.bbox & 0xffu);
+            vmin = min(vmin, (ch.bbox >> 16) & 0xffu);
+            uend = max(uend, ((ch.bbox >> 8) & 0xffu) + Sc);
+            vend = max(vend, (ch.bbox >> 24) + Sc);
+        }
         uint32_t tile;
-        bucket_plane_tile(planes[p], ch.bucket, &pc, &tile);
-        const PlaneLayout pl = planes[pc];
-        const int S = pl.S;
-        const int cu0 = (int)(((tile % (uint32_t)pl.ntu) << pl.log2T) + (ch.bbox & 0xffu));
-        const int cv0 = (int)(((tile / (uint32_t)pl.ntu) << pl.log2T) + ((ch.bbox >> 16) & 0xffu));
-        const int RW = (int)((ch.bbox >> 8) & 0xffu) - (int)(ch.bbox & 0xffu) + S;
-        const int RH = (int)(ch.bbox >> 24) - (int)((ch.bbox >> 16) & 0xffu) + S;
+        {
+            int pc;
+            bucket_plane_tile(gl, chunks[c0].bucket, &pc, &tile);
+        }
+        const int cu0 = (int)(((tile % (uint32_t)gl.ntu) << gl.log2T) + umin);
+        const int cv0 = (int)(((tile / (uint32_t)gl.ntu) << gl.log2T) + vmin);
+        const int RW = (int)(uend - umin);
+        const int RH = (int)(vend - vmin);
 
         // stage the region (cells outside it are never read)
         for (int i = threadIdx.x; i < npol * RH * RW; i += kGroupThreads) {
@@ -352,132 +370,144 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
         }
         __syncthreads();
 
-        // this lane's taps: LDS offset and table byte offset relative to the
-        // footprint's first cell and first tap.  Taps t < nt - 1 lie in every
-        // footprint; tap nt - 1 only where q < S^2 (the others keep zeros).
-        int lg[NTAP];
-        uint32_t lt[NTAP], ltv[NTAP];
-        const int nt = (S * S + 63) >> 6;
-        const bool last_full = (S * S) % 64 == 0;
-        const bool last_on = ((nt - 1) * 64 + lane) < S * S;
-#pragma unroll
-        for (int t = 0; t < NTAP; ++t) {
-            const int q = t * 64 + lane;
-            const int j = q / S, i = q - (q / S) * S;
-            lg[t] = j * kRowStride + i;
-            if constexpr (SEP) {
-                lt[t] = (uint32_t)i * kElem;
-                ltv[t] = (uint32_t)j * kElem;
-            } else {
-                lt[t] = (uint32_t)(j * S + i) * kElem;
-                ltv[t] = 0u;
-            }
-        }
+        uint32_t turn = 0;   // the wave whose turn it is, over the unit's groups
+        for (uint32_t c = c0; c < c1; ++c) {
+            const Chunk ch = chunks[c];
+            int pc;
+            uint32_t tile_;
+            bucket_plane_tile(gl, ch.bucket, &pc, &tile_);
+            const int S = planes[pc].S;
 
-        // groups of B records, taken by the waves in turn; a short last group
-        // repeats the chunk's last record (its sums are not written)
-        const uint32_t rend = ch.start + ch.len;
-        const uint32_t ngroups = (ch.len + B - 1) / B;
-        for (uint32_t gi = (uint32_t)wave; gi < ngroups; gi += kWavesPerGroup) {
-            const uint32_t r0 = ch.start + gi * B;
-            const uint32_t nb = min((uint32_t)B, rend - r0);
-            float part[NV];
+            // this lane's taps: LDS offset and table byte offset relative to the
+            // footprint's first cell and first tap.  Taps t < nt - 1 lie in every
+            // footprint; tap nt - 1 only where q < S^2 (the others keep zeros).
+            int lg[NTAP];
+            uint32_t lt[NTAP], ltv[NTAP];
+            const int nt = (S * S + 63) >> 6;
+            const bool last_full = (S * S) % 64 == 0;
+            const bool last_on = ((nt - 1) * 64 + lane) < S * S;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) part[i] = 0.0f;
-#pragma unroll
-            for (int bi = 0; bi < B; ++bi) {
-                const RecMeta m = smeta[min(r0 + (uint32_t)bi, rend - 1)];
-                const int sg = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
-                const char *tb;
-                const char *tbv = nullptr;
+            for (int t = 0; t < NTAP; ++t) {
+                const int q = t * 64 + lane;
+                const int j = q / S, i = q - (q / S) * S;
+                lg[t] = j * kRowStride + i;
                 if constexpr (SEP) {
-                    tb = tbase + (size_t)(m.toff & 0xffffu) * kElem;
-                    tbv = tbase + (size_t)(m.toff >> 16) * kElem;
+                    lt[t] = (uint32_t)i * kElem;
+                    ltv[t] = (uint32_t)j * kElem;
                 } else {
-                    tb = tbase + (size_t)m.toff * kElem;
+                    lt[t] = (uint32_t)(j * S + i) * kElem;
+                    ltv[t] = 0u;
                 }
-                if constexpr (NTAP > 4) {
-                    // many taps per lane: one tap at a time (registers)
+            }
+
+            // groups of B records, taken by the waves in turn (continuing
+            // from the unit's previous chunk); a short last group repeats the
+            // chunk's last record (its sums are not written)
+            const uint32_t rend = ch.start + ch.len;
+            const uint32_t ngroups = (ch.len + B - 1) / B;
+            const uint32_t gfirst = ((uint32_t)wave + kWavesPerGroup - turn) % kWavesPerGroup;
+            turn = (turn + ngroups) % kWavesPerGroup;
+            for (uint32_t gi = gfirst; gi < ngroups; gi += kWavesPerGroup) {
+                const uint32_t r0 = ch.start + gi * B;
+                const uint32_t nb = min((uint32_t)B, rend - r0);
+                float part[NV];
 #pragma unroll
-                    for (int t = 0; t < NTAP; ++t) {
-                        if (t >= nt) continue;
-                        if (t == nt - 1 && !last_full && !last_on) continue;
-                        uint32_t o = lt[t];
-                        asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
-                        float2 w;
-                        if constexpr (SEP) {
-                            uint32_t ov = ltv[t];
-                            asm volatile("" : "+v"(ov));
-                            w = make_float2(TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
-                                                TapTraits<TapT>::real((const TapT *)(tbv + ov), 0),
-                                            0.0f);
-                        } else {
-                            w = TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
-                        }
-                        const float2 *gp = region + sg + lg[t];
+                for (int i = 0; i < NV; ++i) part[i] = 0.0f;
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const float2 gq = gp[q * kPitch];
-                            float &ar = part[bi * 8 + 2 * q];
-                            float &ai = part[bi * 8 + 2 * q + 1];
-                            ar = fmaf(w.x, gq.x, fmaf(w.y, gq.y, ar));
-                            ai = fmaf(w.x, gq.y, fmaf(-w.y, gq.x, ai));
-                        }
+                for (int bi = 0; bi < B; ++bi) {
+                    const RecMeta m = smeta[min(r0 + (uint32_t)bi, rend - 1)];
+                    const int sg = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
+                    const char *tb;
+                    const char *tbv = nullptr;
+                    if constexpr (SEP) {
+                        tb = tbase + (size_t)(m.toff & 0xffffu) * kElem;
+                        tbv = tbase + (size_t)(m.toff >> 16) * kElem;
+                    } else {
+                        tb = tbase + (size_t)m.toff * kElem;
                     }
-                } else {
-                    // loads of TB taps, then their multiply-adds
-                    constexpr int TB = NTAP < 4 ? NTAP : 4;
+                    if constexpr (NTAP > 4) {
+                        // many taps per lane: one tap at a time (registers)
 #pragma unroll
-                    for (int t0 = 0; t0 < NTAP; t0 += TB) {
-                        float2 w[TB], gv[TB][4];
-                        auto load = [&](const int t, const int u) {
+                        for (int t = 0; t < NTAP; ++t) {
+                            if (t >= nt) continue;
+                            if (t == nt - 1 && !last_full && !last_on) continue;
                             uint32_t o = lt[t];
                             asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+                            float2 w;
                             if constexpr (SEP) {
                                 uint32_t ov = ltv[t];
                                 asm volatile("" : "+v"(ov));
-                                w[u] = make_float2(TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
-                                                       TapTraits<TapT>::real((const TapT *)(tbv + ov), 0),
-                                                   0.0f);
+                                w = make_float2(TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
+                                                    TapTraits<TapT>::real((const TapT *)(tbv + ov), 0),
+                                                0.0f);
                             } else {
-                                w[u] = TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
+                                w = TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
                             }
                             const float2 *gp = region + sg + lg[t];
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) gv[u][q] = gp[q * kPitch];
-                        };
-#pragma unroll
-                        for (int u = 0; u < TB; ++u) {
-                            const int t = t0 + u;
-                            if (t >= nt) continue;
-                            if (t < nt - 1 || last_full) {
-                                load(t, u);
-                            } else {
-                                w[u] = make_float2(0.0f, 0.0f);
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) gv[u][q] = make_float2(0.0f, 0.0f);
-                                if (last_on) load(t, u);
-                            }
-                        }
-#pragma unroll
-                        for (int u = 0; u < TB; ++u) {
-                            if (t0 + u >= nt) continue;
-#pragma unroll
                             for (int q = 0; q < 4; ++q) {
+                                const float2 gq = gp[q * kPitch];
                                 float &ar = part[bi * 8 + 2 * q];
                                 float &ai = part[bi * 8 + 2 * q + 1];
-                                ar = fmaf(w[u].x, gv[u][q].x, fmaf(w[u].y, gv[u][q].y, ar));
-                                ai = fmaf(w[u].x, gv[u][q].y, fmaf(-w[u].y, gv[u][q].x, ai));
+                                ar = fmaf(w.x, gq.x, fmaf(w.y, gq.y, ar));
+                                ai = fmaf(w.x, gq.y, fmaf(-w.y, gq.x, ai));
+                            }
+                        }
+                    } else {
+                        // loads of TB taps, then their multiply-adds
+                        constexpr int TB = NTAP < 4 ? NTAP : 4;
+#pragma unroll
+                        for (int t0 = 0; t0 < NTAP; t0 += TB) {
+                            float2 w[TB], gv[TB][4];
+                            auto load = [&](const int t, const int u) {
+                                uint32_t o = lt[t];
+                                asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+                                if constexpr (SEP) {
+                                    uint32_t ov = ltv[t];
+                                    asm volatile("" : "+v"(ov));
+                                    w[u] = make_float2(TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
+                                                           TapTraits<TapT>::real((const TapT *)(tbv + ov), 0),
+                                                       0.0f);
+                                } else {
+                                    w[u] = TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
+                                }
+                                const float2 *gp = region + sg + lg[t];
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) gv[u][q] = gp[q * kPitch];
+                            };
+#pragma unroll
+                            for (int u = 0; u < TB; ++u) {
+                                const int t = t0 + u;
+                                if (t >= nt) continue;
+                                if (t < nt - 1 || last_full) {
+                                    load(t, u);
+                                } else {
+                                    w[u] = make_float2(0.0f, 0.0f);
+#pragma unroll
+                                    for (int q = 0; q < 4; ++q) gv[u][q] = make_float2(0.0f, 0.0f);
+                                    if (last_on) load(t, u);
+                                }
+                            }
+#pragma unroll
+                            for (int u = 0; u < TB; ++u) {
+                                if (t0 + u >= nt) continue;
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    float &ar = part[bi * 8 + 2 * q];
+                                    float &ai = part[bi * 8 + 2 * q + 1];
+                                    ar = fmaf(w[u].x, gv[u][q].x, fmaf(w[u].y, gv[u][q].y, ar));
+                                    ai = fmaf(w[u].x, gv[u][q].y, fmaf(-w[u].y, gv[u][q].x, ai));
+                                }
                             }
                         }
                     }
                 }
-            }
-            wave_reduce_scatter<NV>(part, lane);
-            if (writer) {
-                const int bi = my_idx >> 3, q = my_idx & 7;
-                if ((uint32_t)bi < nb && (q >> 1) < npol)
-                    vis_out[((size_t)sperm[r0 + bi] * npol + (q >> 1)) * 2 + (q & 1)] = part[0];
+                wave_reduce_scatter<NV>(part, lane);
+                if (writer) {
+                    const int bi = my_idx >> 3, q = my_idx & 7;
+                    if ((uint32_t)bi < nb && (q >> 1) < npol)
+                        vis_out[((size_t)sperm[r0 + bi] * npol + (q >> 1)) * 2 + (q & 1)] = part[0];
+                }
             }
         }
     }
@@ -510,6 +540,9 @@ struct DegridPtrs {
     const void *taps;
     const Chunk *chunks;
     const uint32_t *plane_cfirst;
+    const uint32_t *bucket_cfirst;
+    const uint2 *units;
+    const uint32_t *group_nunits;
     const PlaneLayout *planes;
     uint32_t *queue;
 };
@@ -547,7 +580,8 @@ hipError_t launch_dt(const DegridPtrs &a, const DegridParams &prm, int tile, int
         per = 1;
     hipLaunchKernelGGL(kern, dim3(std::max(1, per) * std::max(1, cus)), dim3(kGroupThreads), lds,
                        stream, a.smeta, a.sperm, a.grid, a.vis_out, (const TapT *)a.taps,
-                       a.chunks, a.plane_cfirst, a.planes, a.queue, prm);
+                       a.chunks, a.bucket_cfirst, a.units, a.group_nunits, a.planes, a.queue,
+                       prm);
     return hipGetLastError();
 }
 
@@ -587,8 +621,9 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hip
         hipLaunchKernelGGL(zero_skipped_kernel, dim3((unsigned)nb), dim3(256), 0, stream,
                            P.counters, P.nrec, P.sperm, P.geom.npol, (float2 *)vis_out);
     }
-    DegridPtrs a{P.smeta, P.sperm, (const float *)grid, (float *)vis_out, P.taps, P.chunks,
-                 P.plane_cfirst, P.d_planes, nullptr};
+    DegridPtrs a{P.smeta,         P.sperm,          (const float *)grid, (float *)vis_out,
+                 P.taps,          P.chunks,         P.plane_cfirst,      P.bucket_cfirst,
+                 P.units,         P.group_nunits,   P.d_planes,          nullptr};
     DegridParams prm{P.geom.npol, P.geom.nu, P.geom.nv, P.geom.beta, 0, 0};
     const bool sep = P.kind == MG_KERNEL_SEPARABLE;
     // one launch per run of consecutive planes of the same class
