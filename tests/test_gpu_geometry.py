@@ -26,6 +26,11 @@ CASES = [
     ("sep-S24-b4-f16", "sep", 300, 300, 4, [24], 4, "f16"),
     ("wproj-odd-b2", "wproj", 300, 280, 2, [5, 9, 17, 33], 4, "f32"),
     ("wproj-b4-f16", "wproj", 260, 390, 4, [8, 14, 26, 50], 2, "f16"),
+    # several planes per support class: tile-major plane groups and units
+    # spanning planes of different supports
+    ("wproj-groups", "wproj", 300, 260, 2, [6, 8, 10, 12, 16, 18, 24, 32, 34, 48], 4, "f32"),
+    # supports out of order: every plane its own group, classes interleaved
+    ("wproj-unordered", "wproj", 280, 300, 2, [40, 10, 20, 8, 12, 36], 3, "f32"),
 ]
 
 
@@ -35,7 +40,7 @@ def _case(kind, nu, nv, beta, supports, npol, seed):
     smax = max(supports)
     u = rng.uniform(-nu / 2 - 4, nu / 2 + 4, nrec)      # some beyond the edge
     v = rng.uniform(-nv / 2 - 4, nv / 2 + 4, nrec)
-    w = rng.uniform(-3.4, 3.4, nrec)
+    w = rng.uniform(-len(supports) + 0.6, len(supports) - 0.6, nrec)
     # a few records exactly on cell and tie positions
     u[:50] = np.round(u[:50])
     v[50:100] = np.round(v[50:100] * beta) / beta + 0.5 / beta
