@@ -1,31 +1,33 @@
 // Gridding (scatter) kernels.
 //
-// Work unit: one chunk = up to R records of one (plane, uv tile) bucket,
-// taken by one workgroup; chunks are handed out through a per-launch counter.
+// Work unit: a run of chunks (up to R records each) of one uv tile over the
+// planes of a group (consecutive planes of one support class), taken by one
+// workgroup; units are handed out through a per-launch counter.
 //
-// Supports up to 16: moving window (grid_window_kernel).
-//  * Each wave keeps a moving window of S x S slots in registers: slot
-//    (su, sv) owns the grid cells congruent to (su, sv) modulo S, so every
-//    record's S x S footprint holds exactly one cell of each slot, and a
-//    slot's accumulators (4 polarisations, complex) keep summing while its
-//    cell stays inside the footprints of consecutive records.  This is the
+// Supports up to 32: moving window (grid_window_kernel).
+//  * Each wave keeps a moving window of slots in registers: slot (su, sv)
+//    owns the grid cells congruent to (su, sv) modulo S, so every record's
+//    S x S footprint holds exactly one cell of each slot, and a slot's
+//    accumulators (4 polarisations, complex) keep summing while its cell
+//    stays inside the footprints of consecutive records.  This is the
 //    owner-computes scheme of Romein's GPU gridder, which the thesis's
 //    Convolutional Gridder builds on (Chapter 4); the slots are spread over
-//    the 64 lanes of a wave and the records come cell-sorted, so windows
-//    move rarely where records are dense.
+//    the 64 lanes of a wave (up to S = 16) or of a team of four waves (up to
+//    S = 32), and the records come cell-sorted, so windows move rarely where
+//    records are dense.
 //  * When a slot's cell leaves the footprint its sums are committed into an
-//    LDS copy of the chunk's grid region (bounding box plus S-1 halo) shared
-//    by the 4 waves.  The region holds 32-bit fixed point: each chunk first
+//    LDS copy of the unit's grid region (bounding box plus S-1 halo) shared
+//    by the workgroup.  The region holds 32-bit fixed point: each unit first
 //    bounds every partial sum it can produce (2 * max|tap component| * sum
 //    over its records of max|visibility component|) and picks the
 //    power-of-two scale that maps that bound to 2^30, so integer LDS atomics
 //    (which run at full wave rate, unlike float LDS atomics, which serialise
 //    per lane) add the commits exactly and cannot overflow; truncation costs
-//    at most 2^-30 of the bound per commit.  At the end of the chunk the
+//    at most 2^-30 of the bound per commit.  At the end of the unit the
 //    region is converted back to FP32 and added to the grid with float
 //    atomics, one per touched cell.
 //
-// Supports above 16: blocked output-stationary kernel (grid_block_kernel),
+// Supports above 32: blocked output-stationary kernel (grid_block_kernel),
 // for the sparse planes of large |w|; see the kernel's comment.
 //
 // All polarisations are handled per visit: one tap load feeds 4 complex

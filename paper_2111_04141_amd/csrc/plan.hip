@@ -362,32 +362,46 @@ __device__ inline uint32_t cell_key(uint32_t du, uint32_t dv, int log2T) {
 constexpr uint32_t kWaveSortMax = 64;
 
 __global__ __launch_bounds__(256) void chunk_sort_small_kernel(
-    const uint32_t *__restrict__ plane_cfirst, int32_t p_split,
-    const PlaneLayout *__restrict__ planes, const Chunk *__restrict__ chunks,
+    const uint32_t *__restrict__ plane_cfirst, int32_t nplanes,
+    const PlaneLayout *__restrict__ planes, Chunk *__restrict__ chunks,
     RecMeta *__restrict__ smeta, uint32_t *__restrict__ sperm) {
-    const uint32_t c_end = plane_cfirst[p_split];
+    const uint32_t c_end = plane_cfirst[nplanes];
     const int lane = threadIdx.x & 63;
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
     int p = 0;   // chunks come in increasing order: the plane only moves forward
     for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < c_end;
          c += nwaves) {
         const Chunk ch = chunks[c];
-        if (ch.len < 2 || ch.len > kWaveSortMax) continue;
-        while (p + 1 < p_split && c >= plane_cfirst[p + 1]) ++p;
+        if (ch.len > kWaveSortMax) continue;
+        while (p + 1 < nplanes && c >= plane_cfirst[p + 1]) ++p;
         int pp;
         uint32_t tile;
         bucket_plane_tile(planes[p], ch.bucket, &pp, &tile);
         const PlaneLayout pl = planes[pp];
+        if (pl.cls >= 3) continue;   // the blocked kernels need neither
         const uint32_t tu0 = (tile % (uint32_t)pl.ntu) << pl.log2T;
         const uint32_t tv0 = (tile / (uint32_t)pl.ntu) << pl.log2T;
         RecMeta m{0u, 0u};
         uint32_t perm = 0u;
         uint32_t v = 0xffffffffu;   // lanes past the chunk sort last
+        uint32_t umin = 0xffu, umax = 0u, vmin = 0xffu, vmax = 0u;
         if ((uint32_t)lane < ch.len) {
             m = smeta[ch.start + lane];
             perm = sperm[ch.start + lane];
-            v = (cell_key(meta_ku(m) - tu0, meta_kv(m) - tv0, pl.log2T) << 6) | (uint32_t)lane;
+            const uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
+            v = (cell_key(du, dv, pl.log2T) << 6) | (uint32_t)lane;
+            umin = umax = du;
+            vmin = vmax = dv;
         }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            umin = min(umin, (uint32_t)__shfl_xor((int)umin, off, 64));
+            umax = max(umax, (uint32_t)__shfl_xor((int)umax, off, 64));
+            vmin = min(vmin, (uint32_t)__shfl_xor((int)vmin, off, 64));
+            vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off, 64));
+        }
+        if (lane == 0) chunks[c].bbox = umin | (umax << 8) | (vmin << 16) | (vmax << 24);
+        if (ch.len < 2) continue;
 #pragma unroll
         for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
@@ -409,39 +423,69 @@ __global__ __launch_bounds__(256) void chunk_sort_small_kernel(
 }
 
 __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restrict__ plane_cfirst,
-                                                         int32_t p_split,
+                                                         int32_t nplanes,
                                                          const PlaneLayout *__restrict__ planes,
-                                                         const Chunk *__restrict__ chunks,
+                                                         Chunk *__restrict__ chunks,
                                                          RecMeta *__restrict__ smeta,
                                                          uint32_t *__restrict__ sperm) {
     __shared__ uint32_t hist[1024];
     __shared__ RecMeta m_in[kMaxR];
     __shared__ uint32_t p_in[kMaxR];
-    // only the planes before p_split (supports up to 32) are cell-sorted; the
+    __shared__ uint32_t s_box[4][4];   // per wave: umin, umax, vmin, vmax
+    // only chunks of supports up to 32 are cell-sorted and bounded; the
     // blocked kernels of the larger supports take the records in any order
-    const uint32_t c_end = plane_cfirst[p_split];
+    const uint32_t c_end = plane_cfirst[nplanes];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int p = 0;   // chunks come in increasing order: the plane only moves forward
     for (uint32_t c = blockIdx.x; c < c_end; c += gridDim.x) {
         const Chunk ch = chunks[c];
         if (ch.len <= kWaveSortMax) continue;   // the wave sort's chunks
-        while (p + 1 < p_split && c >= plane_cfirst[p + 1]) ++p;
+        while (p + 1 < nplanes && c >= plane_cfirst[p + 1]) ++p;
         int pp;
         uint32_t tile;
         bucket_plane_tile(planes[p], ch.bucket, &pp, &tile);
         const PlaneLayout pl = planes[pp];
+        if (pl.cls >= 3) continue;
         const uint32_t tu0 = (tile % (uint32_t)pl.ntu) << pl.log2T;
         const uint32_t tv0 = (tile / (uint32_t)pl.ntu) << pl.log2T;
         const int ncell = pl.T * pl.T;
         for (int i = threadIdx.x; i < ncell; i += blockDim.x) hist[i] = 0;
         __syncthreads();
+        uint32_t umin = 0xffu, umax = 0u, vmin = 0xffu, vmax = 0u;
         for (uint32_t i = threadIdx.x; i < ch.len; i += blockDim.x) {
             RecMeta m = smeta[ch.start + i];
             m_in[i] = m;
             p_in[i] = sperm[ch.start + i];
             uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
             atomicAdd(&hist[cell_key(du, dv, pl.log2T)], 1u);
+            umin = min(umin, du);
+            umax = max(umax, du);
+            vmin = min(vmin, dv);
+            vmax = max(vmax, dv);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            umin = min(umin, (uint32_t)__shfl_xor((int)umin, off, 64));
+            umax = max(umax, (uint32_t)__shfl_xor((int)umax, off, 64));
+            vmin = min(vmin, (uint32_t)__shfl_xor((int)vmin, off, 64));
+            vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off, 64));
+        }
+        if (lane == 0) {
+            s_box[wave][0] = umin;
+            s_box[wave][1] = umax;
+            s_box[wave][2] = vmin;
+            s_box[wave][3] = vmax;
         }
         __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < 4; ++w) {
+                umin = min(umin, s_box[w][0]);
+                umax = max(umax, s_box[w][1]);
+                vmin = min(vmin, s_box[w][2]);
+                vmax = max(vmax, s_box[w][3]);
+            }
+            chunks[c].bbox = umin | (umax << 8) | (vmin << 16) | (vmax << 24);
+        }
         {
             // exclusive scan of the (up to 1024) cell counts: 4 per thread
             uint2 v = make_uint2(0, 0);
@@ -469,55 +513,6 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint32_t *__restr
             sperm[ch.start + pos] = p_in[i];
         }
         __syncthreads();
-    }
-}
-
-// Bounding box of each chunk's k_lo, relative to its tile origin: one wave
-// per chunk (no barriers), so the many small chunks of the sparse planes
-// cost little.
-__global__ __launch_bounds__(256) void chunk_bbox_kernel(const int64_t *__restrict__ counters,
-                                                         const uint32_t *__restrict__ plane_cfirst,
-                                                         int32_t nplanes,
-                                                         const PlaneLayout *__restrict__ planes,
-                                                         const RecMeta *__restrict__ smeta,
-                                                         Chunk *__restrict__ chunks) {
-    const int64_t nchunks = counters[2];
-    const int lane = threadIdx.x & 63;
-    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-    const uint32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
-                                                          (threadIdx.x >> 6));
-    for (uint32_t c = first; (int64_t)c < nchunks; c += waves) {
-        const Chunk ch = chunks[c];
-        // plane of chunk c: the last p with plane_cfirst[p] <= c
-        int lo = 0, hi = nplanes - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (plane_cfirst[mid] <= c) lo = mid;
-            else hi = mid - 1;
-        }
-        int pp;
-        uint32_t tile;
-        bucket_plane_tile(planes[lo], ch.bucket, &pp, &tile);
-        const PlaneLayout pl = planes[pp];
-        const uint32_t tu0 = (tile % (uint32_t)pl.ntu) << pl.log2T;
-        const uint32_t tv0 = (tile / (uint32_t)pl.ntu) << pl.log2T;
-        uint32_t umin = 0xffffffffu, umax = 0, vmin = 0xffffffffu, vmax = 0;
-        for (uint32_t i = lane; i < ch.len; i += 64) {
-            const RecMeta m = smeta[ch.start + i];
-            const uint32_t du = meta_ku(m) - tu0, dv = meta_kv(m) - tv0;
-            umin = min(umin, du);
-            umax = max(umax, du);
-            vmin = min(vmin, dv);
-            vmax = max(vmax, dv);
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            umin = min(umin, (uint32_t)__shfl_xor((int)umin, off));
-            umax = max(umax, (uint32_t)__shfl_xor((int)umax, off));
-            vmin = min(vmin, (uint32_t)__shfl_xor((int)vmin, off));
-            vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off));
-        }
-        if (lane == 0) chunks[c].bbox = umin | (umax << 8) | (vmin << 16) | (vmax << 24);
     }
 }
 
@@ -739,31 +734,20 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
     hipLaunchKernelGGL(plane_ranges_kernel, dim3(1), dim3(256), 0, stream, np, P.d_planes, nb,
                        cstart, sums + nscan, P.plane_cfirst, P.counters);
     {
-        // cell sort of the chunks of the window gridders' supports (up to
-        // 32; planes before p_split), then the bounding box of every chunk
-        int p_split = np;
-        for (int p = 0; p < np; ++p)
-            if (P.planes[p].cls >= 3) {
-                p_split = p;
-                break;
-            }
+        // cell sort and bounding box of the chunks of the window gridders'
+        // supports (up to 32): small chunks one per wave, the others one per
+        // workgroup
         int dev = 0, cus = 0, per = 0;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, chunk_sort_kernel, 256, 0) !=
             hipSuccess)
             per = 1;
-        if (p_split > 0) {
-            hipLaunchKernelGGL(chunk_sort_small_kernel, dim3(8 * std::max(1, cus)), dim3(256), 0,
-                               stream, P.plane_cfirst, p_split, P.d_planes, P.chunks, P.smeta,
-                               P.sperm);
-            hipLaunchKernelGGL(chunk_sort_kernel, dim3(std::max(1, per) * std::max(1, cus)),
-                               dim3(256), 0, stream, P.plane_cfirst, p_split, P.d_planes,
-                               P.chunks, P.smeta, P.sperm);
-        }
-        hipLaunchKernelGGL(chunk_bbox_kernel, dim3(grid_blocks(P.max_chunks * 64, 256)),
-                           dim3(256), 0, stream, P.counters, P.plane_cfirst, np, P.d_planes,
-                           P.smeta, P.chunks);
+        hipLaunchKernelGGL(chunk_sort_small_kernel, dim3(8 * std::max(1, cus)), dim3(256), 0,
+                           stream, P.plane_cfirst, np, P.d_planes, P.chunks, P.smeta, P.sperm);
+        hipLaunchKernelGGL(chunk_sort_kernel, dim3(std::max(1, per) * std::max(1, cus)),
+                           dim3(256), 0, stream, P.plane_cfirst, np, P.d_planes, P.chunks,
+                           P.smeta, P.sperm);
         // units of every plane group
         for (int p = 0; p < np; p += P.planes[p].grp_n) {
             const PlaneLayout &L = P.planes[p];
