@@ -122,14 +122,14 @@ template <int KMAX, int TEAM, bool SEP, typename TapT>
 __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel(
     const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
-    const uint32_t *__restrict__ bucket_cfirst, const uint2 *__restrict__ units, const uint32_t *__restrict__ group_nunits,
-    const PlaneLayout *__restrict__ planes, const uint32_t *__restrict__ nonfinite,
-    uint32_t *__restrict__ queue, GridParams prm) {
+    const uint32_t *__restrict__ bucket_cfirst, const uint2 *__restrict__ units,
+    const uint32_t *__restrict__ group_nunits, const PlaneLayout *__restrict__ planes,
+    const uint32_t *__restrict__ nonfinite, uint32_t *__restrict__ queue, GridParams prm) {
     constexpr int NW = window_waves(TEAM);
     constexpr int NTEAMS = NW / TEAM;
     // fixed point cannot hold NaN or Inf: calls whose visibilities are not
     // all finite commit straight to the grid in FP32
-    const bool use_lds = uniform_u32(*nonfinite) == 0u;
+    const bool all_finite = uniform_u32(*nonfinite) == 0u;
     extern __shared__ int32_t region[];   // [8][RH][RW]: (pol, re/im) planes
     __shared__ float s_bound[NW];
     __shared__ uint32_t s_next;
@@ -172,7 +172,9 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
         const int RH = (int)(vend - vmin);
         const int plane_cells = RH * RW;
 
-        // fixed-point scale of this item: 2^scale * bound <= 2^30
+        // fixed-point scale of this item: 2^scale * bound <= 2^30 (an item
+        // whose bound overflows FP32 commits straight to the grid as well)
+        bool use_lds = all_finite;
         int scale = 0;
         if (use_lds) {
             for (int i = threadIdx.x; i < 8 * plane_cells; i += NW * kWave) region[i] = 0;
@@ -198,8 +200,9 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
             for (int w = 0; w < NW; ++w) bound += s_bound[w];
             // margin for the rounding of the sums above
             bound = 2.0f * bound * 1.0001f + 1e-30f;
-            int e;
-            frexpf(bound, &e);          // bound < 2^e
+            use_lds = uniform_u32(isfinite(bound) ? 1u : 0u) != 0u;
+            int e = 0;
+            if (use_lds) frexpf(bound, &e);   // bound < 2^e
             scale = max(-120, min(120, 30 - e));
             scale = (int)uniform_u32((uint32_t)scale);
             __syncthreads();

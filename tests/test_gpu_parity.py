@@ -232,6 +232,21 @@ def test_single_record_and_hot_cell(torch_cuda, api, small_sep, small_wproj):
         assert H.rel_l2(G, G_ref) < TOL
 
 
+def test_large_finite_visibilities_commit_in_fp32(torch_cuda, api, small_sep, small_wproj):
+    """64 records on one pixel with visibilities near 1e36: the window
+    gridders' fixed-point bound (2 max|tap| times the sum of the records'
+    largest components) overflows FP32 although every cell sum is far below
+    it; such units must commit in FP32 instead (the result stays finite and
+    matches the definition)."""
+    torch = torch_cuda
+    for wl in (small_sep, small_wproj):
+        hot = np.repeat(np.array([[20.3 / wl.scale, -11.6 / wl.scale, 0.0]]), 64, axis=0)
+        vis = W.vis_normal(hot.shape[0], 4, seed=8) * 2e36
+        G, G_ref = _grid_both(torch, api, wl, vis, uvw=hot)
+        assert np.isfinite(G).all() and np.isfinite(G_ref).all()
+        assert H.rel_l2(G, G_ref) < TOL
+
+
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
 def test_reduced_precision_bank(torch_cuda, api, small_wproj, dtype):
     """FP16/BF16 taps, FP32 arithmetic.  Against the oracle run on the same
