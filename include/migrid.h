@@ -121,10 +121,13 @@ mg_status mg_compute_indices(const mg_grid_desc *g, const mg_kernel_desc *k, int
 /* ---- plans: index + sort once, grid / degrid many times (major cycles) ----
  *
  * mg_plan_create runs the index rule over all records and sorts the valid
- * ones by (plane, cell) on `stream` (the thesis's sorted record order,
- * Section 3.2.4), and prepares the kernel bank.  The plan owns device memory
- * it allocates itself (freed by mg_plan_destroy); it keeps no pointer to
- * uvw, and copies the tap table, so neither needs to outlive the create
+ * ones on `stream` by uv tile and plane (the planes of one support class
+ * share their tiles) and by cell inside each run of records (the thesis's
+ * sorted record order, Section 3.2.4), and prepares the kernel bank: a
+ * private copy re-laid so that the taps of each oversampling phase are
+ * contiguous, plus its conjugate for W-projection.  The plan owns device
+ * memory it allocates itself (freed by mg_plan_destroy); it keeps no pointer
+ * to uvw or to the caller's taps, so neither needs to outlive the create
  * call's stream work.  A plan is immutable after creation and may be used
  * from several streams once the creating stream's work has completed. */
 typedef struct mg_plan mg_plan;
