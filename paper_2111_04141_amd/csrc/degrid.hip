@@ -378,64 +378,78 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
             bucket_plane_tile(gl, ch.bucket, &pc, &tile_);
             const int S = planes[pc].S;
 
-            // this lane's taps: LDS offset and table byte offset relative to the
-            // footprint's first cell and first tap.  Taps t < nt - 1 lie in every
-            // footprint; tap nt - 1 only where q < S^2 (the others keep zeros).
-            int lg[NTAP];
-            uint32_t lt[NTAP], ltv[NTAP];
-            const int nt = (S * S + 63) >> 6;
+            // this lane's taps q = t * 64 + lane: LDS offset and table byte
+            // offset relative to the footprint's first cell and first tap.
+            // Taps t < nt - 1 lie in every footprint; where S^2 is not a
+            // multiple of 64, lanes past S^2 in the last tap read the first
+            // tap and first cell (in bounds) and their products are zeroed.
+            const int nt_rt = (S * S + 63) >> 6;
             const bool last_full = (S * S) % 64 == 0;
-            const bool last_on = ((nt - 1) * 64 + lane) < S * S;
+            const bool last_on = ((nt_rt - 1) * 64 + lane) < S * S;
+            // NT: taps held per lane; a compile-time count (one instance per
+            // count) for up to 4 taps, else NTAP with the count tested
+            auto run = [&](auto nt_t) {
+                constexpr int NT = decltype(nt_t)::value;
+                const int nt = (NTAP <= 4) ? NT : nt_rt;
+                int lg[NT];
+                uint32_t lt[NT], ltv[NT];
 #pragma unroll
-            for (int t = 0; t < NTAP; ++t) {
-                const int q = t * 64 + lane;
-                const int j = q / S, i = q - (q / S) * S;
-                lg[t] = j * kRowStride + i;
-                if constexpr (SEP) {
-                    lt[t] = (uint32_t)i * kElem;
-                    ltv[t] = (uint32_t)j * kElem;
-                } else {
-                    lt[t] = (uint32_t)(j * S + i) * kElem;
-                    ltv[t] = 0u;
-                }
-            }
-
-            // groups of B records, taken by the waves in turn (continuing
-            // from the unit's previous chunk); a short last group repeats the
-            // chunk's last record (its sums are not written)
-            const uint32_t rend = ch.start + ch.len;
-            const uint32_t ngroups = (ch.len + B - 1) / B;
-            const uint32_t gfirst = ((uint32_t)wave + kWavesPerGroup - turn) % kWavesPerGroup;
-            turn = (turn + ngroups) % kWavesPerGroup;
-            for (uint32_t gi = gfirst; gi < ngroups; gi += kWavesPerGroup) {
-                const uint32_t r0 = ch.start + gi * B;
-                const uint32_t nb = min((uint32_t)B, rend - r0);
-                float part[NV];
-#pragma unroll
-                for (int i = 0; i < NV; ++i) part[i] = 0.0f;
-#pragma unroll
-                for (int bi = 0; bi < B; ++bi) {
-                    const RecMeta m = smeta[min(r0 + (uint32_t)bi, rend - 1)];
-                    const int sg = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
-                    const char *tb;
-                    const char *tbv = nullptr;
+                for (int t = 0; t < NT; ++t) {
+                    const int q = min(t * 64 + lane, S * S - 1);
+                    const int qq = (t * 64 + lane < S * S) ? q : 0;
+                    const int j = qq / S, i = qq - (qq / S) * S;
+                    lg[t] = j * kRowStride + i;
                     if constexpr (SEP) {
-                        tb = tbase + (size_t)(m.toff & 0xffffu) * kElem;
-                        tbv = tbase + (size_t)(m.toff >> 16) * kElem;
+                        lt[t] = (uint32_t)i * kElem;
+                        ltv[t] = (uint32_t)j * kElem;
                     } else {
-                        tb = tbase + (size_t)m.toff * kElem;
+                        lt[t] = (uint32_t)(j * S + i) * kElem;
+                        ltv[t] = 0u;
                     }
-                    if constexpr (NTAP > 4) {
-                        // many taps per lane: one tap at a time (registers)
+                }
+                // the last tap's offsets (its index is a run-time value for
+                // NTAP > 4: picked once per chunk)
+                int lg_last = lg[0];
+                uint32_t lt_last = lt[0], ltv_last = ltv[0];
 #pragma unroll
-                        for (int t = 0; t < NTAP; ++t) {
-                            if (t >= nt) continue;
-                            if (t == nt - 1 && !last_full && !last_on) continue;
-                            uint32_t o = lt[t];
+                for (int t = 0; t < NT; ++t) {
+                    if (t == nt - 1) {
+                        lg_last = lg[t];
+                        lt_last = lt[t];
+                        ltv_last = ltv[t];
+                    }
+                }
+
+                // groups of B records, taken by the waves in turn (continuing
+                // from the unit's previous chunk); a short last group repeats
+                // the chunk's last record (its sums are not written)
+                const uint32_t rend = ch.start + ch.len;
+                const uint32_t ngroups = (ch.len + B - 1) / B;
+                const uint32_t gfirst = ((uint32_t)wave + kWavesPerGroup - turn) % kWavesPerGroup;
+                turn = (turn + ngroups) % kWavesPerGroup;
+                for (uint32_t gi = gfirst; gi < ngroups; gi += kWavesPerGroup) {
+                    const uint32_t r0 = ch.start + gi * B;
+                    const uint32_t nb = min((uint32_t)B, rend - r0);
+                    float part[NV];
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) part[i] = 0.0f;
+#pragma unroll
+                    for (int bi = 0; bi < B; ++bi) {
+                        const RecMeta m = smeta[min(r0 + (uint32_t)bi, rend - 1)];
+                        const int sg = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
+                        const char *tb;
+                        const char *tbv = nullptr;
+                        if constexpr (SEP) {
+                            tb = tbase + (size_t)(m.toff & 0xffffu) * kElem;
+                            tbv = tbase + (size_t)(m.toff >> 16) * kElem;
+                        } else {
+                            tb = tbase + (size_t)m.toff * kElem;
+                        }
+                        // tap weight and the 4 grid values of one tap
+                        auto load = [&](const int g_off, uint32_t o, uint32_t ov, float2 &w,
+                                        float2 (&gv)[4]) {
                             asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
-                            float2 w;
                             if constexpr (SEP) {
-                                uint32_t ov = ltv[t];
                                 asm volatile("" : "+v"(ov));
                                 w = make_float2(TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
                                                     TapTraits<TapT>::real((const TapT *)(tbv + ov), 0),
@@ -443,71 +457,74 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                             } else {
                                 w = TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
                             }
-                            const float2 *gp = region + sg + lg[t];
+                            const float2 *gp = region + sg + g_off;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) gv[q] = gp[q * kPitch];
+                        };
+                        // lanes past S^2 in the last tap contribute nothing
+                        auto mask_last = [&](float2 &w, float2 (&gv)[4]) {
+                            if (!last_on) {
+                                w = make_float2(0.0f, 0.0f);
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) gv[q] = make_float2(0.0f, 0.0f);
+                            }
+                        };
+                        // acc += conj(w) * G
+                        auto fma4 = [&](const float2 w, const float2 (&gv)[4]) {
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
-                                const float2 gq = gp[q * kPitch];
                                 float &ar = part[bi * 8 + 2 * q];
                                 float &ai = part[bi * 8 + 2 * q + 1];
-                                ar = fmaf(w.x, gq.x, fmaf(w.y, gq.y, ar));
-                                ai = fmaf(w.x, gq.y, fmaf(-w.y, gq.x, ai));
+                                ar = fmaf(w.x, gv[q].x, fmaf(w.y, gv[q].y, ar));
+                                ai = fmaf(w.x, gv[q].y, fmaf(-w.y, gv[q].x, ai));
                             }
+                        };
+                        if constexpr (NTAP > 4) {
+                            // many taps per lane: one tap at a time (registers)
+#pragma unroll
+                            for (int t = 0; t < NT - 1; ++t) {
+                                if (t < nt - 1) {
+                                    float2 w, gv[4];
+                                    load(lg[t], lt[t], ltv[t], w, gv);
+                                    fma4(w, gv);
+                                }
+                            }
+                            float2 w, gv[4];
+                            load(lg_last, lt_last, ltv_last, w, gv);
+                            if (!last_full) mask_last(w, gv);
+                            fma4(w, gv);
+                        } else {
+                            // all NT taps' loads, then their multiply-adds
+                            float2 w[NT], gv[NT][4];
+#pragma unroll
+                            for (int t = 0; t < NT; ++t) load(lg[t], lt[t], ltv[t], w[t], gv[t]);
+                            if (!last_full) mask_last(w[NT - 1], gv[NT - 1]);
+#pragma unroll
+                            for (int t = 0; t < NT; ++t) fma4(w[t], gv[t]);
                         }
-                    } else {
-                        // loads of TB taps, then their multiply-adds
-                        constexpr int TB = NTAP < 4 ? NTAP : 4;
-#pragma unroll
-                        for (int t0 = 0; t0 < NTAP; t0 += TB) {
-                            float2 w[TB], gv[TB][4];
-                            auto load = [&](const int t, const int u) {
-                                uint32_t o = lt[t];
-                                asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
-                                if constexpr (SEP) {
-                                    uint32_t ov = ltv[t];
-                                    asm volatile("" : "+v"(ov));
-                                    w[u] = make_float2(TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
-                                                           TapTraits<TapT>::real((const TapT *)(tbv + ov), 0),
-                                                       0.0f);
-                                } else {
-                                    w[u] = TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
-                                }
-                                const float2 *gp = region + sg + lg[t];
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) gv[u][q] = gp[q * kPitch];
-                            };
-#pragma unroll
-                            for (int u = 0; u < TB; ++u) {
-                                const int t = t0 + u;
-                                if (t >= nt) continue;
-                                if (t < nt - 1 || last_full) {
-                                    load(t, u);
-                                } else {
-                                    w[u] = make_float2(0.0f, 0.0f);
-#pragma unroll
-                                    for (int q = 0; q < 4; ++q) gv[u][q] = make_float2(0.0f, 0.0f);
-                                    if (last_on) load(t, u);
-                                }
-                            }
-#pragma unroll
-                            for (int u = 0; u < TB; ++u) {
-                                if (t0 + u >= nt) continue;
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) {
-                                    float &ar = part[bi * 8 + 2 * q];
-                                    float &ai = part[bi * 8 + 2 * q + 1];
-                                    ar = fmaf(w[u].x, gv[u][q].x, fmaf(w[u].y, gv[u][q].y, ar));
-                                    ai = fmaf(w[u].x, gv[u][q].y, fmaf(-w[u].y, gv[u][q].x, ai));
-                                }
-                            }
-                        }
+                        // records one after another: the next record's loads
+                        // are not hoisted above these multiply-adds (which
+                        // would hold every record's taps in registers)
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    wave_reduce_scatter<NV>(part, lane);
+                    if (writer) {
+                        const int bi = my_idx >> 3, q = my_idx & 7;
+                        if ((uint32_t)bi < nb && (q >> 1) < npol)
+                            vis_out[((size_t)sperm[r0 + bi] * npol + (q >> 1)) * 2 + (q & 1)] =
+                                part[0];
                     }
                 }
-                wave_reduce_scatter<NV>(part, lane);
-                if (writer) {
-                    const int bi = my_idx >> 3, q = my_idx & 7;
-                    if ((uint32_t)bi < nb && (q >> 1) < npol)
-                        vis_out[((size_t)sperm[r0 + bi] * npol + (q >> 1)) * 2 + (q & 1)] = part[0];
+            };
+            if constexpr (NTAP <= 4) {
+                switch (nt_rt) {
+                case 1: run(std::integral_constant<int, 1>{}); break;
+                case 2: run(std::integral_constant<int, (NTAP < 2 ? NTAP : 2)>{}); break;
+                case 3: run(std::integral_constant<int, (NTAP < 3 ? NTAP : 3)>{}); break;
+                default: run(std::integral_constant<int, NTAP>{}); break;
                 }
+            } else {
+                run(std::integral_constant<int, NTAP>{});
             }
         }
     }
@@ -571,8 +588,9 @@ hipError_t launch_dt(const DegridPtrs &a, const DegridParams &prm, int tile, int
     // the region must fit the compile-time pitch and the taps the lanes
     if (tile + smax - 1 > PITCH || smax * smax > NTAP * 64) return hipErrorInvalidValue;
     const size_t lds = sizeof(float2) * (size_t)row_stride<PITCH>() * (size_t)(tile + smax - 1);
-    // records per reduction group: fewer for many taps per lane (registers)
-    auto kern = degrid_taps_kernel<NTAP, PITCH, (NTAP > 4 ? 2 : 4), SEP, TapT>;
+    // records per reduction group: two where a lane holds several taps
+    // (registers; the reduction costs about the same per record either way)
+    auto kern = degrid_taps_kernel<NTAP, PITCH, (NTAP > 1 ? 2 : 4), SEP, TapT>;
     int dev = 0, cus = 0, per = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
