@@ -1,8 +1,8 @@
 // Degridding (gather): vis_out[r] = sum_{i,j} conj(w_ij) G[k_lo + (i, j)], the
 // adjoint of the gridding map.
 //
-// Work unit: one chunk of records of one (plane, tile) bucket, the same
-// chunks the gridder uses.  The grid region the chunk can touch (its tile
+// Supports above 32 (degrid_block_kernel): work unit one chunk of records of
+// one (plane, tile) bucket.  The grid region the chunk can touch (its tile
 // plus an S - 1 halo) is cut into 8 x 8-cell blocks, one cell per lane;
 // block b belongs to wave b mod NW and its 4 polarisations stay in
 // registers for the whole chunk, so the grid is read once per chunk with
@@ -12,7 +12,8 @@
 // per lane into the record's partial sums.  Partial sums of B records are
 // then reduced across the wave's lanes (a butterfly that halves the values
 // each lane holds at every step) and across the waves through LDS, and one
-// thread per (record, component) writes the result.
+// thread per (record, component) writes the result.  Supports up to 32 take
+// degrid_taps_kernel (below).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -438,16 +438,16 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
 // ---------------------------------------------------------------------------
 // blocked output-stationary gridder (large supports)
 // ---------------------------------------------------------------------------
-// The grid region a chunk can touch (its tile plus an S - 1 halo) is cut
-// into 8 x 8-cell blocks, one cell per lane; block b belongs to wave
-// b mod NW of the workgroup (its k-th block is b = k NW + wave), and its 8
-// accumulators per lane stay in registers for the whole chunk.  Every wave
-// walks all records of the chunk (scalar loads).  Per record, lane k of a
+// The grid region a unit can touch (its tile plus the group's largest S - 1
+// halo) is cut into 8 x 8-cell blocks, one cell per lane; block b belongs to
+// wave b mod NW of the workgroup (its k-th block is b = k NW + wave), and its
+// 8 accumulators per lane stay in registers for the whole unit.  Every wave
+// walks all records of the unit (scalar loads).  Per record, lane k of a
 // wave tests block k against the record's footprint, so one vector compare
 // and a ballot give the wave's overlapped blocks (and those lying wholly
 // inside the footprint, which need no per-lane mask); each overlapped block
 // then takes one tap load and 16 multiply-adds per lane.  Nothing is
-// committed until the chunk ends; then each touched cell is added to the
+// committed until the unit ends; then each touched cell is added to the
 // grid with float atomics.  Where records are sparse, as in the high-|w|
 // planes of large support, this replaces the moving window's per-record
 // slot commits; the lane utilisation is S^2 over the overlapped blocks'

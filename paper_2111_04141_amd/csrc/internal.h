@@ -97,14 +97,15 @@ mg_status plan_taps(PlanState &P, const void *src, int64_t table_elems, hipStrea
 mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream_t stream);
 mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hipStream_t stream);
 
-// Gridder classes: support range -> slots per lane and LDS tile use.
-//   class 0: S <= 8   (one window slot per lane)
-//   class 1: S <= 16  (up to 4 slots per lane)
-//   class 2: S <= 32  (up to 8 slots per lane, slots split over 2 waves)
+// Support classes (each has its own gridding and degridding kernels):
+//   class 0: S <= 8   moving window, one slot per lane
+//   class 1: S <= 16  moving window, up to 4 slots per lane
+//   class 2: S <= 32  moving window held by teams of 4 waves, up to 4 slots
+//                     per lane
+//   class 3: S <= 64  blocked output-stationary kernel (registers per 8 x 8
+//                     block of the unit's region)
 // Classes 0-2 accumulate committed sums in a fixed-point LDS region (see
-// grid.hip); class 3 commits straight to the grid.
-//   class 3: S <= 64  (16 slots per lane, slots split over the 4 waves,
-//                      commits straight to the grid)
+// grid.hip); class 3 commits its registers to the grid once per unit.
 // Entries of padding after the sorted record arrays (metadata, and the
 // gridder's sorted visibilities): the gridders load records in batches of
 // two, one batch ahead, so their reads reach 3 entries past the last record
