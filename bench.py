@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 # call's dispatches and scaled by the reading of a plain device copy of known
 # size.  Valid only for the kernel sources with this digest; any change to
 # them makes the figure stale and it is then reported as null.
-MEASURED_TRAFFIC = {"sources": "40f36c5843f5f545", "bytes_per_call": 36073690170,
+MEASURED_TRAFFIC = {"sources": "bdba28663fb0f24f", "bytes_per_call": 36069298547,
                     "profile": "profiles/grid_wproj8192_134M_hbm_traffic.txt"}
 TRAFFIC_SOURCES = ("grid.hip", "plan.hip", "api.hip", "common.h", "internal.h")
 
@@ -102,6 +102,8 @@ def main():
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--serving-jobs", type=int, default=40,
                     help="jobs in the serving trace (0 = skip the serving measurement)")
+    ap.add_argument("--no-reduced-precision", action="store_true",
+                    help="skip timing the FP16 and BF16 banks")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
@@ -206,6 +208,37 @@ def main():
     log(f"[bench] plan build {plan_ms:.3f} ms, plan grid {grid_ms:.3f} ms, "
         f"plan degrid {degrid_ms:.3f} ms")
 
+    # ---- reduced-precision banks on the same records (error vs FP64 is
+    # measured by the precision test; here only their speed) ----
+    reduced = {}
+    if not args.no_reduced_precision:
+        pairs = np.stack([b.taps.real, b.taps.imag], -1)
+        for name, tdt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+            bank_r = api.KernelBank("wproj", torch.from_numpy(pairs).to(tdt).to(dev),
+                                    plane_support=b.supports.tolist(),
+                                    plane_offset=b.offsets.tolist(), inv_dw=b.inv_dw)
+            plan_r = api.Plan(spec, bank_r, uvw)
+            plan_r.grid(vis, out=grid)
+            plan_r.degrid(grid, out=vis_out)
+            torch.cuda.synchronize()
+            er = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            er[0].record(stream)
+            for i in range(args.steps):
+                plan_r.grid(vis, out=grid)
+            er[1].record(stream)
+            er[2].record(stream)
+            for i in range(args.steps):
+                plan_r.degrid(grid, out=vis_out)
+            er[3].record(stream)
+            torch.cuda.synchronize()
+            g_ms = er[0].elapsed_time(er[1]) / args.steps
+            d_ms = er[2].elapsed_time(er[3]) / args.steps
+            plan_r.close()
+            reduced[name] = {"plan_grid_ms": g_ms, "plan_grid_updates_per_s": updates / (g_ms * 1e-3),
+                             "plan_degrid_ms": d_ms,
+                             "plan_degrid_updates_per_s": updates / (d_ms * 1e-3)}
+            log(f"[bench] {name} bank: plan grid {g_ms:.3f} ms, plan degrid {d_ms:.3f} ms")
+
     flops = 32.0 * updates            # 4 polarisations x complex multiply-add
     traffic = None
     if (MEASURED_TRAFFIC is not None and args.channels == 128
@@ -236,6 +269,7 @@ def main():
         "plan_grid_updates_per_s": updates / (grid_ms * 1e-3),
         "plan_degrid_ms": degrid_ms,
         "plan_degrid_updates_per_s": updates / (degrid_ms * 1e-3),
+        "reduced_precision_banks": reduced,
         "roofline": {
             "bound": "alu",
             "achieved": achieved_tflops,
