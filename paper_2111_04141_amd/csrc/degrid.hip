@@ -481,13 +481,17 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                             }
                         };
                         if constexpr (NTAP > 4) {
-                            // many taps per lane: one tap at a time (registers)
+                            // many taps per lane: two at a time (both taps'
+                            // loads in flight, registers for two only)
 #pragma unroll
-                            for (int t = 0; t < NT - 1; ++t) {
+                            for (int t = 0; t < NT - 1; t += 2) {
                                 if (t < nt - 1) {
-                                    float2 w, gv[4];
-                                    load(lg[t], lt[t], ltv[t], w, gv);
-                                    fma4(w, gv);
+                                    const bool two = t + 1 < nt - 1;
+                                    float2 w0, gv0[4], w1, gv1[4];
+                                    load(lg[t], lt[t], ltv[t], w0, gv0);
+                                    if (two) load(lg[t + 1], lt[t + 1], ltv[t + 1], w1, gv1);
+                                    fma4(w0, gv0);
+                                    if (two) fma4(w1, gv1);
                                 }
                             }
                             float2 w, gv[4];
