@@ -481,17 +481,21 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                             }
                         };
                         if constexpr (NTAP > 4) {
-                            // many taps per lane: two at a time (both taps'
-                            // loads in flight, registers for two only)
+                            // many taps per lane: four at a time (their loads
+                            // in flight together; the LDS region already
+                            // limits the kernel to two waves per SIMD, so the
+                            // registers are there)
 #pragma unroll
-                            for (int t = 0; t < NT - 1; t += 2) {
+                            for (int t = 0; t < NT - 1; t += 4) {
                                 if (t < nt - 1) {
-                                    const bool two = t + 1 < nt - 1;
-                                    float2 w0, gv0[4], w1, gv1[4];
-                                    load(lg[t], lt[t], ltv[t], w0, gv0);
-                                    if (two) load(lg[t + 1], lt[t + 1], ltv[t + 1], w1, gv1);
-                                    fma4(w0, gv0);
-                                    if (two) fma4(w1, gv1);
+                                    float2 w[4], gv[4][4];
+#pragma unroll
+                                    for (int u = 0; u < 4; ++u)
+                                        if (t + u < NT - 1 && t + u < nt - 1)
+                                            load(lg[t + u], lt[t + u], ltv[t + u], w[u], gv[u]);
+#pragma unroll
+                                    for (int u = 0; u < 4; ++u)
+                                        if (t + u < NT - 1 && t + u < nt - 1) fma4(w[u], gv[u]);
                                 }
                             }
                             float2 w, gv[4];
