@@ -434,53 +434,59 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                     float part[NV];
 #pragma unroll
                     for (int i = 0; i < NV; ++i) part[i] = 0.0f;
+                    // record bi of the group: its LDS offset and tap pointers
+                    int sg[B];
+                    const char *tb[B];
+                    const char *tbv[B];
 #pragma unroll
                     for (int bi = 0; bi < B; ++bi) {
                         const RecMeta m = smeta[min(r0 + (uint32_t)bi, rend - 1)];
-                        const int sg = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
-                        const char *tb;
-                        const char *tbv = nullptr;
+                        sg[bi] = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
                         if constexpr (SEP) {
-                            tb = tbase + (size_t)(m.toff & 0xffffu) * kElem;
-                            tbv = tbase + (size_t)(m.toff >> 16) * kElem;
+                            tb[bi] = tbase + (size_t)(m.toff & 0xffffu) * kElem;
+                            tbv[bi] = tbase + (size_t)(m.toff >> 16) * kElem;
                         } else {
-                            tb = tbase + (size_t)m.toff * kElem;
+                            tb[bi] = tbase + (size_t)m.toff * kElem;
+                            tbv[bi] = nullptr;
                         }
-                        // tap weight and the 4 grid values of one tap
-                        auto load = [&](const int g_off, uint32_t o, uint32_t ov, float2 &w,
-                                        float2 (&gv)[4]) {
-                            asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
-                            if constexpr (SEP) {
-                                asm volatile("" : "+v"(ov));
-                                w = make_float2(TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
-                                                    TapTraits<TapT>::real((const TapT *)(tbv + ov), 0),
-                                                0.0f);
-                            } else {
-                                w = TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
-                            }
-                            const float2 *gp = region + sg + g_off;
+                    }
+                    // tap weight and the 4 grid values of one tap of record bi
+                    auto load = [&](const int bi, const int g_off, uint32_t o, uint32_t ov,
+                                    float2 &w, float2 (&gv)[4]) {
+                        asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+                        if constexpr (SEP) {
+                            asm volatile("" : "+v"(ov));
+                            w = make_float2(TapTraits<TapT>::real((const TapT *)(tb[bi] + o), 0) *
+                                                TapTraits<TapT>::real((const TapT *)(tbv[bi] + ov), 0),
+                                            0.0f);
+                        } else {
+                            w = TapTraits<TapT>::cplx((const TapT *)(tb[bi] + o), 0);
+                        }
+                        const float2 *gp = region + sg[bi] + g_off;
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) gv[q] = gp[q * kPitch];
-                        };
-                        // lanes past S^2 in the last tap contribute nothing
-                        auto mask_last = [&](float2 &w, float2 (&gv)[4]) {
-                            if (!last_on) {
-                                w = make_float2(0.0f, 0.0f);
+                        for (int q = 0; q < 4; ++q) gv[q] = gp[q * kPitch];
+                    };
+                    // lanes past S^2 in the last tap contribute nothing
+                    auto mask_last = [&](float2 &w, float2 (&gv)[4]) {
+                        if (!last_on) {
+                            w = make_float2(0.0f, 0.0f);
 #pragma unroll
-                                for (int q = 0; q < 4; ++q) gv[q] = make_float2(0.0f, 0.0f);
-                            }
-                        };
-                        // acc += conj(w) * G
-                        auto fma4 = [&](const float2 w, const float2 (&gv)[4]) {
+                            for (int q = 0; q < 4; ++q) gv[q] = make_float2(0.0f, 0.0f);
+                        }
+                    };
+                    // record bi's sums += conj(w) * G
+                    auto fma4 = [&](const int bi, const float2 w, const float2 (&gv)[4]) {
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                float &ar = part[bi * 8 + 2 * q];
-                                float &ai = part[bi * 8 + 2 * q + 1];
-                                ar = fmaf(w.x, gv[q].x, fmaf(w.y, gv[q].y, ar));
-                                ai = fmaf(w.x, gv[q].y, fmaf(-w.y, gv[q].x, ai));
-                            }
-                        };
-                        if constexpr (NTAP > 4) {
+                        for (int q = 0; q < 4; ++q) {
+                            float &ar = part[bi * 8 + 2 * q];
+                            float &ai = part[bi * 8 + 2 * q + 1];
+                            ar = fmaf(w.x, gv[q].x, fmaf(w.y, gv[q].y, ar));
+                            ai = fmaf(w.x, gv[q].y, fmaf(-w.y, gv[q].x, ai));
+                        }
+                    };
+                    if constexpr (NTAP > 4) {
+#pragma unroll
+                        for (int bi = 0; bi < B; ++bi) {
                             // many taps per lane: four at a time (their loads
                             // in flight together; the LDS region already
                             // limits the kernel to two waves per SIMD, so the
@@ -492,29 +498,32 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
 #pragma unroll
                                     for (int u = 0; u < 4; ++u)
                                         if (t + u < NT - 1 && t + u < nt - 1)
-                                            load(lg[t + u], lt[t + u], ltv[t + u], w[u], gv[u]);
+                                            load(bi, lg[t + u], lt[t + u], ltv[t + u], w[u], gv[u]);
 #pragma unroll
                                     for (int u = 0; u < 4; ++u)
-                                        if (t + u < NT - 1 && t + u < nt - 1) fma4(w[u], gv[u]);
+                                        if (t + u < NT - 1 && t + u < nt - 1) fma4(bi, w[u], gv[u]);
                                 }
                             }
                             float2 w, gv[4];
-                            load(lg_last, lt_last, ltv_last, w, gv);
+                            load(bi, lg_last, lt_last, ltv_last, w, gv);
                             if (!last_full) mask_last(w, gv);
-                            fma4(w, gv);
-                        } else {
-                            // all NT taps' loads, then their multiply-adds
-                            float2 w[NT], gv[NT][4];
-#pragma unroll
-                            for (int t = 0; t < NT; ++t) load(lg[t], lt[t], ltv[t], w[t], gv[t]);
-                            if (!last_full) mask_last(w[NT - 1], gv[NT - 1]);
-#pragma unroll
-                            for (int t = 0; t < NT; ++t) fma4(w[t], gv[t]);
+                            fma4(bi, w, gv);
                         }
-                        // records one after another: the next record's loads
-                        // are not hoisted above these multiply-adds (which
-                        // would hold every record's taps in registers)
-                        __builtin_amdgcn_sched_barrier(0);
+                    } else {
+                        // every tap of the group's records loaded, then the
+                        // multiply-adds
+                        float2 w[B][NT], gv[B][NT][4];
+#pragma unroll
+                        for (int bi = 0; bi < B; ++bi)
+#pragma unroll
+                            for (int t = 0; t < NT; ++t)
+                                load(bi, lg[t], lt[t], ltv[t], w[bi][t], gv[bi][t]);
+#pragma unroll
+                        for (int bi = 0; bi < B; ++bi) {
+                            if (!last_full) mask_last(w[bi][NT - 1], gv[bi][NT - 1]);
+#pragma unroll
+                            for (int t = 0; t < NT; ++t) fma4(bi, w[bi][t], gv[bi][t]);
+                        }
                     }
                     wave_reduce_scatter<NV>(part, lane);
                     if (writer) {
