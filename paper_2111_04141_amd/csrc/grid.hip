@@ -676,19 +676,44 @@ __global__ __launch_bounds__(256) void gather_vis_kernel(const int64_t *__restri
                                                          const float2 *__restrict__ vis,
                                                          int32_t npol, float4 *__restrict__ svis,
                                                          uint32_t *__restrict__ nonfinite) {
-    const int64_t nvalid = counters[1];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvalid && i < nrec;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const float2 *v = vis + (size_t)sperm[i] * npol;
-        float2 x[4];
+    constexpr int U = 4;   // records per thread in flight (independent random loads)
+    const int64_t n = min(counters[1], nrec);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
+        uint32_t idx[U];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) x[q] = (q < npol) ? v[q] : make_float2(0.0f, 0.0f);
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * stride;
+            idx[u] = (i < n) ? sperm[i] : 0u;
+        }
+        float4 a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * stride >= n) continue;
+            const float2 *v = vis + (size_t)idx[u] * npol;
+            if (npol == 4) {
+                a[u] = reinterpret_cast<const float4 *>(v)[0];
+                b[u] = reinterpret_cast<const float4 *>(v)[1];
+            } else {
+                float2 x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[q] = (q < npol) ? v[q] : make_float2(0.0f, 0.0f);
+                a[u] = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
+                b[u] = make_float4(x[2].x, x[2].y, x[3].x, x[3].y);
+            }
+        }
         bool finite = true;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) finite = finite && isfinite(x[q].x) && isfinite(x[q].y);
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i >= n) continue;
+            finite = finite && isfinite(a[u].x) && isfinite(a[u].y) && isfinite(a[u].z) &&
+                     isfinite(a[u].w) && isfinite(b[u].x) && isfinite(b[u].y) &&
+                     isfinite(b[u].z) && isfinite(b[u].w);
+            svis[2 * i] = a[u];
+            svis[2 * i + 1] = b[u];
+        }
         if (!finite) atomicOr(nonfinite, 1u);
-        svis[2 * i] = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
-        svis[2 * i + 1] = make_float4(x[2].x, x[2].y, x[3].x, x[3].y);
     }
 }
 
