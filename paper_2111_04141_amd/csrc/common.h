@@ -59,13 +59,6 @@ struct RecIndex {
     int32_t ku, kv, ou, ov, plane, S, conj, valid;
 };
 
-// Floor division of a possibly negative numerator by a positive divisor.
-__device__ inline int64_t floor_div_pos(int64_t a, int64_t b) {
-    int64_t q = a / b;
-    if ((a % b != 0) && (a < 0)) q -= 1;
-    return q;
-}
-
 // One axis of the index rule, in FP64 with every operation rounded as
 // written (no contraction into fused multiply-add), so that the GPU and any
 // other implementation of the same rule agree bit for bit.
@@ -80,9 +73,14 @@ __device__ inline bool index_axis(double coord, double scale, int32_t n, int32_t
     if (!(fabs(fq) < 4.0e15)) return false;
     int64_t q = (int64_t)fq;
     int64_t half = (int64_t)beta * S / 2;
-    int64_t k = floor_div_pos(q - half, beta) + 1;
-    int64_t t0 = k * beta - q + half;
-    bool ok = (k >= 0) && (k + S - 1 <= (int64_t)n - 1);
+    // k = floor((q - half) / beta) + 1 lies in [0, n - S] exactly when
+    // -beta <= q - half < beta * (n - S); inside that range the shifted
+    // numerator is non-negative and below 2^31, so one unsigned 32-bit
+    // division gives k (no 64-bit division).
+    const int64_t d = q - half;
+    const bool ok = (d >= -(int64_t)beta) && (d < (int64_t)beta * ((int64_t)n - S));
+    const uint32_t k = ok ? (uint32_t)(d + beta) / (uint32_t)beta : 0u;
+    const int64_t t0 = (int64_t)k * beta - d;
     *k_lo = ok ? (int32_t)k : 0;
     *o = ok ? (int32_t)(t0 - 1) : 0;
     return ok;
