@@ -51,6 +51,12 @@ constexpr uint32_t kNoCell = 0xffffffffu;
 constexpr int kBatch = 2;   // records per batch of scalar loads
 static_assert(kBatch + 1 <= kRecPad, "the sorted arrays are padded for one batch of read-ahead");
 
+// Waits for every outstanding scalar load.  Called once after a record
+// loop's first batch is issued: otherwise the compiler places the wait for
+// that batch at the loop top, where (scalar loads complete out of order) it
+// also waits for the next batch's loads on every iteration.
+__device__ inline void wait_scalar_loads() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
 struct GridParams {
     int32_t npol, nu, nv, beta;
     int32_t p_lo, p_hi;       // planes handled by this launch
@@ -368,6 +374,7 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
                         pv += 2 * kBatch;
                     };
                     load_batch();
+                    wait_scalar_loads();
                     for (uint32_t r = rb; r < re; r += kBatch) {
                         RecMeta mm[kBatch];
                         float4 va4[kBatch], vb4[kBatch];
@@ -627,6 +634,7 @@ void grid_block_kernel(
                         pv += 2 * kBatch;
                     };
                     load_batch();
+                    wait_scalar_loads();
                     for (uint32_t r = rb; r < re; r += kBatch) {
                         RecMeta mm[kBatch];
                         float4 va4[kBatch], vb4[kBatch];
