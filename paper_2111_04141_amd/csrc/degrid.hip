@@ -428,9 +428,21 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                 const uint32_t ngroups = (ch.len + B - 1) / B;
                 const uint32_t gfirst = ((uint32_t)wave + kWavesPerGroup - turn) % kWavesPerGroup;
                 turn = (turn + ngroups) % kWavesPerGroup;
+                // the records of this wave's next group are loaded while the
+                // current group's taps are (indices clamped into the chunk)
+                RecMeta mnext[B];
+                auto load_meta = [&](const uint32_t g) {
+#pragma unroll
+                    for (int bi = 0; bi < B; ++bi)
+                        mnext[bi] = smeta[min(ch.start + g * B + (uint32_t)bi, rend - 1)];
+                };
+                load_meta(gfirst);
                 for (uint32_t gi = gfirst; gi < ngroups; gi += kWavesPerGroup) {
                     const uint32_t r0 = ch.start + gi * B;
                     const uint32_t nb = min((uint32_t)B, rend - r0);
+                    // destination of this lane's sum (read now, used after the
+                    // reduction)
+                    const uint32_t dst = sperm[r0 + min((uint32_t)(my_idx >> 3), nb - 1)];
                     float part[NV];
 #pragma unroll
                     for (int i = 0; i < NV; ++i) part[i] = 0.0f;
@@ -440,7 +452,7 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                     const char *tbv[B];
 #pragma unroll
                     for (int bi = 0; bi < B; ++bi) {
-                        const RecMeta m = smeta[min(r0 + (uint32_t)bi, rend - 1)];
+                        const RecMeta m = mnext[bi];
                         sg[bi] = ((int)meta_kv(m) - cv0) * kRowStride + ((int)meta_ku(m) - cu0);
                         if constexpr (SEP) {
                             tb[bi] = tbase + (size_t)(m.toff & 0xffffu) * kElem;
@@ -450,6 +462,7 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                             tbv[bi] = nullptr;
                         }
                     }
+                    load_meta(gi + kWavesPerGroup);
                     // tap weight and the 4 grid values of one tap of record bi
                     auto load = [&](const int bi, const int g_off, uint32_t o, uint32_t ov,
                                     float2 &w, float2 (&gv)[4]) {
@@ -529,8 +542,7 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                     if (writer) {
                         const int bi = my_idx >> 3, q = my_idx & 7;
                         if ((uint32_t)bi < nb && (q >> 1) < npol)
-                            vis_out[((size_t)sperm[r0 + bi] * npol + (q >> 1)) * 2 + (q & 1)] =
-                                part[0];
+                            vis_out[((size_t)dst * npol + (q >> 1)) * 2 + (q & 1)] = part[0];
                     }
                 }
             };

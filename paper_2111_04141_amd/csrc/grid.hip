@@ -49,7 +49,9 @@ namespace {
 
 constexpr uint32_t kNoCell = 0xffffffffu;
 constexpr int kBatch = 2;   // records per batch of scalar loads
-static_assert(kBatch + 1 <= kRecPad, "the sorted arrays are padded for one batch of read-ahead");
+// the last batch of a range starts at most kBatch - 1 past its end and the
+// read-ahead batch kBatch further: the sorted arrays are padded for that
+static_assert(2 * kBatch - 1 <= kRecPad, "record read-ahead runs past the padding");
 
 // Waits for every outstanding scalar load.  Called once after a record
 // loop's first batch is issued: otherwise the compiler places the wait for
