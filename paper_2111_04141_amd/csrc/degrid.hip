@@ -258,8 +258,24 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
         };
 
         auto records = [&](auto exact_t) {
-            for (uint32_t r0 = ch.start; r0 < ch.start + ch.len; r0 += B) {
-                const uint32_t nb = min((uint32_t)B, ch.start + ch.len - r0);
+            const uint32_t rend = ch.start + ch.len;
+            // the next group's records are loaded while this group's taps are
+            // (indices clamped into the chunk)
+            RecMeta mnext[B];
+            auto load_meta = [&](const uint32_t r) {
+#pragma unroll
+                for (int bi = 0; bi < B; ++bi) mnext[bi] = smeta[min(r + (uint32_t)bi, rend - 1)];
+            };
+            load_meta(ch.start);
+            for (uint32_t r0 = ch.start; r0 < rend; r0 += B) {
+                const uint32_t nb = min((uint32_t)B, rend - r0);
+                // destination of the sums this thread writes (read now, used
+                // after the reductions)
+                const uint32_t dst = sperm[r0 + min((uint32_t)threadIdx.x >> 3, nb - 1)];
+                RecMeta m[B];
+#pragma unroll
+                for (int bi = 0; bi < B; ++bi) m[bi] = mnext[bi];
+                load_meta(r0 + B);
                 float part[NV];
 #pragma unroll
                 for (int i = 0; i < NV; ++i) part[i] = 0.0f;
@@ -267,7 +283,7 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
                 for (int bi = 0; bi < B; ++bi) {
                     if ((uint32_t)bi < nb) {
                         float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                        visit(smeta[r0 + bi], acc, exact_t);
+                        visit(m[bi], acc, exact_t);
 #pragma unroll
                         for (int q = 0; q < 8; ++q) part[bi * 8 + q] = acc[q];
                     }
@@ -281,7 +297,7 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
                         float sum = 0.0f;
 #pragma unroll
                         for (int w = 0; w < NW; ++w) sum += s_part[parity][w][threadIdx.x];
-                        vis_out[((size_t)sperm[r0 + bi] * npol + (q >> 1)) * 2 + (q & 1)] = sum;
+                        vis_out[((size_t)dst * npol + (q >> 1)) * 2 + (q & 1)] = sum;
                     }
                 }
                 // the other buffer takes the next group, so one barrier per
@@ -360,14 +376,27 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
         const int RW = (int)(uend - umin);
         const int RH = (int)(vend - vmin);
 
-        // stage the region (cells outside it are never read)
-        for (int i = threadIdx.x; i < npol * RH * RW; i += kGroupThreads) {
-            const int ru = i % RW;
-            const int t = i / RW;
-            const int rv = t % RH;
-            const int pol = t / RH;
-            region[rv * kRowStride + pol * kPitch + ru] = *reinterpret_cast<const float2 *>(
-                grid + 2 * (((int64_t)pol * prm.nv + cv0 + rv) * prm.nu + cu0 + ru));
+        // stage the region (cells outside it are never read); cell
+        // j = rv * RW + ru of each polarisation, a thread stepping j by the
+        // workgroup size and (rv, ru) by a fixed step (no division per cell)
+        {
+            const int cells = RH * RW;
+            const int step_u = kGroupThreads % RW, step_v = kGroupThreads / RW;
+            const int ru0 = (int)threadIdx.x % RW, rv0 = (int)threadIdx.x / RW;
+            for (int pol = 0; pol < npol; ++pol) {
+                const float2 *gp = reinterpret_cast<const float2 *>(grid) +
+                                   ((int64_t)pol * prm.nv + cv0) * prm.nu + cu0;
+                int ru = ru0, rv = rv0;
+                for (int j = threadIdx.x; j < cells; j += kGroupThreads) {
+                    region[rv * kRowStride + pol * kPitch + ru] = gp[(int64_t)rv * prm.nu + ru];
+                    ru += step_u;
+                    rv += step_v;
+                    if (ru >= RW) {
+                        ru -= RW;
+                        ++rv;
+                    }
+                }
+            }
         }
         __syncthreads();
 

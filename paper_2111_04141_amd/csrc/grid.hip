@@ -425,18 +425,30 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
 
         if (use_lds) {
             __syncthreads();
-            const int n = npol * plane_cells;
-            for (int i = threadIdx.x; i < n; i += NW * kWave) {
-                const int ru_ = i % RW;
-                const int t = i / RW;
-                const int rv_ = t % RH;
-                const int pol = t / RH;
-                const int32_t qr = region[(2 * pol) * plane_cells + rv_ * RW + ru_];
-                const int32_t qi = region[(2 * pol + 1) * plane_cells + rv_ * RW + ru_];
-                if ((qr | qi) != 0) {
-                    float *dst = grid + 2 * (((int64_t)pol * prm.nv + cv0 + rv_) * prm.nu + cu0 + ru_);
-                    unsafeAtomicAdd(dst, ldexpf((float)qr, -scale));
-                    unsafeAtomicAdd(dst + 1, ldexpf((float)qi, -scale));
+            // cell j = rv * RW + ru of each polarisation's plane; a thread
+            // steps j by the workgroup size, so its (rv, ru) advance by a
+            // fixed step (no division per cell)
+            constexpr int kThreads = NW * kWave;
+            const int step_u = kThreads % RW, step_v = kThreads / RW;
+            const int ru0 = (int)threadIdx.x % RW, rv0 = (int)threadIdx.x / RW;
+            for (int pol = 0; pol < npol; ++pol) {
+                const int32_t *qre = region + (2 * pol) * plane_cells;
+                const int32_t *qim = qre + plane_cells;
+                float *gp = grid + 2 * (((int64_t)pol * prm.nv + cv0) * prm.nu + cu0);
+                int ru_ = ru0, rv_ = rv0;
+                for (int j = threadIdx.x; j < plane_cells; j += kThreads) {
+                    const int32_t qr = qre[j], qi = qim[j];
+                    if ((qr | qi) != 0) {
+                        float *dst = gp + 2 * ((int64_t)rv_ * prm.nu + ru_);
+                        unsafeAtomicAdd(dst, ldexpf((float)qr, -scale));
+                        unsafeAtomicAdd(dst + 1, ldexpf((float)qi, -scale));
+                    }
+                    ru_ += step_u;
+                    rv_ += step_v;
+                    if (ru_ >= RW) {
+                        ru_ -= RW;
+                        ++rv_;
+                    }
                 }
             }
             __syncthreads();
