@@ -122,12 +122,15 @@ __device__ inline uint32_t next_chunk(uint32_t *queue, uint32_t *slot) {
 // Work items are units: chunks of one tile over the planes of the launch's
 // group.  An item's sums go to an LDS region covering what its chunks can
 // touch, in fixed point, and from there to the grid once per item.
-// Waves per workgroup: four single-wave teams, or two teams of TEAM waves
-// (two such workgroups share a CU's LDS for supports up to 32).
-constexpr int window_waves(int team) { return team == 1 ? 4 : 2 * team; }
+// Waves per workgroup: four single-wave teams, or eight waves in teams of
+// TEAM (two such workgroups share a CU's LDS for supports up to 32, and the
+// multi-wave instances are held to four waves per SIMD: beyond 128 VGPRs the
+// eight-slot instance ran a third slower at three waves per SIMD).
+constexpr int window_waves(int team) { return team == 1 ? 4 : 8; }
 
 template <int KMAX, int TEAM, bool SEP, typename TapT>
-__global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel(
+__global__ __launch_bounds__(kWave * window_waves(TEAM))
+__attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
     const RecMeta *__restrict__ smeta, const float4 *__restrict__ svis, float *__restrict__ grid,
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
     const uint32_t *__restrict__ bucket_cfirst, const uint2 *__restrict__ units,
@@ -412,13 +415,24 @@ __global__ __launch_bounds__(kWave * window_waves(TEAM)) void grid_window_kernel
             const int kdyn = (q_ + kWave - 1) / kWave;
             if constexpr (KMAX == 1) {
                 run(std::integral_constant<int, 1>{});
-            } else {
-                static_assert(KMAX == 4, "slot counts 1..4");
+            } else if constexpr (KMAX == 4) {
                 switch (kdyn) {
                 case 1: run(std::integral_constant<int, 1>{}); break;
                 case 2: run(std::integral_constant<int, 2>{}); break;
                 case 3: run(std::integral_constant<int, 3>{}); break;
                 default: run(std::integral_constant<int, 4>{}); break;
+                }
+            } else {
+                static_assert(KMAX == 8, "slot counts 1..8");
+                switch (kdyn) {
+                case 1: run(std::integral_constant<int, 1>{}); break;
+                case 2: run(std::integral_constant<int, 2>{}); break;
+                case 3: run(std::integral_constant<int, 3>{}); break;
+                case 4: run(std::integral_constant<int, 4>{}); break;
+                case 5: run(std::integral_constant<int, 5>{}); break;
+                case 6: run(std::integral_constant<int, 6>{}); break;
+                case 7: run(std::integral_constant<int, 7>{}); break;
+                default: run(std::integral_constant<int, 8>{}); break;
                 }
             }
         }
@@ -804,7 +818,7 @@ hipError_t launch_class(int cls, const GridPtrs &a, const GridParams &prm, int s
     switch (cls) {
     case 0: launch_window<1, 1, SEP, TapT>(a, prm, lds, stream); break;
     case 1: launch_window<4, 1, SEP, TapT>(a, prm, lds, stream); break;
-    case 2: launch_window<4, 4, SEP, TapT>(a, prm, lds, stream); break;
+    case 2: launch_window<8, 2, SEP, TapT>(a, prm, lds, stream); break;
     default:
         if (region_blocks(tile, smax) > 7 * 16) return hipErrorInvalidValue;
         launch_block<7, 16, SEP, TapT>(a, prm, stream);

@@ -100,7 +100,7 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hip
 // Support classes (each has its own gridding and degridding kernels):
 //   class 0: S <= 8   moving window, one slot per lane
 //   class 1: S <= 16  moving window, up to 4 slots per lane
-//   class 2: S <= 32  moving window held by teams of 4 waves, up to 4 slots
+//   class 2: S <= 32  moving window held by teams of 2 waves, up to 8 slots
 //                     per lane
 //   class 3: S <= 64  blocked output-stationary kernel (registers per 8 x 8
 //                     block of the unit's region)
