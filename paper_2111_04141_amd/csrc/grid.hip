@@ -12,7 +12,7 @@
 //    stays inside the footprints of consecutive records.  This is the
 //    owner-computes scheme of Romein's GPU gridder, which the thesis's
 //    Convolutional Gridder builds on (Chapter 4); the slots are spread over
-//    the 64 lanes of a wave (up to S = 16) or of a team of four waves (up to
+//    the 64 lanes of a wave (up to S = 16) or of a team of two waves (up to
 //    S = 32), and the records come cell-sorted, so windows move rarely where
 //    records are dense.
 //  * When a slot's cell leaves the footprint its sums are committed into an
