@@ -317,20 +317,29 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
 // workgroup takes a unit (chunks of one tile over the planes of the group);
 // the unit's grid region is staged once in LDS as [row][pol][col] float2
 // rows of PITCH columns (a row stride of 4 PITCH + 8 float2, 16 banks
-// modulo 64, spreads the rows of a footprint over the LDS banks); the four
+// modulo 64, spreads the rows of a footprint over the LDS banks); the
 // waves of the workgroup take groups of B records in turn, and each group's
 // sums are reduced across the wave's lanes only.
 template <int PITCH>
 constexpr int row_stride() { return 4 * PITCH + 8; }
 
+// Waves per workgroup of the taps kernel: the S <= 8 and S <= 32 instances
+// share each staged region among eight waves, which doubles the waves a CU
+// holds where the region's LDS (S <= 32) or the workgroup count (S <= 8)
+// limits them; the S <= 16 instance is held to four waves per SIMD by its
+// registers either way.
+constexpr int taps_waves(int ntap) { return ntap == 4 ? 4 : 8; }
+
 template <int NTAP, int PITCH, int B, bool SEP, typename TapT>
-__global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
+__global__ __launch_bounds__(kWave * taps_waves(NTAP)) void degrid_taps_kernel(
     const RecMeta *__restrict__ smeta, const uint32_t *__restrict__ sperm,
     const float *__restrict__ grid, float *__restrict__ vis_out, const TapT *__restrict__ taps,
     const Chunk *__restrict__ chunks, const uint32_t *__restrict__ bucket_cfirst,
     const uint2 *__restrict__ units, const uint32_t *__restrict__ group_nunits,
     const PlaneLayout *__restrict__ planes, uint32_t *__restrict__ queue, DegridParams prm) {
     constexpr int NV = B * 8;
+    constexpr int kWaves = taps_waves(NTAP);
+    constexpr int kThreads = kWave * kWaves;
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);
     constexpr int kPitch = PITCH;
     constexpr int kRowStride = row_stride<PITCH>();
@@ -381,13 +390,13 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
         // workgroup size and (rv, ru) by a fixed step (no division per cell)
         {
             const int cells = RH * RW;
-            const int step_u = kGroupThreads % RW, step_v = kGroupThreads / RW;
+            const int step_u = kThreads % RW, step_v = kThreads / RW;
             const int ru0 = (int)threadIdx.x % RW, rv0 = (int)threadIdx.x / RW;
             for (int pol = 0; pol < npol; ++pol) {
                 const float2 *gp = reinterpret_cast<const float2 *>(grid) +
                                    ((int64_t)pol * prm.nv + cv0) * prm.nu + cu0;
                 int ru = ru0, rv = rv0;
-                for (int j = threadIdx.x; j < cells; j += kGroupThreads) {
+                for (int j = threadIdx.x; j < cells; j += kThreads) {
                     region[rv * kRowStride + pol * kPitch + ru] = gp[(int64_t)rv * prm.nu + ru];
                     ru += step_u;
                     rv += step_v;
@@ -455,8 +464,8 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                 // the chunk's last record (its sums are not written)
                 const uint32_t rend = ch.start + ch.len;
                 const uint32_t ngroups = (ch.len + B - 1) / B;
-                const uint32_t gfirst = ((uint32_t)wave + kWavesPerGroup - turn) % kWavesPerGroup;
-                turn = (turn + ngroups) % kWavesPerGroup;
+                const uint32_t gfirst = ((uint32_t)wave + kWaves - turn) % kWaves;
+                turn = (turn + ngroups) % kWaves;
                 // the records of this wave's next group are loaded while the
                 // current group's taps are (indices clamped into the chunk)
                 RecMeta mnext[B];
@@ -466,7 +475,7 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                         mnext[bi] = smeta[min(ch.start + g * B + (uint32_t)bi, rend - 1)];
                 };
                 load_meta(gfirst);
-                for (uint32_t gi = gfirst; gi < ngroups; gi += kWavesPerGroup) {
+                for (uint32_t gi = gfirst; gi < ngroups; gi += kWaves) {
                     const uint32_t r0 = ch.start + gi * B;
                     const uint32_t nb = min((uint32_t)B, rend - r0);
                     // destination of this lane's sum (read now, used after the
@@ -491,7 +500,7 @@ __global__ __launch_bounds__(kGroupThreads) void degrid_taps_kernel(
                             tbv[bi] = nullptr;
                         }
                     }
-                    load_meta(gi + kWavesPerGroup);
+                    load_meta(gi + kWaves);
                     // tap weight and the 4 grid values of one tap of record bi
                     auto load = [&](const int bi, const int g_off, uint32_t o, uint32_t ov,
                                     float2 &w, float2 (&gv)[4]) {
@@ -650,12 +659,13 @@ hipError_t launch_dt(const DegridPtrs &a, const DegridParams &prm, int tile, int
     // records per reduction group: two where a lane holds several taps
     // (registers; the reduction costs about the same per record either way)
     auto kern = degrid_taps_kernel<NTAP, PITCH, (NTAP > 1 ? 2 : 4), SEP, TapT>;
+    constexpr int threads = kWave * taps_waves(NTAP);
     int dev = 0, cus = 0, per = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kGroupThreads, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, lds) != hipSuccess)
         per = 1;
-    hipLaunchKernelGGL(kern, dim3(std::max(1, per) * std::max(1, cus)), dim3(kGroupThreads), lds,
+    hipLaunchKernelGGL(kern, dim3(std::max(1, per) * std::max(1, cus)), dim3(threads), lds,
                        stream, a.smeta, a.sperm, a.grid, a.vis_out, (const TapT *)a.taps,
                        a.chunks, a.bucket_cfirst, a.units, a.group_nunits, a.planes, a.queue,
                        prm);

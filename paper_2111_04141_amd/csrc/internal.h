@@ -124,7 +124,4 @@ inline size_t dtype_size(mg_dtype d) {
 
 inline int support_class(int S) { return S <= 8 ? 0 : S <= 16 ? 1 : S <= 32 ? 2 : 3; }
 
-constexpr int kWavesPerGroup = 4;
-constexpr int kGroupThreads = kWave * kWavesPerGroup;
-
 }  // namespace mg
