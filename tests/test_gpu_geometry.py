@@ -31,6 +31,11 @@ CASES = [
     ("wproj-groups", "wproj", 300, 260, 2, [6, 8, 10, 12, 16, 18, 24, 32, 34, 48], 4, "f32"),
     # supports out of order: every plane its own group, classes interleaved
     ("wproj-unordered", "wproj", 280, 300, 2, [40, 10, 20, 8, 12, 36], 3, "f32"),
+    # every support of the 17..32 class in one group (each slot count 3..8 of
+    # its two-wave teams, odd supports included), and the separable kernel
+    # at the class's largest slot count
+    ("wproj-class2-all", "wproj", 300, 300, 4, list(range(17, 33)), 4, "f32"),
+    ("sep-S31-b2", "sep", 300, 290, 2, [31], 4, "f32"),
 ]
 
 
