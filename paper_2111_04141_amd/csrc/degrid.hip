@@ -1,13 +1,13 @@
 // Degridding (gather): vis_out[r] = sum_{i,j} conj(w_ij) G[k_lo + (i, j)], the
 // adjoint of the gridding map.
 //
-// Supports above 32 (degrid_block_kernel): work unit one chunk of records of
-// one (plane, tile) bucket.  The grid region the chunk can touch (its tile
-// plus an S - 1 halo) is cut into 8 x 8-cell blocks, one cell per lane;
-// block b belongs to wave b mod NW and its 4 polarisations stay in
-// registers for the whole chunk, so the grid is read once per chunk with
-// coalesced loads.  Every wave walks all records of the chunk (scalar
-// loads).  Per record, a vector compare and a ballot give the wave's blocks
+// Supports above 32 (degrid_block_kernel): work unit a unit, the chunks of
+// one tile over the planes of the launch's group.  The grid region the unit
+// can touch (its tile plus the group's largest S - 1 halo) is cut into
+// 8 x 8-cell blocks, one cell per lane; block b belongs to wave b mod NW and
+// its 4 polarisations stay in registers for the whole unit, so the grid is
+// read once per unit with coalesced loads.  Every wave walks all records of
+// the unit's chunks (scalar loads).  Per record, a vector compare and a ballot give the wave's blocks
 // that the footprint overlaps; each takes one tap load and 16 multiply-adds
 // per lane into the record's partial sums.  Partial sums of B records are
 // then reduced across the wave's lanes (a butterfly that halves the values
@@ -120,7 +120,8 @@ template <int KMAX, int NW, int B, bool SEP, typename TapT>
 __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
     const RecMeta *__restrict__ smeta, const uint32_t *__restrict__ sperm,
     const float *__restrict__ grid, float *__restrict__ vis_out, const TapT *__restrict__ taps,
-    const Chunk *__restrict__ chunks, const uint32_t *__restrict__ plane_cfirst,
+    const Chunk *__restrict__ chunks, const uint32_t *__restrict__ bucket_cfirst,
+    const uint2 *__restrict__ units, const uint32_t *__restrict__ group_nunits,
     const PlaneLayout *__restrict__ planes, uint32_t *__restrict__ queue, DegridParams prm) {
     constexpr int NV = B * 8;   // partial values per lane: B records x 4 pol x (re, im)
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);
@@ -130,56 +131,54 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
     const int lane = threadIdx.x & 63;
     const int lu = lane & 7, lv = lane >> 3;
     const int npol = prm.npol;
-    const uint32_t c_begin = plane_cfirst[prm.p_lo];
-    const uint32_t c_end = plane_cfirst[prm.p_hi];
     const char *tbase = reinterpret_cast<const char *>(taps);
     const int my_idx = reduce_index<NV>(lane);
     const bool writer = reduce_writer<NV>(lane);
-    int p = prm.p_lo;
     int parity = 0;
 
-    for (uint32_t c = c_begin + next_chunk_dg(queue, &s_next); c < c_end;
-         c = c_begin + next_chunk_dg(queue, &s_next)) {
-        const Chunk ch = chunks[c];
-        while (p + 1 < prm.p_hi && c >= plane_cfirst[p + 1]) ++p;
-        int pc;
-        uint32_t tile;
-        bucket_plane_tile(planes[p], ch.bucket, &pc, &tile);
-        const PlaneLayout pl = planes[pc];
-        const int S = pl.S;
-        const int Tm = pl.T - 1;
-        const int cu0 = (int)((tile % (uint32_t)pl.ntu) << pl.log2T);
-        const int cv0 = (int)((tile / (uint32_t)pl.ntu) << pl.log2T);
-        const int nbx = (pl.T + S - 1 + 7) >> 3;
-        const int nblocks = nbx * nbx;
-
-        uint32_t blo_u = 0xffff0000u, blo_v = 0xffff0000u;
-        {
-            const int b = lane * NW + wave;
-            if (lane < KMAX && b < nblocks) {
-                blo_u = (uint32_t)((b % nbx) << 3);
-                blo_v = (uint32_t)((b / nbx) << 3);
-            }
+    // The launch covers one plane group; its work items are units (chunks of
+    // one tile over the group's planes), whose grid values are loaded once
+    // over the tile plus the group's largest halo.
+    const PlaneLayout g0 = planes[prm.p_lo];
+    const int Tm = g0.T - 1;
+    const uint32_t ntu = (uint32_t)g0.ntu;
+    const uint32_t gn = (uint32_t)g0.grp_n;
+    const uint32_t gbase = (uint32_t)g0.base;
+    const uint32_t nunits = group_nunits[prm.p_lo];
+    const uint2 *gunits = units + bucket_cfirst[gbase];
+    const int nbx = (g0.T + g0.grp_smax - 1 + 7) >> 3;
+    const int nblocks = nbx * nbx;
+    // lane k < KMAX: origin of the wave's block k, for the overlap tests
+    uint32_t blo_u = 0xffff0000u, blo_v = 0xffff0000u;   // never overlaps
+    {
+        const int b = lane * NW + wave;
+        if (lane < KMAX && b < nblocks) {
+            blo_u = (uint32_t)((b % nbx) << 3);
+            blo_v = (uint32_t)((b / nbx) << 3);
         }
-        // this lane's cell of each block: grid values, packed coordinates and
-        // tap offset relative to the footprint's first tap
-        uint32_t cuv[KMAX], voff[KMAX], voffv[KMAX];
+    }
+    // this lane's cell of each block (packed u | v << 16, region-relative)
+    uint32_t cuv[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int b = k * NW + wave;
+        cuv[k] = (uint32_t)(((b % nbx) << 3) + lu) | ((uint32_t)(((b / nbx) << 3) + lv) << 16);
+    }
+
+    for (uint32_t it = next_chunk_dg(queue, &s_next); it < nunits;
+         it = next_chunk_dg(queue, &s_next)) {
+        const uint2 un = gunits[it];
+        const uint32_t c0 = un.x, c1 = un.x + un.y;
+        const uint32_t t = (chunks[c0].bucket - gbase) / gn;
+        const int cu0 = (int)((t % ntu) << g0.log2T);
+        const int cv0 = (int)((t / ntu) << g0.log2T);
+        // this lane's grid values of each block
         float g[KMAX][8];
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const int b = k * NW + wave;
-            const uint32_t cu = (uint32_t)(((b % nbx) << 3) + lu);
-            const uint32_t cv = (uint32_t)(((b / nbx) << 3) + lv);
-            cuv[k] = cu | (cv << 16);
-            if constexpr (SEP) {
-                voff[k] = cu * kElem;
-                voffv[k] = cv * kElem;
-            } else {
-                voff[k] = (cv * (uint32_t)S + cu) * kElem;
-                voffv[k] = 0u;
-            }
-            const int u = cu0 + (int)cu, v = cv0 + (int)cv;
+            const int u = cu0 + (int)(cuv[k] & 0xffffu), v = cv0 + (int)(cuv[k] >> 16);
             const bool in_grid = b < nblocks && u < prm.nu && v < prm.nv;
 #pragma unroll
             for (int pol = 0; pol < 4; ++pol) {
@@ -192,123 +191,146 @@ __global__ __launch_bounds__(NW * kWave) void degrid_block_kernel(
                 bad = bad || !isfinite(x.x) || !isfinite(x.y);
             }
         }
-        // a zero tap times a non-finite grid value is NaN: chunks whose region
+        // a zero tap times a non-finite grid value is NaN: units whose region
         // holds one mask the taps outside each footprint instead
         const bool exact = __syncthreads_or(bad) != 0;
 
-        auto visit = [&](const RecMeta m, float (&acc)[8], auto exact_t) {
-            constexpr bool EXACT = decltype(exact_t)::value;
-            const uint32_t a = meta_ku(m) & (uint32_t)Tm;
-            const uint32_t bq = meta_kv(m) & (uint32_t)Tm;
-            const uint32_t hit = (uint32_t)__ballot((blo_u + 7u - a <= (uint32_t)(S + 6)) &&
-                                                    (blo_v + 7u - bq <= (uint32_t)(S + 6)));
-            const uint32_t full = (uint32_t)__ballot((blo_u - a <= (uint32_t)(S - 8)) &&
-                                                     (blo_v - bq <= (uint32_t)(S - 8)));
-            const uint32_t ab = a | (bq << 16);
-            const char *tb;
-            const char *tbv = nullptr;
-            if constexpr (SEP) {
-                tb = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a) * (int64_t)kElem;
-                tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq) * (int64_t)kElem;
-            } else {
-                tb = tbase + ((int64_t)m.toff - (int64_t)(bq * (uint32_t)S + a)) * (int64_t)kElem;
-            }
-            auto tap = [&](const int k) {
-                uint32_t o = voff[k];
-                asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+        for (uint32_t c = c0; c < c1; ++c) {
+            const Chunk ch = chunks[c];
+            const int S = planes[g0.grp_first + (int)((ch.bucket - gbase) % gn)].S;
+            // this lane's tap offset in each block, in bytes relative to the
+            // footprint's first tap
+            uint32_t voff[KMAX], voffv[KMAX];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const uint32_t cu = cuv[k] & 0xffffu, cv = cuv[k] >> 16;
                 if constexpr (SEP) {
-                    uint32_t ov = voffv[k];
-                    asm volatile("" : "+v"(ov));
-                    const float t = TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
-                                    TapTraits<TapT>::real((const TapT *)(tbv + ov), 0);
-                    return make_float2(t, 0.0f);
+                    voff[k] = cu * kElem;
+                    voffv[k] = cv * kElem;
                 } else {
-                    return TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
+                    voff[k] = (cv * (uint32_t)S + cu) * kElem;
+                    voffv[k] = 0u;
                 }
-            };
-            // acc += conj(w) * G = (wr gr + wi gi) + j (wr gi - wi gr)
-            auto madd = [&](const int k, const float2 w) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float gr = g[k][2 * q], gi = g[k][2 * q + 1];
-                    acc[2 * q] = fmaf(w.x, gr, fmaf(w.y, gi, acc[2 * q]));
-                    acc[2 * q + 1] = fmaf(w.x, gi, fmaf(-w.y, gr, acc[2 * q + 1]));
-                }
-            };
-            if constexpr (EXACT) {
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (!((hit >> k) & 1u)) continue;
-                    const uint32_t d = cuv[k] - ab;   // a borrow only where du < 0
-                    if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S) madd(k, tap(k));
-                }
-            } else {
-                float2 w[KMAX];
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    w[k] = make_float2(0.0f, 0.0f);
-                    if (!((hit >> k) & 1u)) continue;
-                    const uint32_t d = cuv[k] - ab;
-                    if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S) w[k] = tap(k);
-                }
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    if ((hit >> k) & 1u) madd(k, w[k]);
             }
-        };
 
-        auto records = [&](auto exact_t) {
-            const uint32_t rend = ch.start + ch.len;
-            // the next group's records are loaded while this group's taps are
-            // (indices clamped into the chunk)
-            RecMeta mnext[B];
-            auto load_meta = [&](const uint32_t r) {
+            auto visit = [&](const RecMeta m, float (&acc)[8], auto exact_t) {
+                constexpr bool EXACT = decltype(exact_t)::value;
+                const uint32_t a = meta_ku(m) & (uint32_t)Tm;
+                const uint32_t bq = meta_kv(m) & (uint32_t)Tm;
+                const uint32_t hit = (uint32_t)__ballot((blo_u + 7u - a <= (uint32_t)(S + 6)) &&
+                                                        (blo_v + 7u - bq <= (uint32_t)(S + 6)));
+                const uint32_t full = (uint32_t)__ballot((blo_u - a <= (uint32_t)(S - 8)) &&
+                                                         (blo_v - bq <= (uint32_t)(S - 8)));
+                const uint32_t ab = a | (bq << 16);
+                const char *tb;
+                const char *tbv = nullptr;
+                if constexpr (SEP) {
+                    tb = tbase + ((int64_t)(m.toff & 0xffffu) - (int64_t)a) * (int64_t)kElem;
+                    tbv = tbase + ((int64_t)(m.toff >> 16) - (int64_t)bq) * (int64_t)kElem;
+                } else {
+                    tb = tbase +
+                         ((int64_t)m.toff - (int64_t)(bq * (uint32_t)S + a)) * (int64_t)kElem;
+                }
+                auto tap = [&](const int k) {
+                    uint32_t o = voff[k];
+                    asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+                    if constexpr (SEP) {
+                        uint32_t ov = voffv[k];
+                        asm volatile("" : "+v"(ov));
+                        const float t = TapTraits<TapT>::real((const TapT *)(tb + o), 0) *
+                                        TapTraits<TapT>::real((const TapT *)(tbv + ov), 0);
+                        return make_float2(t, 0.0f);
+                    } else {
+                        return TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
+                    }
+                };
+                // acc += conj(w) * G = (wr gr + wi gi) + j (wr gi - wi gr)
+                auto madd = [&](const int k, const float2 w) {
 #pragma unroll
-                for (int bi = 0; bi < B; ++bi) mnext[bi] = smeta[min(r + (uint32_t)bi, rend - 1)];
+                    for (int q = 0; q < 4; ++q) {
+                        const float gr = g[k][2 * q], gi = g[k][2 * q + 1];
+                        acc[2 * q] = fmaf(w.x, gr, fmaf(w.y, gi, acc[2 * q]));
+                        acc[2 * q + 1] = fmaf(w.x, gi, fmaf(-w.y, gr, acc[2 * q + 1]));
+                    }
+                };
+                if constexpr (EXACT) {
+#pragma unroll
+                    for (int k = 0; k < KMAX; ++k) {
+                        if (!((hit >> k) & 1u)) continue;
+                        const uint32_t d = cuv[k] - ab;   // a borrow only where du < 0
+                        if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S)
+                            madd(k, tap(k));
+                    }
+                } else {
+                    float2 w[KMAX];
+#pragma unroll
+                    for (int k = 0; k < KMAX; ++k) {
+                        w[k] = make_float2(0.0f, 0.0f);
+                        if (!((hit >> k) & 1u)) continue;
+                        const uint32_t d = cuv[k] - ab;
+                        if (((full >> k) & 1u) || max(d & 0xffffu, d >> 16) < (uint32_t)S)
+                            w[k] = tap(k);
+                    }
+#pragma unroll
+                    for (int k = 0; k < KMAX; ++k)
+                        if ((hit >> k) & 1u) madd(k, w[k]);
+                }
             };
-            load_meta(ch.start);
-            for (uint32_t r0 = ch.start; r0 < rend; r0 += B) {
-                const uint32_t nb = min((uint32_t)B, rend - r0);
-                // destination of the sums this thread writes (read now, used
-                // after the reductions)
-                const uint32_t dst = sperm[r0 + min((uint32_t)threadIdx.x >> 3, nb - 1)];
-                RecMeta m[B];
+
+            auto records = [&](auto exact_t) {
+                const uint32_t rend = ch.start + ch.len;
+                // the next group's records are loaded while this group's taps are
+                // (indices clamped into the chunk)
+                RecMeta mnext[B];
+                auto load_meta = [&](const uint32_t r) {
 #pragma unroll
-                for (int bi = 0; bi < B; ++bi) m[bi] = mnext[bi];
-                load_meta(r0 + B);
-                float part[NV];
+                    for (int bi = 0; bi < B; ++bi)
+                        mnext[bi] = smeta[min(r + (uint32_t)bi, rend - 1)];
+                };
+                load_meta(ch.start);
+                for (uint32_t r0 = ch.start; r0 < rend; r0 += B) {
+                    const uint32_t nb = min((uint32_t)B, rend - r0);
+                    // destination of the sums this thread writes (read now, used
+                    // after the reductions)
+                    const uint32_t dst = sperm[r0 + min((uint32_t)threadIdx.x >> 3, nb - 1)];
+                    RecMeta m[B];
 #pragma unroll
-                for (int i = 0; i < NV; ++i) part[i] = 0.0f;
+                    for (int bi = 0; bi < B; ++bi) m[bi] = mnext[bi];
+                    load_meta(r0 + B);
+                    float part[NV];
 #pragma unroll
-                for (int bi = 0; bi < B; ++bi) {
-                    if ((uint32_t)bi < nb) {
-                        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                        visit(m[bi], acc, exact_t);
+                    for (int i = 0; i < NV; ++i) part[i] = 0.0f;
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) part[bi * 8 + q] = acc[q];
+                    for (int bi = 0; bi < B; ++bi) {
+                        if ((uint32_t)bi < nb) {
+                            float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                            visit(m[bi], acc, exact_t);
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) part[bi * 8 + q] = acc[q];
+                        }
                     }
-                }
-                wave_reduce_scatter<NV>(part, lane);
-                if (writer) s_part[parity][wave][my_idx] = part[0];
-                __syncthreads();
-                if ((int)threadIdx.x < NV) {
-                    const int bi = threadIdx.x >> 3, q = threadIdx.x & 7;
-                    if ((uint32_t)bi < nb && (q >> 1) < npol) {
-                        float sum = 0.0f;
+                    wave_reduce_scatter<NV>(part, lane);
+                    if (writer) s_part[parity][wave][my_idx] = part[0];
+                    __syncthreads();
+                    if ((int)threadIdx.x < NV) {
+                        const int bi = threadIdx.x >> 3, q = threadIdx.x & 7;
+                        if ((uint32_t)bi < nb && (q >> 1) < npol) {
+                            float sum = 0.0f;
 #pragma unroll
-                        for (int w = 0; w < NW; ++w) sum += s_part[parity][w][threadIdx.x];
-                        vis_out[((size_t)dst * npol + (q >> 1)) * 2 + (q & 1)] = sum;
+                            for (int w = 0; w < NW; ++w) sum += s_part[parity][w][threadIdx.x];
+                            vis_out[((size_t)dst * npol + (q >> 1)) * 2 + (q & 1)] = sum;
+                        }
                     }
+                    // the other buffer takes the next group, so one barrier per
+                    // group keeps the readers ahead of the next writers
+                    parity ^= 1;
                 }
-                // the other buffer takes the next group, so one barrier per
-                // group keeps the readers ahead of the next writers
-                parity ^= 1;
-            }
-        };
-        if (exact)
-            records(std::true_type{});
-        else
-            records(std::false_type{});
+            };
+            if (exact)
+                records(std::true_type{});
+            else
+                records(std::false_type{});
+        }
     }
 }
 
@@ -624,7 +646,6 @@ struct DegridPtrs {
     float *vis_out;
     const void *taps;
     const Chunk *chunks;
-    const uint32_t *plane_cfirst;
     const uint32_t *bucket_cfirst;
     const uint2 *units;
     const uint32_t *group_nunits;
@@ -646,7 +667,8 @@ hipError_t launch_dg(const DegridPtrs &a, const DegridParams &prm, int tile, int
         per = 1;
     hipLaunchKernelGGL(kern, dim3(std::max(1, per) * std::max(1, cus)), dim3(NW * kWave), 0,
                        stream, a.smeta, a.sperm, a.grid, a.vis_out, (const TapT *)a.taps,
-                       a.chunks, a.plane_cfirst, a.planes, a.queue, prm);
+                       a.chunks, a.bucket_cfirst, a.units, a.group_nunits, a.planes, a.queue,
+                       prm);
     return hipGetLastError();
 }
 
@@ -708,9 +730,9 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hip
         hipLaunchKernelGGL(zero_skipped_kernel, dim3((unsigned)nb), dim3(256), 0, stream,
                            P.counters, P.nrec, P.sperm, P.geom.npol, (float2 *)vis_out);
     }
-    DegridPtrs a{P.smeta,         P.sperm,          (const float *)grid, (float *)vis_out,
-                 P.taps,          P.chunks,         P.plane_cfirst,      P.bucket_cfirst,
-                 P.units,         P.group_nunits,   P.d_planes,          nullptr};
+    DegridPtrs a{P.smeta,    P.sperm,         (const float *)grid, (float *)vis_out,
+                 P.taps,     P.chunks,        P.bucket_cfirst,     P.units,
+                 P.group_nunits, P.d_planes,  nullptr};
     DegridParams prm{P.geom.npol, P.geom.nu, P.geom.nv, P.geom.beta, 0, 0};
     const bool sep = P.kind == MG_KERNEL_SEPARABLE;
     // one launch per run of consecutive planes of the same class
