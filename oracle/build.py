@@ -2,7 +2,9 @@
 
 gcc -O2 -ffp-contract=off keeps every floating-point operation of the index
 rule and of the accumulations rounded exactly as written (no fused
-multiply-add contraction)."""
+multiply-add contraction).  OpenMP is enabled for the band-parallel
+gridder used for the CPU rate (orc_grid_window_par); every other function is
+single-threaded."""
 import os
 import subprocess
 import sys
@@ -14,7 +16,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC",
-           "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-fopenmp", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)

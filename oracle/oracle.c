@@ -34,6 +34,12 @@
  * All arithmetic in double, compiled with -ffp-contract=off so that the
  * index rule rounds exactly as written.  Records are visited in input order.
  *
+ * orc_grid_window_par is the same gridder run on several host threads, for
+ * the CPU rate only: the window's rows are cut into bands, every band is
+ * owned by one thread and visits, in input order, the records whose
+ * footprint reaches it, so each cell receives its contributions in the same
+ * order as in orc_grid_window and the two agree bit for bit.
+ *
  * Parity pins (in tests/): delta kernel at integer cells, brute-force
  * footprint enumeration, the equivalence theorem (NN onto the beta grid,
  * then a discrete convolution), equal-offset exactness against a direct DFT
@@ -42,7 +48,11 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
@@ -293,4 +303,114 @@ void orc_dft(int64_t nrec, const double *pos, const double *F, int32_t nx, int32
             image[2 * ((int64_t)iy * nx + ix) + 1] = si;
         }
     }
+}
+
+/* Band-parallel gridding for the CPU rate (same result as orc_grid_window,
+ * bit for bit).  The window's wv rows are split into nbands bands of equal
+ * height; pass 1 indexes every record once and counts it in each band its
+ * footprint rows reach; pass 2 lets the threads take bands (dynamically) and
+ * apply, in input order, the taps of the band's records that fall on the
+ * band's rows.  nthreads <= 0 uses the OpenMP default.  Returns the skipped
+ * count, ORC_EINVAL, or -2 if the record lists cannot be allocated. */
+int64_t orc_grid_window_par(GEOM_ARGS, const double *taps, const int64_t *plane_offset,
+                            int64_t nrec, const double *uvw, int32_t npol, const double *vis,
+                            int32_t u0, int32_t v0, int32_t wu, int32_t wv, double *out,
+                            int32_t nthreads, int32_t nbands)
+{
+    orc_geom g = GEOM_INIT;
+    if (check_geom(&g) || npol < 1 || nbands < 1 || wv < 1)
+        return ORC_EINVAL;
+    if (nbands > wv)
+        nbands = wv;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    const int64_t bh = ((int64_t)wv + nbands - 1) / nbands;   /* rows per band */
+    int64_t *cnt = calloc((size_t)nbands + 1, sizeof(int64_t));
+    int32_t *first = malloc(sizeof(int32_t) * (size_t)(nrec > 0 ? nrec : 1));
+    int32_t *last = malloc(sizeof(int32_t) * (size_t)(nrec > 0 ? nrec : 1));
+    if (!cnt || !first || !last) {
+        free(cnt); free(first); free(last);
+        return -2;
+    }
+    int64_t skipped = 0;
+    /* pass 1: band range of every valid record (first > last: none) */
+#pragma omp parallel for schedule(static) reduction(+ : skipped)
+    for (int64_t r = 0; r < nrec; ++r) {
+        rec_index ix = index_record(&g, uvw + 3 * r);
+        first[r] = 1;
+        last[r] = 0;
+        if (!ix.valid) {
+            ++skipped;
+            continue;
+        }
+        int64_t lo = ix.k_lo_v - v0, hi = ix.k_lo_v + ix.S - 1 - v0;
+        int64_t cu_lo = ix.k_lo_u - u0, cu_hi = ix.k_lo_u + ix.S - 1 - u0;
+        if (hi < 0 || lo >= wv || cu_hi < 0 || cu_lo >= wu)
+            continue;
+        if (lo < 0)
+            lo = 0;
+        if (hi >= wv)
+            hi = wv - 1;
+        first[r] = (int32_t)(lo / bh);
+        last[r] = (int32_t)(hi / bh);
+    }
+    for (int64_t r = 0; r < nrec; ++r)
+        for (int32_t b = first[r]; b <= last[r]; ++b)
+            cnt[b + 1]++;
+    for (int32_t b = 0; b < nbands; ++b)
+        cnt[b + 1] += cnt[b];
+    int64_t *list = malloc(sizeof(int64_t) * (size_t)(cnt[nbands] > 0 ? cnt[nbands] : 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)nbands);
+    if (!list || !fill) {
+        free(cnt); free(first); free(last); free(list); free(fill);
+        return -2;
+    }
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)nbands);
+    for (int64_t r = 0; r < nrec; ++r)          /* input order inside every band */
+        for (int32_t b = first[r]; b <= last[r]; ++b)
+            list[fill[b]++] = r;
+    /* pass 2: every band's records, rows of the band only */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t b = 0; b < nbands; ++b) {
+        const int64_t row_lo = (int64_t)b * bh;
+        const int64_t row_hi = row_lo + bh < wv ? row_lo + bh : wv;   /* exclusive */
+        for (int64_t e = cnt[b]; e < cnt[b + 1]; ++e) {
+            const int64_t r = list[e];
+            rec_index ix = index_record(&g, uvw + 3 * r);
+            for (int32_t j = 0; j < ix.S; ++j) {
+                int64_t cv = ix.k_lo_v + j - v0;
+                if (cv < row_lo || cv >= row_hi)
+                    continue;
+                for (int32_t i = 0; i < ix.S; ++i) {
+                    int64_t cu = ix.k_lo_u + i - u0;
+                    if (cu < 0 || cu >= wu)
+                        continue;
+                    double wr, wi;
+                    tap_weight(&g, taps, plane_offset, &ix, i, j, &wr, &wi);
+                    for (int32_t pol = 0; pol < npol; ++pol) {
+                        const double *V = vis + 2 * (r * npol + pol);
+                        double *G = out + 2 * (((int64_t)pol * wv + cv) * wu + cu);
+                        G[0] += wr * V[0] - wi * V[1];
+                        G[1] += wr * V[1] + wi * V[0];
+                    }
+                }
+            }
+        }
+    }
+    free(cnt); free(first); free(last); free(list); free(fill);
+    return skipped;
+}
+
+/* Threads the OpenMP runtime would use (1 without OpenMP). */
+int32_t orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

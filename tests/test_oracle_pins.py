@@ -309,7 +309,7 @@ def test_equal_offset_exactness_against_direct_sum(kind):
     G, sk = oracle.grid(g, taps, uvw, F)
     assert sk == 0
     img = _inverse_dft_of_grid(G[0], n)
-    dft = _direct_sum(pos, F, n)
+    dft = oracle.dft(pos, F, n, n)        # pinned by test_direct_fourier_sum_*
     # l_co(delta, x): sum over the footprint offsets m - delta in (-S/2, S/2]
     l = (np.arange(n) - n // 2) / n
     offs_u = [Fraction(mm) - Fraction(du).limit_denominator(64) for mm in range(-S - 1, S + 2)]
@@ -326,6 +326,72 @@ def test_equal_offset_exactness_against_direct_sum(kind):
     want = dft * lco
     err = np.linalg.norm(img - want) / np.linalg.norm(want)
     assert err < 1e-12, err
+
+
+def test_direct_fourier_sum_plane_waves():
+    """orc_dft (the direct sum of the problem statement, Section 2.2, with
+    the image-from-visibility sign of Section 1.7): one unit record at
+    integer cell k is the exact plane wave exp(+j2pi k.(x - n/2)/n), with u
+    along x (columns) and v along y (rows); the phase is reduced modulo n in
+    integers, so the closed form is exact.  A record at a fractional position
+    gives exp(+j2pi (p_u l + p_v m)); a complex amplitude multiplies it; two
+    records superpose."""
+    nx, ny = 24, 16
+    x = np.arange(nx) - nx // 2
+    y = np.arange(ny) - ny // 2
+    for ku, kv in [(0, 0), (1, 0), (0, 1), (3, -5), (-7, 2), (11, 7)]:
+        img = oracle.dft([[ku, kv]], [1.0], nx, ny)
+        ph_u = ((ku * x) % nx) / nx
+        ph_v = ((kv * y) % ny) / ny
+        want = np.exp(2j * np.pi * ph_v)[:, None] * np.exp(2j * np.pi * ph_u)[None, :]
+        assert np.abs(img - want).max() < 1e-13, (ku, kv)
+    pu, pv, F = 2.375, -1.625, 0.5 - 2.0j
+    img = oracle.dft([[pu, pv]], [F], nx, ny)
+    want = F * np.exp(2j * np.pi * pv * y / ny)[:, None] * np.exp(2j * np.pi * pu * x / nx)[None, :]
+    assert np.abs(img - want).max() < 1e-12
+    both = oracle.dft([[3, -5], [pu, pv]], [1.0, F], nx, ny)
+    assert np.abs(both - oracle.dft([[3, -5]], [1.0], nx, ny) - img).max() < 1e-12
+
+
+def test_direct_fourier_sum_matches_separable_matrix_form():
+    """orc_dft against an independent evaluation of the same sum as a
+    product of two exponential matrices (square image)."""
+    rng = _rng(21)
+    n = 20
+    pos = rng.uniform(-n / 2, n / 2, (50, 2))
+    F = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    got = oracle.dft(pos, F, n, n)
+    want = _direct_sum(pos, F, n)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["separable", "wproj"])
+def test_parallel_gridder_equals_serial_bit_for_bit(kind):
+    """orc_grid_window_par (the CPU-rate build) gives the serial oracle's
+    grid bit for bit: every cell gets the same contributions in the same
+    order.  Full grid and a window, out-of-grid records, several thread and
+    band counts."""
+    rng = _rng(22)
+    n = 72
+    nrec = 3000
+    uvw = np.concatenate([rng.uniform(-40, 40, (nrec, 2)), rng.uniform(-30, 30, (nrec, 1))], 1)
+    vis = rng.standard_normal((nrec, 3)) + 1j * rng.standard_normal((nrec, 3))
+    if kind == "separable":
+        g = Geometry(nu=n, nv=n, beta=8, scale_u=0.9, scale_v=1.1, support=7)
+        taps = W.pswf_taps(7, 8)
+    else:
+        bank = W.wproj_bank(5, 8, 16, 4, w_absmax=30.0, fov_rad=0.2)
+        g = Geometry(nu=n, nv=n, beta=4, scale_u=1.0, scale_v=1.0, kind="wproj",
+                     plane_support=bank.supports, plane_offset=bank.offsets,
+                     inv_dw=bank.inv_dw)
+        taps = bank.taps
+    for window in (None, (5, 9, 40, 33)):
+        ref, sk = oracle.grid(g, taps, uvw, vis, window=window)
+        assert sk > 0
+        for nt, nb in ((1, 1), (3, 7), (8, 64), (4, 1000)):
+            got, sk2 = oracle.grid_par(g, taps, uvw, vis, window=window, nthreads=nt, nbands=nb)
+            assert sk2 == sk
+            assert np.array_equal(got, ref), (window, nt, nb)
 
 
 # ---------------------------------------------------------------------------
