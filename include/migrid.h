@@ -12,7 +12,7 @@
  *   polarisation of a record is gridded with the same weights (Section 1.1).
  *   Degridding is the adjoint map (the forward/backward operator pair of the
  *   major-cycle residual, Section 1.6), which the thesis names as future work
- *   (Chapter 8).
+ *   (Section 9.1).
  *
  * Index rule (identical in every entry point, computed in FP64):
  *   x = coord * scale + n/2            cells, origin at the centre pixel
@@ -109,9 +109,12 @@ const char *mg_status_str(mg_status s);
 const char *mg_last_error(void);
 
 /* Per-record integer indices of the index rule above, in input order
- * (parity and debugging).  Outputs are device arrays of nrec entries:
- * k_lo_u, k_lo_v, o_u, o_v, plane (-1 for a separable kernel), valid (0/1).
- * *d_nskipped (device, may be NULL) is INCREMENTED by the skipped count. */
+ * (parity and debugging): the nearest pixel of Section 2.1.4, the footprint
+ * of Section 2.3.4 and the plane of Section 1.3, computed in FP64.  Outputs
+ * are device arrays of nrec entries: k_lo_u, k_lo_v, o_u, o_v, plane (-1 for
+ * a separable kernel), valid (0/1); k_lo and o are 0 for skipped records.
+ * *d_nskipped (device, may be NULL) is INCREMENTED by the skipped count.
+ * Errors: MG_EINVAL for a bad descriptor or a null output with nrec > 0. */
 mg_status mg_compute_indices(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
                              const void *uvw, mg_dtype uvw_dtype,
                              int32_t *k_lo_u, int32_t *k_lo_v, int32_t *o_u, int32_t *o_v,
@@ -125,35 +128,67 @@ mg_status mg_compute_indices(const mg_grid_desc *g, const mg_kernel_desc *k, int
  * share their tiles) and by cell inside each run of records (the thesis's
  * sorted record order, Section 3.2.4), and prepares the kernel bank: a
  * private copy re-laid so that the taps of each oversampling phase are
- * contiguous, plus its conjugate for W-projection.  The plan owns device
- * memory it allocates itself (freed by mg_plan_destroy); it keeps no pointer
+ * contiguous, plus its conjugate for W-projection.  A plan keeps no pointer
  * to uvw or to the caller's taps, so neither needs to outlive the create
  * call's stream work.  A plan is immutable after creation and may be used
  * from several streams once the creating stream's work has completed. */
 typedef struct mg_plan mg_plan;
 
-mg_status mg_plan_create(mg_plan **plan, const mg_grid_desc *g, const mg_kernel_desc *k,
-                         int64_t nrec, const void *uvw, mg_dtype uvw_dtype, hipStream_t stream);
+/* Bytes of device workspace a plan of these descriptors and nrec records
+ * holds (its sorted record metadata and permutation, chunk and unit lists,
+ * tap table and the build's temporaries).  Host-only: nothing is queued.
+ * Errors: MG_EINVAL as mg_plan_create (uvw is not needed). */
+mg_status mg_plan_workspace_size(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                                 size_t *bytes);
 
-/* grid += G vis.  vis: [nrec][npol] complex64 in the create call's record
- * order; grid: [npol][nv][nu] complex64. */
+/* Builds a plan for the records uvw [nrec][3] (device).  workspace: device
+ * memory of at least mg_plan_workspace_size bytes, 256-byte aligned, owned by
+ * the caller, which keeps it alive (and unused by anything else) until the
+ * plan is destroyed and the plan's queued work has completed; every device
+ * array of the plan lives in it, so a caller's allocator accounts for all of
+ * the plan's memory.  workspace == NULL: the library allocates it
+ * stream-ordered on `stream` and releases it in mg_plan_destroy.
+ * Errors: MG_EINVAL (bad descriptor, misaligned workspace), MG_ENOMEM,
+ * MG_EUNSUPPORTED (tap table above 2^30 entries, too many buckets),
+ * MG_EDEVICE; on error *plan is NULL and nothing remains allocated. */
+mg_status mg_plan_create(mg_plan **plan, const mg_grid_desc *g, const mg_kernel_desc *k,
+                         int64_t nrec, const void *uvw, mg_dtype uvw_dtype, void *workspace,
+                         hipStream_t stream);
+
+/* Gridding Step (Algorithm "General Convolutional Gridding", Section 2.3;
+ * oversampled kernel as in the studied algorithm of Section 2.4.5), every
+ * polarisation with the same weights (Section 1.1): grid += G vis.
+ * vis: [nrec][npol] complex64 in the create call's record order; grid:
+ * [npol][nv][nu] complex64.  Scratch (sorted visibilities, 32 B per record
+ * and a few words per unit) is allocated and released stream-ordered inside
+ * the call.  Errors: MG_EINVAL (null pointer), MG_ENOMEM, MG_EDEVICE. */
 mg_status mg_plan_grid(const mg_plan *plan, const void *vis, void *grid, hipStream_t stream);
 
-/* vis_out = G^H grid (overwritten; skipped records get 0). */
+/* Degridding, the adjoint of the Gridding Step (the forward/backward pair of
+ * the major-cycle residual, Section 1.6): vis_out = G^H grid, i.e.
+ * vis_out[r][pol] = sum over the footprint of conj(weight) * grid (skipped
+ * records get 0; overwritten).  Errors as mg_plan_grid. */
 mg_status mg_plan_degrid(const mg_plan *plan, const void *grid, void *vis_out,
                          hipStream_t stream);
 
-/* Number of skipped records (waits for the plan's creation work). */
+/* Number of records skipped by the Bounded Records rule (Section 2.3.1) or
+ * for non-finite uvw; waits for the plan's creation work. */
 mg_status mg_plan_nskipped(const mg_plan *plan, int64_t *nskipped);
 
-/* Device bytes the plan holds. */
+/* Device bytes the plan holds (its workspace size). */
 mg_status mg_plan_bytes(const mg_plan *plan, size_t *bytes);
 
+/* Releases the plan.  A library-owned workspace is freed stream-ordered
+ * after the plan's build and its last call on every stream it was used on
+ * (no host or device-wide wait); a caller workspace is left to the caller. */
 mg_status mg_plan_destroy(mg_plan *plan);
 
 /* ---- one-shot calls: index + sort + grid (or degrid) in one go ----
- * Scratch is allocated and released stream-ordered inside the call.
- * *d_nskipped (device, may be NULL) is INCREMENTED by the skipped count. */
+ * The same maps as mg_plan_grid / mg_plan_degrid (Sections 2.3, 2.4.5, 1.6)
+ * for one set of records.  The plan and the call's scratch are one
+ * allocation, made and released stream-ordered inside the call.
+ * *d_nskipped (device, may be NULL) is INCREMENTED by the skipped count.
+ * Errors: MG_EINVAL, MG_ENOMEM, MG_EUNSUPPORTED, MG_EDEVICE. */
 mg_status mg_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
                   const void *uvw, mg_dtype uvw_dtype, const void *vis, void *grid,
                   int64_t *d_nskipped, hipStream_t stream);
@@ -164,17 +199,17 @@ mg_status mg_degrid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec
 
 /* ---- serving: continuous batching of gridding jobs ----
  *
- * A server owns a pool of HIP streams (default priority) on the current
- * device and a scheduler thread.  mg_server_submit queues a one-shot
- * gridding job (the same computation as mg_grid) and returns at once.  The
- * scheduler admits queued jobs in arrival order whenever a slot is free and
- * the job's HBM footprint fits the budget beside the jobs already running,
- * and launches each admitted job on the next stream, so the work of jobs
- * that arrive while others run overlaps on the device.  A job's footprint is
- * its caller buffers (uvw, vis, grid) plus the library scratch it needs; it
- * is released when the job completes.  The caller keeps every buffer of a
- * job alive until the job is done.  Jobs on different streams must not
- * share an output grid. */
+ * A server owns a pool of HIP streams (default priority) on one device and a
+ * scheduler thread.  mg_server_submit queues a one-shot gridding job (the
+ * same computation as mg_grid) and returns at once.  The scheduler admits
+ * queued jobs in arrival order whenever a slot is free and the job's HBM
+ * footprint fits the budget beside the jobs already running, and launches
+ * each admitted job on the next stream, so the work of jobs that arrive
+ * while others run overlaps on the device.  A job's footprint is its caller
+ * buffers (uvw, vis, grid) plus the library scratch it needs; it is released
+ * when the job completes.  The caller keeps every buffer of a job alive
+ * until the job is done.  Jobs on different streams must not share an
+ * output grid. */
 typedef struct mg_server mg_server;
 
 typedef enum { MG_JOB_QUEUED = 0, MG_JOB_RUNNING = 1, MG_JOB_DONE = 2, MG_JOB_FAILED = 3 } mg_job_state;
@@ -186,23 +221,32 @@ typedef struct {
 } mg_server_stats;
 
 /* hbm_budget_bytes: admission budget; max_slots: jobs running at once
- * (1..1024); nstreams: streams in the pool (1..64). */
+ * (1..1024); nstreams: streams in the pool (1..64); device: the HIP device
+ * of the server (-1: the calling thread's current device).
+ * Errors: MG_EINVAL, MG_EDEVICE. */
 mg_status mg_server_create(mg_server **srv, size_t hbm_budget_bytes, int32_t max_slots,
-                           int32_t nstreams);
+                           int32_t nstreams, int32_t device);
 
-/* Queues a job.  Returns MG_ENOMEM (nothing queued) if the job alone exceeds
- * the budget, MG_EINVAL for bad arguments (as mg_grid).  *job_id receives the
+/* Queues a job.  inputs_ready (may be NULL): an event recorded after the
+ * work that produces the job's inputs; the job's stream waits for it before
+ * starting, so the caller need not synchronise.  Returns MG_ENOMEM (nothing
+ * queued) if the job alone exceeds the budget, MG_EINVAL for bad arguments
+ * (as mg_grid), MG_EBUSY while the server shuts down.  *job_id receives the
  * job's id. */
 mg_status mg_server_submit(mg_server *srv, const mg_grid_desc *g, const mg_kernel_desc *k,
                            int64_t nrec, const void *uvw, mg_dtype uvw_dtype, const void *vis,
-                           void *grid, uint64_t *job_id);
+                           void *grid, hipEvent_t inputs_ready, uint64_t *job_id);
 
 /* Job state; for a finished job *latency_s is the time from submission to
- * the scheduler observing completion (may be NULL). */
+ * the scheduler observing completion (may be NULL).  MG_EINVAL for an
+ * unknown or already released job id. */
 mg_status mg_server_poll(mg_server *srv, uint64_t job_id, mg_job_state *state,
                          double *latency_s);
 
-/* Blocks until the job finishes; returns the job's own status. */
+/* Blocks until the job finishes, then releases the job's record (its id
+ * becomes unknown); returns the job's own status: MG_OK, or the status of a
+ * failed launch, or MG_EDEVICE if the device reported an error for the job's
+ * work. */
 mg_status mg_server_wait(mg_server *srv, uint64_t job_id, double *latency_s);
 
 mg_status mg_server_get_stats(mg_server *srv, mg_server_stats *out);

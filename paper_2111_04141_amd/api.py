@@ -78,7 +78,8 @@ def lib():
     L.mg_last_error.argtypes = []
     L.mg_last_error.restype = C.c_char_p
     L.mg_compute_indices.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
-    L.mg_plan_create.argtypes = [C.POINTER(vp), gd, kd, i64, vp, i32, vp]
+    L.mg_plan_workspace_size.argtypes = [gd, kd, i64, C.POINTER(C.c_size_t)]
+    L.mg_plan_create.argtypes = [C.POINTER(vp), gd, kd, i64, vp, i32, vp, vp]
     L.mg_plan_grid.argtypes = [vp, vp, vp, vp]
     L.mg_plan_degrid.argtypes = [vp, vp, vp, vp]
     L.mg_plan_nskipped.argtypes = [vp, C.POINTER(i64)]
@@ -86,13 +87,14 @@ def lib():
     L.mg_plan_destroy.argtypes = [vp]
     L.mg_grid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
     L.mg_degrid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
-    L.mg_server_create.argtypes = [C.POINTER(vp), C.c_size_t, i32, i32]
-    L.mg_server_submit.argtypes = [vp, gd, kd, i64, vp, i32, vp, vp, C.POINTER(C.c_uint64)]
+    L.mg_server_create.argtypes = [C.POINTER(vp), C.c_size_t, i32, i32, i32]
+    L.mg_server_submit.argtypes = [vp, gd, kd, i64, vp, i32, vp, vp, vp, C.POINTER(C.c_uint64)]
     L.mg_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(i32), C.POINTER(C.c_double)]
     L.mg_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
     L.mg_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
     L.mg_server_destroy.argtypes = [vp]
-    for f in ("mg_compute_indices", "mg_plan_create", "mg_plan_grid", "mg_plan_degrid",
+    for f in ("mg_compute_indices", "mg_plan_workspace_size", "mg_plan_create",
+              "mg_plan_grid", "mg_plan_degrid",
               "mg_plan_nskipped", "mg_plan_bytes", "mg_plan_destroy", "mg_grid", "mg_degrid",
               "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait",
               "mg_server_get_stats", "mg_server_destroy"):
@@ -274,10 +276,11 @@ class Server:
 
     JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
-    def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, nstreams: int = 8):
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, nstreams: int = 8,
+                 device: int = -1):
         self._h = C.c_void_p()
         _check(lib().mg_server_create(C.byref(self._h), int(hbm_budget_bytes), int(max_slots),
-                                      int(nstreams)), "mg_server_create")
+                                      int(nstreams), int(device)), "mg_server_create")
         self._keep = {}
 
     def submit(self, spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, vis: torch.Tensor,
@@ -286,14 +289,15 @@ class Server:
         n = uvw.shape[0]
         _check_vis(vis, n, spec.npol)
         _check_grid(grid_out, spec)
-        # inputs are produced on torch's current stream; the server's streams
-        # must not start on them before that work is done
-        torch.cuda.current_stream(uvw.device).synchronize()
+        # inputs are produced on torch's current stream: the job's stream waits
+        # for an event recorded there (no host synchronisation)
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(uvw.device))
         gd, kd = spec.desc(), bank.desc()
         jid = C.c_uint64()
         _check(lib().mg_server_submit(self._h, C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt,
-                                      vis.data_ptr(), grid_out.data_ptr(), C.byref(jid)),
-               "mg_server_submit")
+                                      vis.data_ptr(), grid_out.data_ptr(), ev.cuda_event,
+                                      C.byref(jid)), "mg_server_submit")
         self._keep[jid.value] = (uvw, vis, grid_out, bank)
         return jid.value
 
@@ -332,8 +336,18 @@ class Server:
         self.close()
 
 
+def workspace_size(spec: GridSpec, bank: KernelBank, nrec: int) -> int:
+    """Device bytes a plan of nrec records holds (mg_plan_workspace_size)."""
+    gd, kd = spec.desc(), bank.desc()
+    v = C.c_size_t()
+    _check(lib().mg_plan_workspace_size(C.byref(gd), C.byref(kd), int(nrec), C.byref(v)),
+           "mg_plan_workspace_size")
+    return int(v.value)
+
+
 class Plan:
-    """Index + sort once; grid / degrid many times over the same records."""
+    """Index + sort once; grid / degrid many times over the same records.
+    The plan's device arrays live in a torch-allocated workspace."""
 
     def __init__(self, spec: GridSpec, bank: KernelBank, uvw: torch.Tensor):
         dt = _check_uvw(uvw)
@@ -342,9 +356,13 @@ class Plan:
         self.device = uvw.device
         self._h = C.c_void_p()
         gd, kd = spec.desc(), bank.desc()
+        # the plan's device memory is a torch allocation (the caching
+        # allocator accounts for it); it outlives the plan handle
+        self.workspace = torch.empty(workspace_size(spec, bank, self.nrec), dtype=torch.uint8,
+                                     device=uvw.device)
         _check(lib().mg_plan_create(C.byref(self._h), C.byref(gd), C.byref(kd), self.nrec,
-                                    uvw.data_ptr(), dt, _stream_ptr(uvw.device)),
-               "mg_plan_create")
+                                    uvw.data_ptr(), dt, self.workspace.data_ptr(),
+                                    _stream_ptr(uvw.device)), "mg_plan_create")
 
     def grid(self, vis: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         _check_vis(vis, self.nrec, self.spec.npol)
@@ -382,6 +400,7 @@ class Plan:
         if self._h:
             lib().mg_plan_destroy(self._h)
             self._h = C.c_void_p()
+            self.workspace = None
 
     def __del__(self):
         try:

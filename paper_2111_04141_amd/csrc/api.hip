@@ -4,14 +4,24 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "internal.h"
 
 struct mg_plan {
     mg::PlanState st;
     hipEvent_t ready = nullptr;   // recorded after the build work
+    void *owned = nullptr;        // arena allocated by the library (no caller workspace)
+    hipStream_t create_stream = nullptr;
+    // library-owned arenas only: the last call of the plan on each stream,
+    // waited for before the arena is released
+    std::mutex mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
 
 namespace mg {
@@ -23,14 +33,6 @@ int ilog2(int x) {
     int l = 0;
     while ((1 << (l + 1)) <= x) ++l;
     return l;
-}
-
-int lds_limit_bytes() {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 65536;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        return 65536;
-    return v > 0 ? v : 65536;
 }
 
 // Tile side for a gridder class: 16, or 8 where the LDS region
@@ -125,41 +127,101 @@ DevGeom make_geom(const mg_grid_desc *g, const mg_kernel_desc *k) {
     return d;
 }
 
-void free_plan_memory(PlanState &P, hipStream_t s) {
-    void *ptrs[] = {P.taps,          P.smeta, P.sperm,        P.chunks,   P.plane_cfirst,
-                    P.bucket_cfirst, P.units, P.group_nunits, P.d_planes, P.counters};
-    for (void *p : ptrs) {
-        if (!p) continue;
-        if (P.stream_ordered) hipFreeAsync(p, s);
-        else hipFree(p);
+// Records the plan's use on `stream` (library-owned arenas only).
+void note_use(mg_plan *p, hipStream_t stream) {
+    if (!p->owned) return;
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (auto &u : p->uses) {
+        if (u.first == stream) {
+            hipEventRecord(u.second, stream);
+            return;
+        }
     }
-    P.taps = nullptr;
-    P.smeta = nullptr;
-    P.sperm = nullptr;
-    P.chunks = nullptr;
-    P.plane_cfirst = nullptr;
-    P.bucket_cfirst = nullptr;
-    P.units = nullptr;
-    P.group_nunits = nullptr;
-    P.d_planes = nullptr;
-    P.counters = nullptr;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+        hipEventRecord(ev, stream);
+        p->uses.emplace_back(stream, ev);
+    }
 }
 
-// Lays out the plan and runs the build on `stream`.
-mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc *k,
-                       int64_t nrec, const void *uvw, mg_dtype uvw_dtype, hipStream_t stream,
-                       bool stream_ordered) {
+// Lays out the plan in `arena` (plan_arena_bytes(P) bytes) and queues its
+// build on `stream`.
+mg_status build_in(PlanState &P, const mg_kernel_desc *k, const void *uvw, mg_dtype uvw_dtype,
+                   void *arena, hipStream_t stream) {
+    plan_carve(P, arena);
+    const mg_status st = plan_taps(P, k->taps, P.table_elems, stream);
+    if (st != MG_OK) return st;
+    return plan_build(P, uvw, uvw_dtype, stream);
+}
+
+__global__ void add_count_kernel(const int64_t *src, int64_t *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst += *src;
+}
+
+}  // namespace
+
+mg_status set_error(mg_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+// Device queries, once per device (and per kernel configuration for the
+// occupancy): launches on the serving path must not pay for them each time.
+namespace {
+std::mutex g_dev_mu;
+std::map<int, std::pair<int, int>> g_dev_attr;   // device -> (CUs, LDS per workgroup)
+std::map<std::tuple<int, const void *, int, size_t>, int> g_occ;
+
+std::pair<int, int> dev_attr(int *dev_out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (dev_out) *dev_out = dev;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev_attr.find(dev);
+    if (it != g_dev_attr.end()) return it->second;
+    int cus = 0, lds = 0;
+    const bool ok =
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        cus > 0 && lds > 0;
+    if (!ok) return {1, 65536};   // no device: host-only size queries (not cached)
+    return g_dev_attr[dev] = {cus, lds};
+}
+}  // namespace
+
+int device_cus() { return dev_attr(nullptr).first; }
+int device_lds_limit() { return dev_attr(nullptr).second; }
+
+int resident_groups(const void *kernel, int threads, size_t lds) {
+    int dev = 0;
+    const int cus = dev_attr(&dev).first;
+    const auto key = std::make_tuple(dev, kernel, threads, lds);
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        auto it = g_occ.find(key);
+        if (it != g_occ.end()) return it->second;
+    }
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess ||
+        per < 1)
+        per = 1;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    return g_occ[key] = per * cus;
+}
+
+// Host layout of a plan: planes, support classes, tiles, plane groups and
+// their buckets, the chunk bound and the tap table's size.
+mg_status plan_prepare(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc *k,
+                       int64_t nrec) {
     P.geom = make_geom(g, k);
     P.kind = k->kind;
     P.tap_dtype = k->tap_dtype;
     P.nrec = nrec;
-    P.stream_ordered = stream_ordered;
-    P.alloc_stream = stream;
     P.nplanes_eff = (k->kind == MG_KERNEL_WPROJ) ? k->nplanes : 1;
     // chunk size: enough chunks to fill the chip, at most 2048 records
     int64_t R = nrec / 4096;
     P.R = (int32_t)std::max<int64_t>(64, std::min<int64_t>(2048, R));
-    const int lds = lds_limit_bytes();
+    const int lds = device_lds_limit();
     P.planes.resize(P.nplanes_eff);
     for (int p = 0; p < P.nplanes_eff; ++p) {
         PlaneLayout &L = P.planes[p];
@@ -183,6 +245,9 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
     }
     P.geom.conj_base = table;
     if (table >= (1LL << 30)) return set_error(MG_EUNSUPPORTED, "tap table too large");
+    P.table_elems = table;
+    const bool wproj = k->kind == MG_KERNEL_WPROJ;
+    P.taps_bytes = dtype_size(k->tap_dtype) * (wproj ? 2 : 1) * (size_t)table * (wproj ? 2 : 1);
     // groups: runs of consecutive planes of one class share their buckets,
     // numbered tile-major
     int64_t base = 0;
@@ -203,20 +268,8 @@ mg_status create_state(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
     }
     P.nbuckets = base;
     if (base >= 0x7fffffffLL) return set_error(MG_EUNSUPPORTED, "too many (plane, tile) buckets");
-    const mg_status st = plan_taps(P, k->taps, table, stream);
-    if (st != MG_OK) return st;
-    return plan_build(P, uvw, uvw_dtype, stream);
-}
-
-__global__ void add_count_kernel(const int64_t *src, int64_t *dst) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *dst += *src;
-}
-
-}  // namespace
-
-mg_status set_error(mg_status s, const std::string &msg) {
-    g_err = msg;
-    return s;
+    P.max_chunks = base + nrec / P.R + 1;
+    return MG_OK;
 }
 
 }  // namespace mg
@@ -251,23 +304,51 @@ mg_status mg_compute_indices(const mg_grid_desc *g, const mg_kernel_desc *k, int
                                   plane, valid, d_nskipped, stream);
 }
 
+mg_status mg_plan_workspace_size(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                                 size_t *bytes) {
+    if (!bytes) return set_error(MG_EINVAL, "null bytes output");
+    *bytes = 0;
+    // the uvw pointer is not needed for the size: check the rest
+    mg_status s = check_common(g, k, nrec, reinterpret_cast<const void *>(1), MG_F32);
+    if (s != MG_OK) return s;
+    PlanState P;
+    s = plan_prepare(P, g, k, nrec);
+    if (s != MG_OK) return s;
+    *bytes = plan_arena_bytes(P);
+    return MG_OK;
+}
+
 mg_status mg_plan_create(mg_plan **plan, const mg_grid_desc *g, const mg_kernel_desc *k,
-                         int64_t nrec, const void *uvw, mg_dtype uvw_dtype, hipStream_t stream) {
+                         int64_t nrec, const void *uvw, mg_dtype uvw_dtype, void *workspace,
+                         hipStream_t stream) {
     if (!plan) return set_error(MG_EINVAL, "null plan output");
     *plan = nullptr;
     mg_status s = check_common(g, k, nrec, uvw, uvw_dtype);
     if (s != MG_OK) return s;
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kArenaAlign) != 0)
+        return set_error(MG_EINVAL, "workspace must be 256-byte aligned");
     mg_plan *p = new (std::nothrow) mg_plan;
     if (!p) return set_error(MG_ENOMEM, "host allocation failed");
-    s = create_state(p->st, g, k, nrec, uvw, uvw_dtype, stream, false);
+    p->create_stream = stream;
+    s = plan_prepare(p->st, g, k, nrec);
+    void *arena = workspace;
+    if (s == MG_OK && !arena) {
+        const size_t bytes = plan_arena_bytes(p->st);
+        hipError_t e = hipMallocAsync(&arena, std::max<size_t>(bytes, kArenaAlign), stream);
+        if (e != hipSuccess) {
+            arena = nullptr;
+            s = set_error(MG_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
+        }
+        p->owned = arena;
+    }
+    if (s == MG_OK) s = build_in(p->st, k, uvw, uvw_dtype, arena, stream);
     if (s == MG_OK) {
         if (hipEventCreateWithFlags(&p->ready, hipEventDisableTiming) != hipSuccess ||
             hipEventRecord(p->ready, stream) != hipSuccess)
             s = set_error(MG_EDEVICE, "event record failed");
     }
     if (s != MG_OK) {
-        hipStreamSynchronize(stream);
-        free_plan_memory(p->st, stream);
+        if (p->owned) hipFreeAsync(p->owned, stream);
         if (p->ready) hipEventDestroy(p->ready);
         delete p;
         return s;
@@ -280,7 +361,9 @@ mg_status mg_plan_grid(const mg_plan *plan, const void *vis, void *grid, hipStre
     if (!plan) return set_error(MG_EINVAL, "null plan");
     if (plan->st.nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
     if (!grid) return set_error(MG_EINVAL, "null grid");
-    return launch_grid(plan->st, vis, grid, stream);
+    const mg_status s = launch_grid(plan->st, vis, grid, nullptr, stream);
+    note_use(const_cast<mg_plan *>(plan), stream);
+    return s;
 }
 
 mg_status mg_plan_degrid(const mg_plan *plan, const void *grid, void *vis_out,
@@ -288,7 +371,9 @@ mg_status mg_plan_degrid(const mg_plan *plan, const void *grid, void *vis_out,
     if (!plan) return set_error(MG_EINVAL, "null plan");
     if (!grid) return set_error(MG_EINVAL, "null grid");
     if (plan->st.nrec > 0 && !vis_out) return set_error(MG_EINVAL, "null vis_out");
-    return launch_degrid(plan->st, grid, vis_out, stream);
+    const mg_status s = launch_degrid(plan->st, grid, vis_out, nullptr, stream);
+    note_use(const_cast<mg_plan *>(plan), stream);
+    return s;
 }
 
 mg_status mg_plan_nskipped(const mg_plan *plan, int64_t *nskipped) {
@@ -309,13 +394,50 @@ mg_status mg_plan_bytes(const mg_plan *plan, size_t *bytes) {
 
 mg_status mg_plan_destroy(mg_plan *plan) {
     if (!plan) return MG_OK;
-    if (plan->ready) hipEventSynchronize(plan->ready);
-    hipDeviceSynchronize();
-    free_plan_memory(plan->st, nullptr);
+    mg_status s = MG_OK;
+    if (plan->owned) {
+        // the library's arena: released stream-ordered after the build and
+        // after the plan's last call on every stream it was used on (no
+        // host or device-wide wait)
+        hipStream_t st = plan->create_stream;
+        for (auto &u : plan->uses)
+            if (hipStreamWaitEvent(st, u.second, 0) != hipSuccess) s = MG_EDEVICE;
+        if (hipFreeAsync(plan->owned, st) != hipSuccess) {
+            hipEventSynchronize(plan->ready);
+            for (auto &u : plan->uses) hipEventSynchronize(u.second);
+            hipFree(plan->owned);
+        }
+    }
+    for (auto &u : plan->uses) hipEventDestroy(u.second);
     if (plan->ready) hipEventDestroy(plan->ready);
     delete plan;
-    return MG_OK;
+    return s == MG_OK ? MG_OK : set_error(s, "stream wait failed");
 }
+
+namespace {
+// One-shot calls: plan and call scratch in one stream-ordered allocation.
+mg_status one_shot(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                   const void *uvw, mg_dtype uvw_dtype, bool gridding, const void *in, void *out,
+                   int64_t *d_nskipped, hipStream_t stream) {
+    PlanState P;
+    mg_status s = plan_prepare(P, g, k, nrec);
+    if (s != MG_OK) return s;
+    const size_t pb = plan_arena_bytes(P);
+    const size_t cb = gridding ? grid_scratch_bytes(P) : degrid_scratch_bytes(P);
+    void *arena = nullptr;
+    hipError_t e = hipMallocAsync(&arena, pb + cb, stream);
+    if (e != hipSuccess) return set_error(MG_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+    s = build_in(P, k, uvw, uvw_dtype, arena, stream);
+    void *scratch = static_cast<char *>(arena) + pb;
+    if (s == MG_OK)
+        s = gridding ? launch_grid(P, in, out, scratch, stream)
+                     : launch_degrid(P, in, out, scratch, stream);
+    if (s == MG_OK && d_nskipped)
+        hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(64), 0, stream, P.counters, d_nskipped);
+    hipFreeAsync(arena, stream);
+    return s;
+}
+}  // namespace
 
 mg_status mg_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec, const void *uvw,
                   mg_dtype uvw_dtype, const void *vis, void *grid, int64_t *d_nskipped,
@@ -324,13 +446,7 @@ mg_status mg_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec, 
     if (s != MG_OK) return s;
     if (nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
     if (!grid) return set_error(MG_EINVAL, "null grid");
-    PlanState P;
-    s = create_state(P, g, k, nrec, uvw, uvw_dtype, stream, true);
-    if (s == MG_OK) s = launch_grid(P, vis, grid, stream);
-    if (s == MG_OK && d_nskipped)
-        hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(64), 0, stream, P.counters, d_nskipped);
-    free_plan_memory(P, stream);
-    return s;
+    return one_shot(g, k, nrec, uvw, uvw_dtype, true, vis, grid, d_nskipped, stream);
 }
 
 mg_status mg_degrid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
@@ -340,13 +456,7 @@ mg_status mg_degrid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec
     if (s != MG_OK) return s;
     if (!grid) return set_error(MG_EINVAL, "null grid");
     if (nrec > 0 && !vis_out) return set_error(MG_EINVAL, "null vis_out");
-    PlanState P;
-    s = create_state(P, g, k, nrec, uvw, uvw_dtype, stream, true);
-    if (s == MG_OK) s = launch_degrid(P, grid, vis_out, stream);
-    if (s == MG_OK && d_nskipped)
-        hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(64), 0, stream, P.counters, d_nskipped);
-    free_plan_memory(P, stream);
-    return s;
+    return one_shot(g, k, nrec, uvw, uvw_dtype, false, grid, vis_out, d_nskipped, stream);
 }
 
 }  // extern "C"

@@ -660,12 +660,8 @@ hipError_t launch_dg(const DegridPtrs &a, const DegridParams &prm, int tile, int
     const int side = (tile + smax - 1 + 7) / 8;
     if (side * side > KMAX * NW) return hipErrorInvalidValue;
     auto kern = degrid_block_kernel<KMAX, NW, B, SEP, TapT>;
-    int dev = 0, cus = 0, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, NW * kWave, 0) != hipSuccess)
-        per = 1;
-    hipLaunchKernelGGL(kern, dim3(std::max(1, per) * std::max(1, cus)), dim3(NW * kWave), 0,
+    hipLaunchKernelGGL(kern, dim3(resident_groups((const void *)kern, NW * kWave, 0)),
+                       dim3(NW * kWave), 0,
                        stream, a.smeta, a.sperm, a.grid, a.vis_out, (const TapT *)a.taps,
                        a.chunks, a.bucket_cfirst, a.units, a.group_nunits, a.planes, a.queue,
                        prm);
@@ -682,12 +678,8 @@ hipError_t launch_dt(const DegridPtrs &a, const DegridParams &prm, int tile, int
     // (registers; the reduction costs about the same per record either way)
     auto kern = degrid_taps_kernel<NTAP, PITCH, (NTAP > 1 ? 2 : 4), SEP, TapT>;
     constexpr int threads = kWave * taps_waves(NTAP);
-    int dev = 0, cus = 0, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, lds) != hipSuccess)
-        per = 1;
-    hipLaunchKernelGGL(kern, dim3(std::max(1, per) * std::max(1, cus)), dim3(threads), lds,
+    hipLaunchKernelGGL(kern, dim3(resident_groups((const void *)kern, threads, lds)),
+                       dim3(threads), lds,
                        stream, a.smeta, a.sperm, a.grid, a.vis_out, (const TapT *)a.taps,
                        a.chunks, a.bucket_cfirst, a.units, a.group_nunits, a.planes, a.queue,
                        prm);
@@ -717,12 +709,20 @@ hipError_t launch_deg_t(mg_dtype dt, int cls, const DegridPtrs &a, const DegridP
 
 }  // namespace
 
-mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hipStream_t stream) {
+size_t degrid_scratch_bytes(const PlanState &P) {
+    return arena_round(sizeof(uint32_t) * (size_t)P.nplanes_eff);
+}
+
+mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, void *scratch,
+                        hipStream_t stream) {
     if (P.nrec == 0) return MG_OK;
     const int np = P.nplanes_eff;
-    uint32_t *queues = nullptr;
-    hipError_t e = hipMallocAsync((void **)&queues, sizeof(uint32_t) * (size_t)np, stream);
-    if (e != hipSuccess) return set_error(MG_ENOMEM, "degrid: work queue allocation failed");
+    uint32_t *queues = static_cast<uint32_t *>(scratch);
+    hipError_t e = hipSuccess;
+    if (!queues) {
+        e = hipMallocAsync((void **)&queues, degrid_scratch_bytes(P), stream);
+        if (e != hipSuccess) return set_error(MG_ENOMEM, "degrid: work queue allocation failed");
+    }
     hipLaunchKernelGGL(clear_queue_kernel, dim3(1), dim3(256), 0, stream, queues, np);
     {
         int64_t nb = (P.nrec + 255) / 256;
@@ -752,7 +752,8 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hip
                 : launch_deg_t<false>(P.tap_dtype, cls, a, prm, P.planes[p0].T, smax, stream);
         p0 = p1;
     }
-    hipFreeAsync(queues, stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (!scratch) hipFreeAsync(queues, stream);
     if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("degrid kernels: ") + hipGetErrorString(e));
     return MG_OK;
 }

@@ -17,15 +17,18 @@
 //    records are dense.
 //  * When a slot's cell leaves the footprint its sums are committed into an
 //    LDS copy of the unit's grid region (bounding box plus S-1 halo) shared
-//    by the workgroup.  The region holds 32-bit fixed point: each unit first
-//    bounds every partial sum it can produce (2 * max|tap component| * sum
-//    over its records of max|visibility component|) and picks the
-//    power-of-two scale that maps that bound to 2^30, so integer LDS atomics
-//    (which run at full wave rate, unlike float LDS atomics, which serialise
-//    per lane) add the commits exactly and cannot overflow; truncation costs
-//    at most 2^-30 of the bound per commit.  At the end of the unit the
-//    region is converted back to FP32 and added to the grid with float
-//    atomics, one per touched cell.
+//    by the workgroup.  The region holds 32-bit fixed point: the gather
+//    (gather_units_kernel) bounds every partial sum a unit can produce,
+//    B = 2 * sum over its records of max|tap component of the record's
+//    plane| * max|visibility component|, picks the power-of-two scale 2^e
+//    that maps B to at most 2^30, and stores the unit's visibilities already
+//    multiplied by 2^e (exact), so the accumulators hold fixed-point units
+//    and a commit is one conversion, rounded to nearest, and one integer LDS
+//    atomic per component (integer LDS atomics run at full wave rate, unlike
+//    float LDS atomics, which serialise per lane).  The sums cannot overflow
+//    and each commit is off by at most half a quantum, 2^-31 B.  At the end
+//    of the unit the region is converted back to FP32 (times 2^-e) and added
+//    to the grid with float atomics, one per touched cell.
 //
 // Supports above 32: blocked output-stationary kernel (grid_block_kernel),
 // for the sparse planes of large |w|; see the kernel's comment.
@@ -58,6 +61,22 @@ static_assert(2 * kBatch - 1 <= kRecPad, "record read-ahead runs past the paddin
 // that batch at the loop top, where (scalar loads complete out of order) it
 // also waits for the next batch's loads on every iteration.
 __device__ inline void wait_scalar_loads() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Nearest integer (halves round up) in one instruction: the fixed-point
+// commit of an accumulator that is already in units of the quantum.
+__device__ inline int32_t round_to_fixed(float x) {
+    int32_t r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// Per-unit word written by the gather: bits 0-7 the fixed-point exponent e
+// plus 128 (the unit's visibilities are stored times 2^e), bit 8 set if the
+// unit commits in fixed point, bit 9 set if one of its visibilities is not
+// finite.
+constexpr int32_t kUnitFixed = 1 << 8;
+constexpr int32_t kUnitNonFinite = 1 << 9;
+__device__ inline int unit_scale(int32_t info) { return (info & 0xff) - 128; }
 
 struct GridParams {
     int32_t npol, nu, nv, beta;
@@ -135,14 +154,10 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
     const uint32_t *__restrict__ bucket_cfirst, const uint2 *__restrict__ units,
     const uint32_t *__restrict__ group_nunits, const PlaneLayout *__restrict__ planes,
-    const uint32_t *__restrict__ nonfinite, uint32_t *__restrict__ queue, GridParams prm) {
+    const int32_t *__restrict__ uinfo, uint32_t *__restrict__ queue, GridParams prm) {
     constexpr int NW = window_waves(TEAM);
     constexpr int NTEAMS = NW / TEAM;
-    // fixed point cannot hold NaN or Inf: calls whose visibilities are not
-    // all finite commit straight to the grid in FP32
-    const bool all_finite = uniform_u32(*nonfinite) == 0u;
     extern __shared__ int32_t region[];   // [8][RH][RW]: (pol, re/im) planes
-    __shared__ float s_bound[NW];
     __shared__ uint32_t s_next;
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);   // bytes per tap
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
@@ -153,7 +168,8 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
 
     // the launch covers one plane group; its work items are the group's units
     const PlaneLayout gl = planes[prm.p_lo];
-    const uint2 *gunits = units + bucket_cfirst[gl.base];
+    const uint32_t ubase = bucket_cfirst[gl.base];
+    const uint2 *gunits = units + ubase;
     const uint32_t nunits = group_nunits[prm.p_lo];
     for (uint32_t it = next_chunk(queue, &s_next); it < nunits; it = next_chunk(queue, &s_next)) {
         const uint2 un = gunits[it];
@@ -183,51 +199,25 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
         const int RH = (int)(vend - vmin);
         const int plane_cells = RH * RW;
 
-        // fixed-point scale of this item: 2^scale * bound <= 2^30 (an item
-        // whose bound overflows FP32 commits straight to the grid as well)
-        bool use_lds = all_finite;
-        int scale = 0;
+        // the unit's fixed-point exponent (its visibilities come scaled by
+        // 2^scale); units with a non-finite visibility, or whose bound
+        // overflows FP32, commit straight to the grid in FP32 (scale 0)
+        const int32_t info = (int32_t)uniform_u32((uint32_t)uinfo[ubase + it]);
+        const bool use_lds = (info & kUnitFixed) != 0;
+        const int scale = unit_scale(info);
         if (use_lds) {
             for (int i = threadIdx.x; i < 8 * plane_cells; i += NW * kWave) region[i] = 0;
-            float part = 0.0f;
-            for (uint32_t c = c0; c < c1; ++c) {
-                const Chunk ch = chunks[c];
-                int pc;
-                uint32_t tile_;
-                bucket_plane_tile(gl, ch.bucket, &pc, &tile_);
-                const float tmax = planes[pc].tmax;
-                const float wmax = SEP ? tmax * tmax : tmax;   // bound on a weight component
-                for (uint32_t r = ch.start + threadIdx.x; r < ch.start + ch.len; r += NW * kWave) {
-                    const float4 a = svis[2 * (size_t)r], b = svis[2 * (size_t)r + 1];
-                    const float m = fmaxf(fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))),
-                                          fmaxf(fmaxf(fabsf(b.x), fabsf(b.y)), fmaxf(fabsf(b.z), fabsf(b.w))));
-                    part += wmax * m;
-                }
-            }
-            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-            if (lane == 0) s_bound[wave] = part;
-            __syncthreads();
-            float bound = 0.0f;
-            for (int w = 0; w < NW; ++w) bound += s_bound[w];
-            // margin for the rounding of the sums above
-            bound = 2.0f * bound * 1.0001f + 1e-30f;
-            use_lds = uniform_u32(isfinite(bound) ? 1u : 0u) != 0u;
-            int e = 0;
-            if (use_lds) frexpf(bound, &e);   // bound < 2^e
-            scale = max(-120, min(120, 30 - e));
-            scale = (int)uniform_u32((uint32_t)scale);
             __syncthreads();
         }
-        // adds a slot's sums to its cell (fixed point: scaled by the exact
-        // power of two 2^scale and truncated, at most one quantum per commit)
-        const float fscale = ldexpf(1.0f, scale);
+        // adds a slot's sums to its cell (fixed point: rounded to the nearest
+        // quantum)
         auto commit = [&](float (&sums)[8], uint32_t cell_uv) {
             const uint32_t cu_ = cell_uv & 0xffffu, cv_ = cell_uv >> 16;
             if (use_lds) {
                 int32_t *dst = &region[(int)(cv_ - cv0) * RW + (int)(cu_ - cu0)];
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    atomicAdd(&dst[q * plane_cells], (int32_t)(sums[q] * fscale));
+                    atomicAdd(&dst[q * plane_cells], round_to_fixed(sums[q]));
             } else {
 #pragma unroll
                 for (int pol = 0; pol < 4; ++pol) {
@@ -496,11 +486,10 @@ void grid_block_kernel(
     const TapT *__restrict__ taps, const Chunk *__restrict__ chunks,
     const uint32_t *__restrict__ bucket_cfirst, const uint2 *__restrict__ units,
     const uint32_t *__restrict__ group_nunits, const PlaneLayout *__restrict__ planes,
-    const uint32_t *__restrict__ nonfinite, uint32_t *__restrict__ queue, GridParams prm) {
+    const int32_t *__restrict__ uinfo, uint32_t *__restrict__ queue, GridParams prm) {
     // Lanes outside a footprint normally multiply a zero tap, which adds
-    // nothing; a non-finite visibility would turn that into NaN, so calls
-    // whose visibilities are not all finite take the masked path instead.
-    const bool exact = uniform_u32(*nonfinite) != 0u;
+    // nothing; a non-finite visibility would turn that into NaN, so units
+    // holding one take the masked path instead.
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);   // bytes per tap
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -540,9 +529,12 @@ void grid_block_kernel(
     }
 
     __shared__ uint32_t s_next;
-    // the exact or fast path is chosen once per launch, outside the unit loop
-    auto work = [&](auto exact_t) {
-        for (uint32_t i = next_chunk(queue, &s_next); i < nunits; i = next_chunk(queue, &s_next)) {
+    const uint32_t ubase = bucket_cfirst[gbase];
+    // the exact or fast path is chosen per unit
+    for (uint32_t i = next_chunk(queue, &s_next); i < nunits; i = next_chunk(queue, &s_next)) {
+        const bool exact_unit =
+            (uniform_u32((uint32_t)uinfo[ubase + i]) & (uint32_t)kUnitNonFinite) != 0u;
+        auto work = [&](auto exact_t) {
             const uint2 un = gunits[i];
             const uint32_t c0 = un.x, c1 = un.x + un.y;
             const uint32_t t = (chunks[c0].bucket - gbase) / gn;
@@ -697,59 +689,142 @@ void grid_block_kernel(
                     }
                 }
             }
-        }
-    };
-    if (exact)
-        work(std::true_type{});
-    else
-        work(std::false_type{});
+        };
+        if (exact_unit)
+            work(std::true_type{});
+        else
+            work(std::false_type{});
+    }
 }
 
-// Gathers visibilities into sorted order, padded to 4 polarisations.
-__global__ __launch_bounds__(256) void gather_vis_kernel(const int64_t *__restrict__ counters,
-                                                         int64_t nrec,
-                                                         const uint32_t *__restrict__ sperm,
-                                                         const float2 *__restrict__ vis,
-                                                         int32_t npol, float4 *__restrict__ svis,
-                                                         uint32_t *__restrict__ nonfinite) {
-    constexpr int U = 4;   // records per thread in flight (independent random loads)
-    const int64_t n = min(counters[1], nrec);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
-        uint32_t idx[U];
+// Gathers the visibilities of one plane group's units into sorted order,
+// padded to 4 polarisations, and writes each unit's word (see kUnitFixed).
+// A workgroup takes a unit (at most kGatherThreads * kGatherPerThread
+// records, contiguous in sorted order): every thread first loads the
+// permutation entries of its records, then their visibilities (all loads in
+// flight together), bounds the unit's partial sums, and for the window
+// classes (fixed = 1) stores the visibilities multiplied by the unit's
+// power-of-two scale.
+constexpr int kGatherThreads = 256;
+constexpr int kGatherPerThread = 8;   // R <= 2048 records per unit
+
+__global__ __launch_bounds__(kGatherThreads) void gather_units_kernel(
+    const PlaneLayout *__restrict__ planes, int32_t g, int32_t sep, int32_t fixed,
+    const uint32_t *__restrict__ bucket_cfirst, const uint2 *__restrict__ units,
+    const uint32_t *__restrict__ group_nunits, const Chunk *__restrict__ chunks,
+    const uint32_t *__restrict__ sperm, const float2 *__restrict__ vis, int32_t npol,
+    float4 *__restrict__ svis, int32_t *__restrict__ uinfo) {
+    __shared__ float s_part[kGatherThreads / kWave];
+    __shared__ int s_bad[kGatherThreads / kWave];
+    const PlaneLayout gl = planes[g];
+    const uint32_t ubase = bucket_cfirst[gl.base];
+    const uint32_t n = group_nunits[g];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const uint2 un = units[ubase + it];
+        const uint32_t c0 = un.x, c1 = un.x + un.y;
+        const uint32_t rs = chunks[c0].start;
+        const Chunk last = chunks[c1 - 1];
+        const uint32_t re = last.start + last.len;
+        uint32_t idx[kGatherPerThread];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u * stride;
-            idx[u] = (i < n) ? sperm[i] : 0u;
+        for (int k = 0; k < kGatherPerThread; ++k) {
+            const uint32_t r = rs + threadIdx.x + (uint32_t)k * kGatherThreads;
+            idx[k] = (r < re) ? sperm[r] : 0u;
         }
-        float4 a[U], b[U];
+        float4 a[kGatherPerThread], b[kGatherPerThread];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (i0 + u * stride >= n) continue;
-            const float2 *v = vis + (size_t)idx[u] * npol;
+        for (int k = 0; k < kGatherPerThread; ++k) {
+            const uint32_t r = rs + threadIdx.x + (uint32_t)k * kGatherThreads;
+            a[k] = b[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (r >= re) continue;
+            const float2 *v = vis + (size_t)idx[k] * npol;
             if (npol == 4) {
-                a[u] = reinterpret_cast<const float4 *>(v)[0];
-                b[u] = reinterpret_cast<const float4 *>(v)[1];
+                a[k] = reinterpret_cast<const float4 *>(v)[0];
+                b[k] = reinterpret_cast<const float4 *>(v)[1];
             } else {
                 float2 x[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) x[q] = (q < npol) ? v[q] : make_float2(0.0f, 0.0f);
-                a[u] = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
-                b[u] = make_float4(x[2].x, x[2].y, x[3].x, x[3].y);
+                a[k] = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
+                b[k] = make_float4(x[2].x, x[2].y, x[3].x, x[3].y);
             }
         }
-        bool finite = true;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u * stride;
-            if (i >= n) continue;
-            finite = finite && isfinite(a[u].x) && isfinite(a[u].y) && isfinite(a[u].z) &&
-                     isfinite(a[u].w) && isfinite(b[u].x) && isfinite(b[u].y) &&
-                     isfinite(b[u].z) && isfinite(b[u].w);
-            svis[2 * i] = a[u];
-            svis[2 * i + 1] = b[u];
+        // bound: sum over the records of the plane's largest weight component
+        // times the record's largest visibility component (the chunk of a
+        // record, hence its plane, only moves forward with r)
+        float part = 0.0f;
+        bool bad = false;
+        uint32_t c = c0;
+        uint32_t cend = chunks[c0].start + chunks[c0].len;
+        float wmax = 0.0f;
+        {
+            int pc;
+            uint32_t tile_;
+            bucket_plane_tile(gl, chunks[c0].bucket, &pc, &tile_);
+            const float t = planes[pc].tmax;
+            wmax = sep ? t * t : t;
         }
-        if (!finite) atomicOr(nonfinite, 1u);
+#pragma unroll
+        for (int k = 0; k < kGatherPerThread; ++k) {
+            const uint32_t r = rs + threadIdx.x + (uint32_t)k * kGatherThreads;
+            if (r >= re) continue;
+            while (r >= cend) {
+                ++c;
+                const Chunk ch = chunks[c];
+                cend = ch.start + ch.len;
+                int pc;
+                uint32_t tile_;
+                bucket_plane_tile(gl, ch.bucket, &pc, &tile_);
+                const float t = planes[pc].tmax;
+                wmax = sep ? t * t : t;
+            }
+            const float m = fmaxf(fmaxf(fmaxf(fabsf(a[k].x), fabsf(a[k].y)), fmaxf(fabsf(a[k].z), fabsf(a[k].w))),
+                                  fmaxf(fmaxf(fabsf(b[k].x), fabsf(b[k].y)), fmaxf(fabsf(b[k].z), fabsf(b[k].w))));
+            part += wmax * m;
+            bad = bad || !(isfinite(a[k].x) && isfinite(a[k].y) && isfinite(a[k].z) &&
+                           isfinite(a[k].w) && isfinite(b[k].x) && isfinite(b[k].y) &&
+                           isfinite(b[k].z) && isfinite(b[k].w));
+        }
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        const bool wbad = __any(bad);
+        if (lane == 0) {
+            s_part[wave] = part;
+            s_bad[wave] = wbad ? 1 : 0;
+        }
+        __syncthreads();
+        float bound = 0.0f;
+        int anybad = 0;
+        for (int w = 0; w < kGatherThreads / kWave; ++w) {
+            bound += s_part[w];
+            anybad |= s_bad[w];
+        }
+        __syncthreads();   // s_part is rewritten by the next unit
+        // margin for the rounding of the sums above
+        bound = 2.0f * bound * 1.0001f + 1e-30f;
+        int scale = 0;
+        int32_t info = anybad ? kUnitNonFinite : 0;
+        if (fixed && !anybad && isfinite(bound)) {
+            int e = 0;
+            frexpf(bound, &e);   // bound < 2^e
+            scale = max(-120, min(120, 30 - e));
+            info |= kUnitFixed;
+        }
+        info |= (scale + 128) & 0xff;
+        if (threadIdx.x == 0) uinfo[ubase + it] = info;
+        const float fs = ldexpf(1.0f, scale);
+#pragma unroll
+        for (int k = 0; k < kGatherPerThread; ++k) {
+            const uint32_t r = rs + threadIdx.x + (uint32_t)k * kGatherThreads;
+            if (r >= re) continue;
+            float4 x = a[k], y = b[k];
+            if (scale != 0) {
+                x.x *= fs; x.y *= fs; x.z *= fs; x.w *= fs;
+                y.x *= fs; y.y *= fs; y.z *= fs; y.w *= fs;
+            }
+            svis[2 * (size_t)r] = x;
+            svis[2 * (size_t)r + 1] = y;
+        }
     }
 }
 
@@ -767,38 +842,27 @@ struct GridPtrs {
     const uint2 *units;
     const uint32_t *group_nunits;
     const PlaneLayout *planes;
-    const uint32_t *nonfinite;   // set by the gather if a visibility is not finite
-    uint32_t *queue;             // this launch's chunk counter
+    const int32_t *uinfo;        // per-unit words written by the gather
+    uint32_t *queue;             // this launch's unit counter
 };
-
-// Workgroups of `kernel` that fit on the device at once.
-template <typename Kern>
-int resident_groups(Kern kernel, int threads, size_t lds) {
-    int dev = 0, cus = 0, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess)
-        per = 1;
-    return std::max(1, per) * std::max(1, cus);
-}
 
 template <int KMAX, int TEAM, bool SEP, typename TapT>
 void launch_window(const GridPtrs &a, const GridParams &prm, size_t lds, hipStream_t stream) {
     auto kern = grid_window_kernel<KMAX, TEAM, SEP, TapT>;
     const int threads = kWave * window_waves(TEAM);
-    hipLaunchKernelGGL(kern, dim3(resident_groups(kern, threads, lds)), dim3(threads), lds,
-                       stream, a.smeta, a.svis, a.grid, (const TapT *)a.taps, a.chunks,
-                       a.bucket_cfirst, a.units, a.group_nunits, a.planes,
-                       a.nonfinite, a.queue, prm);
+    hipLaunchKernelGGL(kern, dim3(resident_groups((const void *)kern, threads, lds)),
+                       dim3(threads), lds, stream, a.smeta, a.svis, a.grid, (const TapT *)a.taps,
+                       a.chunks, a.bucket_cfirst, a.units, a.group_nunits, a.planes, a.uinfo,
+                       a.queue, prm);
 }
 
 template <int KMAX, int NW, bool SEP, typename TapT>
 void launch_block(const GridPtrs &a, const GridParams &prm, hipStream_t stream) {
     auto kern = grid_block_kernel<KMAX, NW, SEP, TapT>;
-    hipLaunchKernelGGL(kern, dim3(resident_groups(kern, NW * kWave, 0)), dim3(NW * kWave), 0,
-                       stream, a.smeta, a.svis, a.grid, (const TapT *)a.taps, a.chunks,
-                       a.bucket_cfirst, a.units, a.group_nunits, a.planes, a.nonfinite, a.queue,
-                       prm);
+    hipLaunchKernelGGL(kern, dim3(resident_groups((const void *)kern, NW * kWave, 0)),
+                       dim3(NW * kWave), 0, stream, a.smeta, a.svis, a.grid, (const TapT *)a.taps,
+                       a.chunks, a.bucket_cfirst, a.units, a.group_nunits, a.planes, a.uinfo,
+                       a.queue, prm);
 }
 
 // Largest region, in 8 x 8 blocks, of a chunk of tile side T and support S.
@@ -839,31 +903,58 @@ hipError_t launch_class_t(mg_dtype dt, int cls, const GridPtrs &a, const GridPar
 
 }  // namespace
 
-mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream_t stream) {
+namespace {
+template <typename F>
+size_t walk_grid_scratch(const PlanState &P, F &&place) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += arena_round(bytes);
+        return at;
+    };
+    place(0, take(sizeof(float4) * 2 * (size_t)(P.nrec + kRecPad)));
+    place(1, take(sizeof(int32_t) * (size_t)P.max_chunks));
+    place(2, take(sizeof(uint32_t) * (size_t)P.nplanes_eff));
+    return off;
+}
+}  // namespace
+
+size_t grid_scratch_bytes(const PlanState &P) {
+    return walk_grid_scratch(P, [](int, size_t) {});
+}
+
+mg_status launch_grid(const PlanState &P, const void *vis, void *grid, void *scratch,
+                      hipStream_t stream) {
     if (P.nrec == 0) return MG_OK;
-    float4 *svis = nullptr;
-    // sorted visibilities (padded like the sorted metadata), then the non-finite
-    // flag and one chunk counter per launch (at most one per plane)
-    const size_t nsv = 2 * (size_t)(P.nrec + kRecPad);
-    const int nwords = 1 + P.nplanes_eff;
-    hipError_t e = hipMallocAsync((void **)&svis,
-                                  sizeof(float4) * nsv + sizeof(uint32_t) * (size_t)nwords, stream);
-    if (e != hipSuccess) return set_error(MG_ENOMEM, "grid: gather buffer allocation failed");
-    uint32_t *nonfinite = reinterpret_cast<uint32_t *>(svis + nsv);
-    {
-        hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(256), 0, stream, nonfinite, nwords);
-        int64_t nb = (P.nrec + 255) / 256;
-        if (nb > 16384) nb = 16384;
-        hipLaunchKernelGGL(gather_vis_kernel, dim3((unsigned)nb), dim3(256), 0, stream,
-                           P.counters, P.nrec, P.sperm, (const float2 *)vis, P.geom.npol, svis,
-                           nonfinite);
+    hipError_t e = hipSuccess;
+    void *own = nullptr;
+    if (!scratch) {
+        e = hipMallocAsync(&own, grid_scratch_bytes(P), stream);
+        if (e != hipSuccess) return set_error(MG_ENOMEM, "grid: scratch allocation failed");
+        scratch = own;
     }
-    GridPtrs a{P.smeta,   svis,           (float *)grid, P.taps,    P.chunks, P.bucket_cfirst,
-               P.units,   P.group_nunits, P.d_planes,   nonfinite, nullptr};
-    GridParams prm{P.geom.npol, P.geom.nu, P.geom.nv, P.geom.beta, 0, 0};
-    const bool sep = P.kind == MG_KERNEL_SEPARABLE;
-    // one launch per run of consecutive planes of the same class
+    GridScratch gs;
+    walk_grid_scratch(P, [&](int what, size_t at) {
+        void *p = static_cast<char *>(scratch) + at;
+        if (what == 0) gs.svis = static_cast<float4 *>(p);
+        else if (what == 1) gs.uinfo = static_cast<int32_t *>(p);
+        else gs.queues = static_cast<uint32_t *>(p);
+    });
     const int np = P.nplanes_eff;
+    const bool sep = P.kind == MG_KERNEL_SEPARABLE;
+    hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(256), 0, stream, gs.queues, np);
+    // sorted, scaled visibilities and unit words, one launch per plane group
+    const int gather_groups = resident_groups((const void *)gather_units_kernel, kGatherThreads, 0);
+    for (int p = 0; p < np; p += P.planes[p].grp_n)
+        hipLaunchKernelGGL(gather_units_kernel, dim3(gather_groups), dim3(kGatherThreads), 0,
+                           stream, P.d_planes, p, (int32_t)sep,
+                           (int32_t)(P.planes[p].cls <= 2), P.bucket_cfirst, P.units,
+                           P.group_nunits, P.chunks, P.sperm, (const float2 *)vis, P.geom.npol,
+                           gs.svis, gs.uinfo);
+    GridPtrs a{P.smeta,   gs.svis,        (float *)grid, P.taps,   P.chunks, P.bucket_cfirst,
+               P.units,   P.group_nunits, P.d_planes,   gs.uinfo, nullptr};
+    GridParams prm{P.geom.npol, P.geom.nu, P.geom.nv, P.geom.beta, 0, 0};
+    // one launch per run of consecutive planes of the same class
     int p0 = 0;
     while (p0 < np && e == hipSuccess) {
         int p1 = p0 + 1;
@@ -875,12 +966,13 @@ mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream
         prm.p_lo = p0;
         prm.p_hi = p1;
         const int cls = P.planes[p0].cls;
-        a.queue = nonfinite + 1 + p0;
+        a.queue = gs.queues + p0;
         e = sep ? launch_class_t<true>(P.tap_dtype, cls, a, prm, smax, P.planes[p0].T, stream)
                 : launch_class_t<false>(P.tap_dtype, cls, a, prm, smax, P.planes[p0].T, stream);
         p0 = p1;
     }
-    hipFreeAsync(svis, stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (own) hipFreeAsync(own, stream);
     if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("grid kernels: ") + hipGetErrorString(e));
     return MG_OK;
 }

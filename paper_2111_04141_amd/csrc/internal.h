@@ -51,6 +51,10 @@ struct Chunk {
     uint32_t bbox;
 };
 
+// A plan's device arrays are carved from one arena (caller workspace, a
+// stream-ordered allocation, or the library's static scratch), at offsets
+// computed on the host from the geometry and the record count alone
+// (plan_arena_bytes).  The arena also holds the build's temporaries.
 struct PlanState {
     DevGeom geom{};
     mg_kernel_kind kind = MG_KERNEL_SEPARABLE;
@@ -59,13 +63,14 @@ struct PlanState {
     int64_t nrec = 0;
     int64_t nbuckets = 0;
     int64_t max_chunks = 0;
+    int64_t table_elems = 0;          // elements of one copy of the plan's tap table
     int32_t R = 1024;                 // records per chunk (max)
     std::vector<PlaneLayout> planes;  // host copy
-    // device memory
+    // device arrays (inside the arena)
     void *taps = nullptr;             // plan-owned copy of the table(s)
     size_t taps_bytes = 0;
-    RecMeta *smeta = nullptr;         // [nrec] sorted (first nvalid valid)
-    uint32_t *sperm = nullptr;        // [nrec] original record index
+    RecMeta *smeta = nullptr;         // [nrec + kRecPad] sorted (first nvalid valid)
+    uint32_t *sperm = nullptr;        // [nrec + kRecPad] original record index
     Chunk *chunks = nullptr;          // [max_chunks]
     uint32_t *plane_cfirst = nullptr; // [nplanes_eff + 1] first chunk of each plane's group
     uint32_t *bucket_cfirst = nullptr; // [nbuckets + 1] first chunk of each bucket
@@ -73,15 +78,39 @@ struct PlanState {
     uint32_t *group_nunits = nullptr; // [nplanes_eff] unit count, at each group's first plane
     PlaneLayout *d_planes = nullptr;  // [nplanes_eff]
     int64_t *counters = nullptr;      // [0] skipped, [1] valid, [2] chunks, [3], [4] scratch
-    size_t bytes = 0;
-    bool stream_ordered = false;      // allocated with hipMallocAsync
-    hipStream_t alloc_stream = nullptr;
+    // build temporaries (inside the arena, unused after the build)
+    uint32_t *hist = nullptr, *bstart = nullptr, *cursor = nullptr;   // [nbuckets]
+    uint2 *sums = nullptr;                                            // [nscan + 1]
+    size_t bytes = 0;                 // arena bytes
+};
+
+// Per-call scratch of the gridders (grid.hip): sorted visibilities, each
+// unit's fixed-point scale word, one work counter per plane.
+struct GridScratch {
+    float4 *svis = nullptr;      // [2 (nrec + kRecPad)]
+    int32_t *uinfo = nullptr;    // [max_chunks]
+    uint32_t *queues = nullptr;  // [nplanes_eff]
 };
 
 // Errors (thread-local message).
 mg_status set_error(mg_status s, const std::string &msg);
 
-// Build steps (plan.hip).  All asynchronous on `stream`.
+// Host layout of a plan (planes, groups, buckets, chunk bound) from the
+// descriptors; no device work (api.hip).
+mg_status plan_prepare(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec);
+
+// Arena bytes of a prepared plan, and the carving of an arena of that size
+// (256-byte aligned base) into its arrays (plan.hip).
+size_t plan_arena_bytes(const PlanState &P);
+void plan_carve(PlanState &P, void *arena);
+
+// Bytes of the per-call scratch of launch_grid / launch_degrid, and its
+// carving (grid.hip, degrid.hip).
+size_t grid_scratch_bytes(const PlanState &P);
+size_t degrid_scratch_bytes(const PlanState &P);
+
+// Build steps (plan.hip), on a carved plan.  All asynchronous on `stream`;
+// nothing is allocated.
 mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStream_t stream);
 mg_status launch_compute_indices(const DevGeom &g, int64_t nrec, const void *uvw,
                                  mg_dtype uvw_dtype, int32_t *k_lo_u, int32_t *k_lo_v,
@@ -93,9 +122,24 @@ mg_status launch_compute_indices(const DevGeom &g, int64_t nrec, const void *uvw
 // W-projection by its complex conjugate (plan.hip).
 mg_status plan_taps(PlanState &P, const void *src, int64_t table_elems, hipStream_t stream);
 
-// Hot kernels (grid.hip, degrid.hip).
-mg_status launch_grid(const PlanState &P, const void *vis, void *grid, hipStream_t stream);
-mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, hipStream_t stream);
+// Hot kernels (grid.hip, degrid.hip).  `scratch` holds grid_scratch_bytes /
+// degrid_scratch_bytes (256-byte aligned); nullptr: allocated and released
+// stream-ordered inside the call.
+mg_status launch_grid(const PlanState &P, const void *vis, void *grid, void *scratch,
+                      hipStream_t stream);
+mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, void *scratch,
+                        hipStream_t stream);
+
+// Workgroups of `kernel` (threads per workgroup, dynamic LDS bytes) that fit
+// on the current device at once; device attributes and occupancy are queried
+// once per (device, kernel, threads, lds) and cached (api.hip).
+int resident_groups(const void *kernel, int threads, size_t lds);
+int device_cus();
+int device_lds_limit();
+
+// Bytes rounded up to the arena alignment.
+constexpr size_t kArenaAlign = 256;
+inline size_t arena_round(size_t b) { return (b + kArenaAlign - 1) & ~(kArenaAlign - 1); }
 
 // Support classes (each has its own gridding and degridding kernels):
 //   class 0: S <= 8   moving window, one slot per lane

@@ -562,14 +562,6 @@ int grid_blocks(int64_t n, int threads) {
     return (int)b;
 }
 
-template <typename T>
-hipError_t malloc_bytes(PlanState &P, T **p, size_t bytes, hipStream_t s) {
-    hipError_t e = P.stream_ordered ? hipMallocAsync((void **)p, bytes, s)
-                                    : hipMalloc((void **)p, bytes);
-    if (e == hipSuccess) P.bytes += bytes;
-    return e;
-}
-
 // The plan's tap table, phase-major (see common.h): entry
 // (o_v, o_u, j, i) of plane p takes bank element (o_v + 1 + j beta) *
 // (beta S + 1) + (o_u + 1 + i beta) of the caller's plane; for W-projection
@@ -619,14 +611,10 @@ __global__ __launch_bounds__(256) void tap_layout_kernel(PlaneLayout *__restrict
 mg_status plan_taps(PlanState &P, const void *src, int64_t table_elems, hipStream_t stream) {
     const int np = P.nplanes_eff;
     const bool wproj = P.kind == MG_KERNEL_WPROJ;
-    const size_t esz = dtype_size(P.tap_dtype) * (wproj ? 2 : 1);
-    P.taps_bytes = esz * (size_t)table_elems * (wproj ? 2 : 1);
-    hipError_t e;
-    if ((e = malloc_bytes(P, &P.d_planes, sizeof(PlaneLayout) * (size_t)np, stream)) ||
-        (e = malloc_bytes(P, (char **)&P.taps, P.taps_bytes, stream)))
-        return set_error(MG_ENOMEM, std::string("tap table allocation: ") + hipGetErrorString(e));
-    hipMemcpyAsync(P.d_planes, P.planes.data(), sizeof(PlaneLayout) * np, hipMemcpyHostToDevice,
-                   stream);
+    hipError_t e = hipMemcpyAsync(P.d_planes, P.planes.data(), sizeof(PlaneLayout) * np,
+                                  hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess)
+        return set_error(MG_EDEVICE, std::string("plane layout upload: ") + hipGetErrorString(e));
     int64_t most = 0;
     for (const PlaneLayout &L : P.planes) {
         const int64_t w = (int64_t)P.geom.beta * L.S;
@@ -673,29 +661,10 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
     const uint32_t R = (uint32_t)P.R;
     const int np = P.nplanes_eff;
     hipError_t e = hipSuccess;
-    // persistent plan arrays
-    P.max_chunks = nb + nrec / R + 1;
-    // padded: the gridders read ahead of the records they use
-    if ((e = malloc_bytes(P, &P.smeta, sizeof(RecMeta) * (size_t)(nrec + kRecPad), stream)) ||
-        (e = malloc_bytes(P, &P.sperm, sizeof(uint32_t) * (size_t)(nrec + kRecPad), stream)) ||
-        (e = malloc_bytes(P, &P.chunks, sizeof(Chunk) * (size_t)P.max_chunks, stream)) ||
-        (e = malloc_bytes(P, &P.plane_cfirst, sizeof(uint32_t) * (size_t)(np + 1), stream)) ||
-        (e = malloc_bytes(P, &P.bucket_cfirst, sizeof(uint32_t) * (size_t)(nb + 1), stream)) ||
-        (e = malloc_bytes(P, &P.units, sizeof(uint2) * (size_t)P.max_chunks, stream)) ||
-        (e = malloc_bytes(P, &P.group_nunits, sizeof(uint32_t) * (size_t)np, stream)) ||
-        (e = malloc_bytes(P, &P.counters, sizeof(int64_t) * 6, stream)))
-        return set_error(MG_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
-    // temporaries (stream-ordered)
-    uint32_t *hist = nullptr, *bstart = nullptr, *cursor = nullptr;
+    uint32_t *hist = P.hist, *bstart = P.bstart, *cursor = P.cursor;
     uint32_t *cstart = P.bucket_cfirst;   // kept: first chunk of each bucket
-    uint2 *sums = nullptr;
+    uint2 *sums = P.sums;
     const int64_t nscan = (nb + kScanBlock - 1) / kScanBlock;
-    auto tmp = [&](void **p, size_t bytes) { return hipMallocAsync(p, bytes, stream); };
-    if ((e = tmp((void **)&hist, sizeof(uint32_t) * (size_t)nb)) ||
-        (e = tmp((void **)&bstart, sizeof(uint32_t) * (size_t)nb)) ||
-        (e = tmp((void **)&cursor, sizeof(uint32_t) * (size_t)nb)) ||
-        (e = tmp((void **)&sums, sizeof(uint2) * (size_t)(nscan + 1))))
-        return set_error(MG_ENOMEM, std::string("plan scratch: ") + hipGetErrorString(e));
 
     // zero-fill with a kernel (no memset nodes, so the calls stay capturable)
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, stream, (uint32_t *)P.counters,
@@ -737,15 +706,10 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         // cell sort and bounding box of the chunks of the window gridders'
         // supports (up to 32): small chunks one per wave, the others one per
         // workgroup
-        int dev = 0, cus = 0, per = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, chunk_sort_kernel, 256, 0) !=
-            hipSuccess)
-            per = 1;
-        hipLaunchKernelGGL(chunk_sort_small_kernel, dim3(8 * std::max(1, cus)), dim3(256), 0,
+        hipLaunchKernelGGL(chunk_sort_small_kernel, dim3(8 * device_cus()), dim3(256), 0,
                            stream, P.plane_cfirst, np, P.d_planes, P.chunks, P.smeta, P.sperm);
-        hipLaunchKernelGGL(chunk_sort_kernel, dim3(std::max(1, per) * std::max(1, cus)),
+        hipLaunchKernelGGL(chunk_sort_kernel,
+                           dim3(resident_groups((const void *)chunk_sort_kernel, 256, 0)),
                            dim3(256), 0, stream, P.plane_cfirst, np, P.d_planes, P.chunks,
                            P.smeta, P.sperm);
         // units of every plane group
@@ -758,12 +722,67 @@ mg_status plan_build(PlanState &P, const void *uvw, mg_dtype uvw_dtype, hipStrea
         }
     }
     e = hipGetLastError();
-    hipFreeAsync(hist, stream);
-    hipFreeAsync(bstart, stream);
-    hipFreeAsync(cursor, stream);
-    hipFreeAsync(sums, stream);
     if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("plan kernels: ") + hipGetErrorString(e));
     return MG_OK;
+}
+
+// Arena layout of a plan: every array starts on a kArenaAlign boundary.
+namespace {
+template <typename F>
+size_t walk_arena(const PlanState &P, F &&place) {
+    const int np = P.nplanes_eff;
+    const int64_t nb = P.nbuckets;
+    const int64_t nscan = (nb + kScanBlock - 1) / kScanBlock;
+    const size_t n = (size_t)(P.nrec + kRecPad);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += arena_round(bytes);
+        return at;
+    };
+    place(0, take(sizeof(PlaneLayout) * (size_t)np));
+    place(1, take(P.taps_bytes));
+    place(2, take(sizeof(RecMeta) * n));
+    place(3, take(sizeof(uint32_t) * n));
+    place(4, take(sizeof(Chunk) * (size_t)P.max_chunks));
+    place(5, take(sizeof(uint32_t) * (size_t)(np + 1)));
+    place(6, take(sizeof(uint32_t) * (size_t)(nb + 1)));
+    place(7, take(sizeof(uint2) * (size_t)P.max_chunks));
+    place(8, take(sizeof(uint32_t) * (size_t)np));
+    place(9, take(sizeof(int64_t) * 6));
+    place(10, take(sizeof(uint32_t) * (size_t)nb));
+    place(11, take(sizeof(uint32_t) * (size_t)nb));
+    place(12, take(sizeof(uint32_t) * (size_t)nb));
+    place(13, take(sizeof(uint2) * (size_t)(nscan + 1)));
+    return off;
+}
+}  // namespace
+
+size_t plan_arena_bytes(const PlanState &P) {
+    return walk_arena(P, [](int, size_t) {});
+}
+
+void plan_carve(PlanState &P, void *arena) {
+    char *base = static_cast<char *>(arena);
+    P.bytes = walk_arena(P, [&](int what, size_t at) {
+        void *p = base + at;
+        switch (what) {
+        case 0: P.d_planes = static_cast<PlaneLayout *>(p); break;
+        case 1: P.taps = p; break;
+        case 2: P.smeta = static_cast<RecMeta *>(p); break;
+        case 3: P.sperm = static_cast<uint32_t *>(p); break;
+        case 4: P.chunks = static_cast<Chunk *>(p); break;
+        case 5: P.plane_cfirst = static_cast<uint32_t *>(p); break;
+        case 6: P.bucket_cfirst = static_cast<uint32_t *>(p); break;
+        case 7: P.units = static_cast<uint2 *>(p); break;
+        case 8: P.group_nunits = static_cast<uint32_t *>(p); break;
+        case 9: P.counters = static_cast<int64_t *>(p); break;
+        case 10: P.hist = static_cast<uint32_t *>(p); break;
+        case 11: P.bstart = static_cast<uint32_t *>(p); break;
+        case 12: P.cursor = static_cast<uint32_t *>(p); break;
+        default: P.sums = static_cast<uint2 *>(p); break;
+        }
+    });
 }
 
 }  // namespace mg

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "serve_state.h"
 
 using Clock = std::chrono::steady_clock;
 
@@ -37,10 +38,9 @@ struct Job {
     mg_dtype uvw_dtype = MG_F32;
     const void *vis = nullptr;
     void *grid = nullptr;
-    size_t footprint = 0;
+    JobAccount acct;
     Clock::time_point t_submit, t_done;
-    mg_job_state state = MG_JOB_QUEUED;
-    mg_status status = MG_OK;
+    hipEvent_t ready_ev = nullptr;   // inputs ready (library event), may be null
     hipEvent_t done_ev = nullptr;
 };
 
@@ -52,6 +52,7 @@ struct mg_server {
     size_t budget = 0;
     int max_slots = 1;
     std::vector<hipStream_t> streams;
+    hipStream_t gate = nullptr;        // orders submit-time event waits
     size_t next_stream = 0;
     std::mutex mu;
     std::condition_variable cv_work;    // wakes the scheduler
@@ -59,8 +60,10 @@ struct mg_server {
     std::deque<uint64_t> pending;
     std::vector<uint64_t> running;
     std::unordered_map<uint64_t, std::unique_ptr<mg::Job>> jobs;
+    std::vector<hipEvent_t> free_events;   // reused job events
     uint64_t next_id = 1;
     mg_server_stats stats{};
+    mg::ServerAccount acct;
     bool stopping = false;
     std::thread worker;
 };
@@ -85,28 +88,48 @@ size_t job_footprint(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nre
     const size_t taps = (size_t)k->ntaps * dtype_bytes(k->tap_dtype) *
                         (k->kind == MG_KERNEL_WPROJ ? 4 : 1);
     // per record: sorted meta, permutation, sorted visibilities; per bucket:
-    // count, start, cursor, first chunk, chunk, unit; per R-chunk (R >= 64):
-    // chunk, unit
-    const size_t scratch = n * (8 + 4 + 32) + nb * (4 * 4 + 16 + 8) +
-                           (n / 64 + 1) * 24 + (1u << 20);
+    // count, start, cursor, first chunk, chunk, unit, unit word; per
+    // R-chunk (R >= 64): chunk, unit, unit word
+    const size_t scratch = n * (8 + 4 + 32) + nb * (4 * 4 + 16 + 8 + 4) +
+                           (n / 64 + 1) * 28 + (1u << 20);
     return caller + taps + scratch;
+}
+
+hipEvent_t take_event(mg_server *s) {
+    if (!s->free_events.empty()) {
+        hipEvent_t e = s->free_events.back();
+        s->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+void give_event(mg_server *s, hipEvent_t &e) {
+    if (e) s->free_events.push_back(e);
+    e = nullptr;
+}
+
+EventQuery query(hipEvent_t e) {
+    const hipError_t r = hipEventQuery(e);
+    if (r == hipSuccess) return EventQuery::kDone;
+    if (r == hipErrorNotReady) return EventQuery::kNotReady;
+    return EventQuery::kError;
 }
 
 void scheduler_loop(mg_server *s) {
     hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        // completions
+        // completions (a device error reported for a job's work fails the job)
         bool finished = false;
         for (size_t i = 0; i < s->running.size();) {
             Job &j = *s->jobs[s->running[i]];
-            if (hipEventQuery(j.done_ev) == hipSuccess) {
+            if (settle_running_job(j.acct, query(j.done_ev), s->acct, MG_EDEVICE)) {
                 j.t_done = Clock::now();
-                j.state = MG_JOB_DONE;
-                hipEventDestroy(j.done_ev);
-                j.done_ev = nullptr;
-                s->stats.bytes_in_use -= j.footprint;
-                s->stats.completed++;
+                give_event(s, j.done_ev);
+                give_event(s, j.ready_ev);
                 s->running.erase(s->running.begin() + i);
                 finished = true;
             } else {
@@ -117,29 +140,32 @@ void scheduler_loop(mg_server *s) {
         // admissions, in arrival order
         while (!s->pending.empty() && (int)s->running.size() < s->max_slots) {
             Job &j = *s->jobs[s->pending.front()];
-            if (s->stats.bytes_in_use + j.footprint > s->budget) break;
+            if (s->acct.bytes_in_use + j.acct.footprint > s->budget) break;
             s->pending.pop_front();
-            s->stats.bytes_in_use += j.footprint;
-            s->stats.bytes_peak = std::max(s->stats.bytes_peak, s->stats.bytes_in_use);
+            s->acct.bytes_in_use += j.acct.footprint;
+            s->stats.bytes_peak = std::max<uint64_t>(s->stats.bytes_peak, s->acct.bytes_in_use);
             s->stats.admitted++;
-            j.state = MG_JOB_RUNNING;
+            j.acct.state = kJobRunning;
             s->running.push_back(j.id);
             s->stats.max_running = std::max<int32_t>(s->stats.max_running, (int32_t)s->running.size());
             hipStream_t st = s->streams[s->next_stream++ % s->streams.size()];
+            hipEvent_t ev = take_event(s);
+            hipEvent_t ready = j.ready_ev;
             lk.unlock();
-            mg_status rc = mg_grid(&j.g, &j.k, j.nrec, j.uvw, j.uvw_dtype, j.vis, j.grid, nullptr, st);
-            hipEvent_t ev = nullptr;
-            if (rc == MG_OK && (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-                                hipEventRecord(ev, st) != hipSuccess))
-                rc = MG_EDEVICE;
+            mg_status rc = MG_OK;
+            if (ready && hipStreamWaitEvent(st, ready, 0) != hipSuccess) rc = MG_EDEVICE;
+            if (rc == MG_OK)
+                rc = mg_grid(&j.g, &j.k, j.nrec, j.uvw, j.uvw_dtype, j.vis, j.grid, nullptr, st);
+            if (rc == MG_OK && (!ev || hipEventRecord(ev, st) != hipSuccess)) rc = MG_EDEVICE;
             lk.lock();
             if (rc != MG_OK) {
-                if (ev) hipEventDestroy(ev);
-                j.status = rc;
-                j.state = MG_JOB_FAILED;
+                give_event(s, ev);
+                give_event(s, j.ready_ev);
+                j.acct.status = rc;
+                j.acct.state = kJobFailed;
                 j.t_done = Clock::now();
-                s->stats.bytes_in_use -= j.footprint;
-                s->stats.failed++;
+                s->acct.bytes_in_use -= j.acct.footprint;
+                s->acct.failed++;
                 s->running.erase(std::find(s->running.begin(), s->running.end(), j.id));
                 s->cv_done.notify_all();
             } else {
@@ -164,24 +190,34 @@ using namespace mg;
 extern "C" {
 
 mg_status mg_server_create(mg_server **srv, size_t hbm_budget_bytes, int32_t max_slots,
-                           int32_t nstreams) {
+                           int32_t nstreams, int32_t device) {
     if (!srv) return set_error(MG_EINVAL, "null server output");
     *srv = nullptr;
     if (hbm_budget_bytes == 0) return set_error(MG_EINVAL, "zero budget");
     if (max_slots < 1 || max_slots > 1024) return set_error(MG_EINVAL, "max_slots must be in 1..1024");
     if (nstreams < 1 || nstreams > 64) return set_error(MG_EINVAL, "nstreams must be in 1..64");
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return set_error(MG_EDEVICE, "no device");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < -1 || device >= ndev)
+        return set_error(MG_EINVAL, "device out of range");
     auto s = std::make_unique<mg_server>();
-    if (hipGetDevice(&s->device) != hipSuccess) return set_error(MG_EDEVICE, "no device");
+    s->device = device < 0 ? prev : device;
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     s->stats.budget = hbm_budget_bytes;
-    for (int i = 0; i < nstreams; ++i) {
+    if (hipSetDevice(s->device) != hipSuccess) return set_error(MG_EDEVICE, "cannot select device");
+    bool ok = true;
+    for (int i = 0; i < nstreams + 1 && ok; ++i) {
         hipStream_t st;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            for (hipStream_t x : s->streams) hipStreamDestroy(x);
-            return set_error(MG_EDEVICE, "stream creation failed");
-        }
-        s->streams.push_back(st);
+        ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (ok && i < nstreams) s->streams.push_back(st);
+        if (ok && i == nstreams) s->gate = st;
+    }
+    hipSetDevice(prev);
+    if (!ok) {
+        for (hipStream_t x : s->streams) hipStreamDestroy(x);
+        return set_error(MG_EDEVICE, "stream creation failed");
     }
     mg_server *raw = s.get();
     raw->worker = std::thread(scheduler_loop, raw);
@@ -191,7 +227,7 @@ mg_status mg_server_create(mg_server **srv, size_t hbm_budget_bytes, int32_t max
 
 mg_status mg_server_submit(mg_server *s, const mg_grid_desc *g, const mg_kernel_desc *k,
                            int64_t nrec, const void *uvw, mg_dtype uvw_dtype, const void *vis,
-                           void *grid, uint64_t *job_id) {
+                           void *grid, hipEvent_t inputs_ready, uint64_t *job_id) {
     if (!s || !job_id) return set_error(MG_EINVAL, "null server or job id");
     if (!g || !k) return set_error(MG_EINVAL, "null descriptor");
     if (nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
@@ -214,13 +250,24 @@ mg_status mg_server_submit(mg_server *s, const mg_grid_desc *g, const mg_kernel_
     j->uvw_dtype = uvw_dtype;
     j->vis = vis;
     j->grid = grid;
-    j->footprint = job_footprint(g, k, nrec, uvw_dtype);
-    if (j->footprint > s->budget)
+    j->acct.footprint = job_footprint(g, k, nrec, uvw_dtype);
+    if (j->acct.footprint > s->budget)
         return set_error(MG_ENOMEM, "job footprint exceeds the server's HBM budget");
     j->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) return set_error(MG_EBUSY, "server is shutting down");
+        if (inputs_ready) {
+            // a library event that completes with the caller's: the caller
+            // may re-record or destroy its event once submit returns
+            hipEvent_t ev = take_event(s);
+            if (!ev || hipStreamWaitEvent(s->gate, inputs_ready, 0) != hipSuccess ||
+                hipEventRecord(ev, s->gate) != hipSuccess) {
+                give_event(s, ev);
+                return set_error(MG_EDEVICE, "input event wait failed");
+            }
+            j->ready_ev = ev;
+        }
         j->id = s->next_id++;
         *job_id = j->id;
         s->pending.push_back(j->id);
@@ -237,9 +284,9 @@ mg_status mg_server_poll(mg_server *s, uint64_t job_id, mg_job_state *state, dou
     auto it = s->jobs.find(job_id);
     if (it == s->jobs.end()) return set_error(MG_EINVAL, "unknown job id");
     const Job &j = *it->second;
-    *state = j.state;
+    *state = (mg_job_state)j.acct.state;
     if (latency_s)
-        *latency_s = (j.state == MG_JOB_DONE || j.state == MG_JOB_FAILED)
+        *latency_s = (j.acct.state == kJobDone || j.acct.state == kJobFailed)
                          ? std::chrono::duration<double>(j.t_done - j.t_submit).count()
                          : -1.0;
     return MG_OK;
@@ -251,15 +298,21 @@ mg_status mg_server_wait(mg_server *s, uint64_t job_id, double *latency_s) {
     auto it = s->jobs.find(job_id);
     if (it == s->jobs.end()) return set_error(MG_EINVAL, "unknown job id");
     Job &j = *it->second;
-    s->cv_done.wait(lk, [&] { return j.state == MG_JOB_DONE || j.state == MG_JOB_FAILED; });
+    s->cv_done.wait(lk, [&] { return j.acct.state == kJobDone || j.acct.state == kJobFailed; });
     if (latency_s) *latency_s = std::chrono::duration<double>(j.t_done - j.t_submit).count();
-    return j.state == MG_JOB_DONE ? MG_OK : j.status;
+    const mg_status st = j.acct.state == kJobDone ? MG_OK : (mg_status)j.acct.status;
+    s->jobs.erase(it);
+    if (st != MG_OK) return set_error(st, "job failed");
+    return MG_OK;
 }
 
 mg_status mg_server_get_stats(mg_server *s, mg_server_stats *out) {
     if (!s || !out) return set_error(MG_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(s->mu);
     *out = s->stats;
+    out->bytes_in_use = s->acct.bytes_in_use;
+    out->completed = s->acct.completed;
+    out->failed = s->acct.failed;
     return MG_OK;
 }
 
@@ -275,6 +328,15 @@ mg_status mg_server_destroy(mg_server *s) {
         hipStreamSynchronize(st);
         hipStreamDestroy(st);
     }
+    if (s->gate) {
+        hipStreamSynchronize(s->gate);
+        hipStreamDestroy(s->gate);
+    }
+    for (auto &kv : s->jobs) {
+        if (kv.second->done_ev) hipEventDestroy(kv.second->done_ev);
+        if (kv.second->ready_ev) hipEventDestroy(kv.second->ready_ev);
+    }
+    for (hipEvent_t e : s->free_events) hipEventDestroy(e);
     delete s;
     return MG_OK;
 }

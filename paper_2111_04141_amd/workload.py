@@ -281,12 +281,6 @@ def config_wproj(n_ant: int = 256, n_times: int = 32, n_chan: int = 128, n: int 
                     uvw.astype(uvw_dtype), "wproj", s_max, bank=bank)
 
 
-def config_wproj_full(uvw_dtype=np.float32) -> Workload:
-    """256 antennas (5 km log-radial), 32640 baselines x 32 times x 128
-    channels = 133,693,440 records; 8192^2 grid; 32 planes, S 8 -> 64, beta 4."""
-    return config_wproj(uvw_dtype=uvw_dtype, name="wproj-8192-P32-S8to64-134M")
-
-
 def config_autograd(seed: int = SEED_ANTENNAS) -> Workload:
     """The 64-antenna 1 km array, 2016 baselines x 100 times x 50 channels
     (+-10 % around 1.43 GHz) = 10,080,000 records; 2048^2 grid, 7x7, beta 8."""

@@ -69,8 +69,11 @@ def test_invalid_arguments_rejected_on_host(L, bad):
     st = L.mg_degrid(C.byref(g), C.byref(k), 10, 0x2000, api.MG_F32, 0x3000, 0x4000, None, None)
     assert st == api.MG_EINVAL
     h = C.c_void_p()
-    st = L.mg_plan_create(C.byref(h), C.byref(g), C.byref(k), 10, 0x2000, api.MG_F32, None)
+    st = L.mg_plan_create(C.byref(h), C.byref(g), C.byref(k), 10, 0x2000, api.MG_F32, None, None)
     assert st == api.MG_EINVAL and not h.value
+    nb = C.c_size_t(123)
+    assert L.mg_plan_workspace_size(C.byref(g), C.byref(k), 10, C.byref(nb)) == api.MG_EINVAL
+    assert nb.value == 0
 
 
 def test_null_pointers_and_counts(L):
@@ -100,11 +103,35 @@ def test_python_binding_rejects_host_tensors():
 
 def test_server_argument_checks_on_host(L):
     h = C.c_void_p()
-    assert L.mg_server_create(None, 1 << 30, 4, 2) == api.MG_EINVAL
-    assert L.mg_server_create(C.byref(h), 0, 4, 2) == api.MG_EINVAL
-    assert L.mg_server_create(C.byref(h), 1 << 30, 0, 2) == api.MG_EINVAL
-    assert L.mg_server_create(C.byref(h), 1 << 30, 4, 0) == api.MG_EINVAL
-    assert L.mg_server_create(C.byref(h), 1 << 30, 4, 65) == api.MG_EINVAL
+    assert L.mg_server_create(None, 1 << 30, 4, 2, -1) == api.MG_EINVAL
+    assert L.mg_server_create(C.byref(h), 0, 4, 2, -1) == api.MG_EINVAL
+    assert L.mg_server_create(C.byref(h), 1 << 30, 0, 2, -1) == api.MG_EINVAL
+    assert L.mg_server_create(C.byref(h), 1 << 30, 4, 0, -1) == api.MG_EINVAL
+    assert L.mg_server_create(C.byref(h), 1 << 30, 4, 65, -1) == api.MG_EINVAL
     assert not h.value
-    assert L.mg_server_submit(None, None, None, 0, None, 0, None, None, None) == api.MG_EINVAL
+    assert L.mg_server_submit(None, None, None, 0, None, 0, None, None, None, None) == api.MG_EINVAL
     assert L.mg_server_destroy(None) == api.MG_OK
+
+
+def _workspace_bytes(L, **kw):
+    g, k, keep = _descs(**kw)
+    nb = C.c_size_t()
+    st = L.mg_plan_workspace_size(C.byref(g), C.byref(k), kw.get("nrec", 1000), C.byref(nb))
+    assert st == api.MG_OK, L.mg_last_error()
+    return nb.value
+
+
+def test_plan_workspace_size_on_host(L):
+    """The workspace size is a host computation: it grows with the record
+    count (at least 12 bytes of sorted metadata and permutation per record)
+    and with the grid (bucket arrays), and is a multiple of the 256-byte
+    alignment of its arrays."""
+    a = _workspace_bytes(L, nrec=1000)
+    b = _workspace_bytes(L, nrec=101000)
+    c = _workspace_bytes(L, nrec=1000, nu=4096, nv=4096)
+    assert a % 256 == 0 and b % 256 == 0
+    assert b - a >= 12 * 100000
+    assert c > a
+    w = _workspace_bytes(L, kind=api.MG_KERNEL_WPROJ, nplanes=2, ps=[8, 16, 8, 8],
+                         po=[0, 33 * 33], ntaps=33 * 33 + 65 * 65, beta=4, nrec=1000)
+    assert w > 2 * 8 * (33 * 33 + 65 * 65)      # the tap table and its conjugate

@@ -3,6 +3,7 @@
 Bar: indices bit-exact; grid and degrid values within relative L2 1e-5
 (FP32 arithmetic against the FP64 definition); skipped counts exact.
 """
+import ctypes as C
 import math
 
 import numpy as np
@@ -218,7 +219,7 @@ def test_empty_and_all_skipped(torch_cuda, api, small_sep):
 
 def test_single_record_and_hot_cell(torch_cuda, api, small_sep, small_wproj):
     """One record; and 200k records on one NN pixel (the thesis's
-    Maximum Performance input, Section 3.4.5), the worst case for
+    Maximum Performance input, Section 3.4.4), the worst case for
     same-cell contention."""
     torch = torch_cuda
     for wl in (small_sep, small_wproj):
@@ -261,3 +262,47 @@ def test_reduced_precision_bank(torch_cuda, api, small_wproj, dtype):
     u = 2.0 ** -11 if dtype == "f16" else 2.0 ** -8
     err = H.rel_l2(G, G_full)
     assert err < 2 * u, err
+
+
+def test_plan_in_torch_workspace_and_library_owned(torch_cuda, api, small_sep):
+    """A plan's device arrays live in the workspace the binding allocates
+    with torch (torch's allocator accounts for them); a plan created through
+    the C ABI without a workspace owns a stream-ordered arena, which
+    mg_plan_destroy releases after the plan's last calls, here queued on two
+    streams just before the destroy."""
+    torch = torch_cuda
+    wl = small_sep
+    spec, bank = H.grid_spec(wl), H.device_bank(wl)
+    uvw = _to_dev(torch, wl.uvw)
+    vis = _to_dev(torch, W.vis_normal(wl.nrec, 4, seed=14))
+    need = api.workspace_size(spec, bank, wl.nrec)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    plan = api.Plan(spec, bank, uvw)
+    assert torch.cuda.memory_allocated() - before >= need
+    assert plan.nbytes == need
+    g1 = plan.grid(vis)
+    L = api.lib()
+    h = C.c_void_p()
+    gd, kd = spec.desc(), bank.desc()
+    cur = torch.cuda.current_stream()
+    assert L.mg_plan_create(C.byref(h), C.byref(gd), C.byref(kd), wl.nrec, uvw.data_ptr(),
+                            api.MG_F64, None, cur.cuda_stream) == api.MG_OK
+    g2 = torch.zeros_like(g1)
+    assert L.mg_plan_grid(h, vis.data_ptr(), g2.data_ptr(), cur.cuda_stream) == api.MG_OK
+    side = torch.cuda.Stream()
+    side.wait_stream(cur)
+    v2 = torch.empty_like(vis)
+    assert L.mg_plan_degrid(h, g1.data_ptr(), v2.data_ptr(), side.cuda_stream) == api.MG_OK
+    assert L.mg_plan_destroy(h) == api.MG_OK
+    torch.cuda.synchronize()
+    v1 = plan.degrid(g1)
+    torch.cuda.synchronize()
+    assert H.rel_l2(g2.cpu().numpy(), g1.cpu().numpy()) < 1e-6
+    assert H.rel_l2(v2.cpu().numpy(), v1.cpu().numpy()) < 1e-6
+    G_ref, _ = oracle.grid(H.oracle_geom(wl), H.oracle_taps(wl), wl.uvw, vis.cpu().numpy())
+    assert H.rel_l2(g1.cpu().numpy(), G_ref) < TOL
+    held = torch.cuda.memory_allocated()
+    plan.close()
+    torch.cuda.synchronize()
+    assert held - torch.cuda.memory_allocated() >= need
