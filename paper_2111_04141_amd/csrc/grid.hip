@@ -26,7 +26,8 @@
 //    and a commit is one conversion, rounded to nearest, and one integer LDS
 //    atomic per component (integer LDS atomics run at full wave rate, unlike
 //    float LDS atomics, which serialise per lane).  The sums cannot overflow
-//    and each commit is off by at most half a quantum, 2^-31 B.  At the end
+//    and each commit is off by at most half a quantum 2^-e, which is below
+//    2^-30 B (2^e is the largest power of two with 2^e B <= 2^30).  At the end
 //    of the unit the region is converted back to FP32 (times 2^-e) and added
 //    to the grid with float atomics, one per touched cell.
 //

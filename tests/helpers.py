@@ -77,7 +77,8 @@ def fixed_point_cell_bound(geom, taps, uvw, vis, support: int, tile: int = 32, w
     gridders (supports up to 32), from the oracle alone.
 
     Each commit into a unit's fixed-point region is off by at most half a
-    quantum, 2^-31 B, where B = 2 (1.0001) sum over the unit's records of
+    quantum; the quantum is the power of two 2^(e - 30) with B < 2^e, so half
+    of it is below 2^-30 B, where B = 2 (1.0001) sum over the unit's records of
     max|weight component| max|visibility component| <= 2.0002 R wmax Vmax;
     a unit's records lie in one tile, so Vmax for cell c can be taken over
     the records whose first cell lies within tile + support of c.  A cell
@@ -119,7 +120,7 @@ def fixed_point_cell_bound(geom, taps, uvw, vis, support: int, tile: int = 32, w
     vnear = maximum_filter(vmap, size=2 * reach + 1, mode="constant")[reach:reach + wv,
                                                                        reach:reach + wu]
     R = plan_chunk_records(nrec)
-    quantum_half = 2.0 ** -31 * 2.0002 * R * wmax * vnear
+    quantum_half = 2.0 ** -30 * 2.0002 * R * wmax * vnear
     bound = n_c[None] * quantum_half[None] + (n_c[None] + 4) * 2.0 ** -24 * mag
     return bound, n_c
 
