@@ -197,6 +197,27 @@ mg_status mg_degrid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec
                     const void *uvw, mg_dtype uvw_dtype, const void *grid, void *vis_out,
                     int64_t *d_nskipped, hipStream_t stream);
 
+/* ---- one-shot gridding that allocates nothing ----
+ * For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and arguments as mg_grid, with the plan and the call's
+ * scratch taken from a static device array of mg_grid_static_capacity()
+ * bytes (64 MiB) inside the library, one per GPU, held until the process
+ * ends.  No hipMalloc, hipFree or allocating library routine is called.
+ * Calls that need more scratch than the array holds (about 44 bytes per
+ * record plus the grid's bucket arrays and the tap table: roughly 1.3
+ * million records on a 1024^2 grid) return MG_ENOMEM before anything is
+ * queued, with the needed size in mg_last_error().  Every call on one GPU
+ * uses the same array: calls that overlap on one GPU (different streams or
+ * threads) race and must be ordered by the caller.  Errors otherwise as
+ * mg_grid. */
+mg_status mg_grid_static(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                         const void *uvw, mg_dtype uvw_dtype, const void *vis, void *grid,
+                         int64_t *d_nskipped, hipStream_t stream);
+
+/* Bytes of the static scratch of mg_grid_static. */
+size_t mg_grid_static_capacity(void);
+
 /* ---- serving: continuous batching of gridding jobs ----
  *
  * A server owns a pool of HIP streams (default priority) on one device and a

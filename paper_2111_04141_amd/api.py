@@ -87,6 +87,9 @@ def lib():
     L.mg_plan_destroy.argtypes = [vp]
     L.mg_grid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
     L.mg_degrid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
+    L.mg_grid_static.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
+    L.mg_grid_static_capacity.argtypes = []
+    L.mg_grid_static_capacity.restype = C.c_size_t
     L.mg_server_create.argtypes = [C.POINTER(vp), C.c_size_t, i32, i32, i32]
     L.mg_server_submit.argtypes = [vp, gd, kd, i64, vp, i32, vp, vp, vp, C.POINTER(C.c_uint64)]
     L.mg_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(i32), C.POINTER(C.c_double)]
@@ -96,6 +99,7 @@ def lib():
     for f in ("mg_compute_indices", "mg_plan_workspace_size", "mg_plan_create",
               "mg_plan_grid", "mg_plan_degrid",
               "mg_plan_nskipped", "mg_plan_bytes", "mg_plan_destroy", "mg_grid", "mg_degrid",
+              "mg_grid_static",
               "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait",
               "mg_server_get_stats", "mg_server_destroy"):
         getattr(L, f).restype = i32
@@ -251,6 +255,29 @@ def grid(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, vis: torch.Tensor,
     _check(lib().mg_grid(C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt, vis.data_ptr(),
                          out.data_ptr(), _ptr(nskipped), _stream_ptr(uvw.device)), "mg_grid")
     return out
+
+
+def grid_static(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, vis: torch.Tensor,
+                out: Optional[torch.Tensor] = None, nskipped: Optional[torch.Tensor] = None):
+    """One-shot gridding that allocates no device memory in the library
+    (mg_grid_static: scratch from a static array of static_capacity() bytes;
+    calls on one GPU must not overlap): out += G vis."""
+    dt = _check_uvw(uvw)
+    n = uvw.shape[0]
+    _check_vis(vis, n, spec.npol)
+    if out is None:
+        out = torch.zeros(spec.npol, spec.nv, spec.nu, dtype=torch.complex64, device=uvw.device)
+    _check_grid(out, spec)
+    gd, kd = spec.desc(), bank.desc()
+    _check(lib().mg_grid_static(C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt, vis.data_ptr(),
+                                out.data_ptr(), _ptr(nskipped), _stream_ptr(uvw.device)),
+           "mg_grid_static")
+    return out
+
+
+def static_capacity() -> int:
+    """Bytes of the static scratch behind grid_static."""
+    return int(lib().mg_grid_static_capacity())
 
 
 def degrid(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, grid_in: torch.Tensor,

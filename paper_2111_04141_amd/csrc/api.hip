@@ -414,7 +414,40 @@ mg_status mg_plan_destroy(mg_plan *plan) {
     return s == MG_OK ? MG_OK : set_error(s, "stream wait failed");
 }
 
+}  // extern "C"
+
+// Static scratch of mg_grid_static: the plan and the gridding scratch of
+// one call, for callers that cannot allocate device memory.  Every GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// the array's name is not a device address: its address on each device is
+// queried once, with that device current, and kept.
+static constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+extern "C" {
+
 namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;   // device -> address of its copy
+
+mg_status static_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(MG_EDEVICE, "no device");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return MG_OK;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return set_error(MG_EDEVICE, std::string("static scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return MG_OK;
+}
+
 // One-shot calls: plan and call scratch in one stream-ordered allocation.
 mg_status one_shot(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
                    const void *uvw, mg_dtype uvw_dtype, bool gridding, const void *in, void *out,
@@ -448,6 +481,35 @@ mg_status mg_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec, 
     if (!grid) return set_error(MG_EINVAL, "null grid");
     return one_shot(g, k, nrec, uvw, uvw_dtype, true, vis, grid, d_nskipped, stream);
 }
+
+mg_status mg_grid_static(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                         const void *uvw, mg_dtype uvw_dtype, const void *vis, void *grid,
+                         int64_t *d_nskipped, hipStream_t stream) {
+    mg_status s = check_common(g, k, nrec, uvw, uvw_dtype);
+    if (s != MG_OK) return s;
+    if (nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
+    if (!grid) return set_error(MG_EINVAL, "null grid");
+    PlanState P;
+    s = plan_prepare(P, g, k, nrec);
+    if (s != MG_OK) return s;
+    const size_t pb = plan_arena_bytes(P);
+    const size_t need = pb + grid_scratch_bytes(P);
+    if (need > kStaticScratchBytes)
+        return set_error(MG_ENOMEM, "mg_grid_static needs " + std::to_string(need) +
+                                        " bytes of scratch; the static scratch holds " +
+                                        std::to_string(kStaticScratchBytes));
+    void *arena = nullptr;
+    s = static_scratch(&arena);
+    if (s != MG_OK) return s;
+    s = build_in(P, k, uvw, uvw_dtype, arena, stream);
+    if (s == MG_OK) s = launch_grid(P, vis, grid, static_cast<char *>(arena) + pb, stream);
+    if (s == MG_OK && d_nskipped)
+        hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(64), 0, stream, P.counters, d_nskipped);
+    if (s == MG_OK && hipGetLastError() != hipSuccess) s = set_error(MG_EDEVICE, "launch failed");
+    return s;
+}
+
+size_t mg_grid_static_capacity(void) { return kStaticScratchBytes; }
 
 mg_status mg_degrid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
                     const void *uvw, mg_dtype uvw_dtype, const void *grid, void *vis_out,
