@@ -337,6 +337,8 @@ def main():
                     help="skip the small, autograd and precision workload legs")
     ap.add_argument("--only-headline", action="store_true",
                     help="headline step and dominant unit only (profiling runs)")
+    ap.add_argument("--only-leg", choices=["small", "autograd", "precision", "serving"],
+                    help="run one of the other workloads alone (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
@@ -356,6 +358,19 @@ def main():
     props = torch.cuda.get_device_properties(dev)
     log(f"[bench] device {props.name}, {props.multi_processor_count} CUs, "
         f"{props.total_memory / 2**30:.0f} GiB")
+    if args.only_leg:
+        stream = torch.cuda.current_stream(dev)
+        if args.only_leg == "small":
+            r = separable_leg(api, W, torch, dev, stream, W.config_small(), "small-sep7-1024-100800")
+        elif args.only_leg == "autograd":
+            r = separable_leg(api, W, torch, dev, stream, W.config_autograd(),
+                              "autograd-sep7-2048-10M", autograd=True)
+        elif args.only_leg == "precision":
+            r = precision_leg(api, W, torch, dev, stream, steps=args.steps)
+        else:
+            r = serving_leg(dev, args.serving_jobs)
+        print(json.dumps(r), flush=True)
+        return
     if args.copy_calibration_mib > 0:
         nb = args.copy_calibration_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)

@@ -189,6 +189,38 @@ std::pair<int, int> dev_attr(int *dev_out) {
 }
 }  // namespace
 
+namespace {
+std::map<int, hipMemPool_t> g_pools;   // device -> the library's pool
+}  // namespace
+
+hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t stream) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipMemPool_t pool = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        auto it = g_pools.find(dev);
+        if (it != g_pools.end()) {
+            pool = it->second;
+        } else {
+            hipMemPoolProps props;
+            std::memset(&props, 0, sizeof props);
+            props.allocType = hipMemAllocationTypePinned;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = dev;
+            e = hipMemPoolCreate(&pool, &props);
+            if (e != hipSuccess) return e;
+            uint64_t keep = kPoolKeepBytes;
+            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            g_pools[dev] = pool;
+        }
+    }
+    return hipMallocFromPoolAsync(p, bytes, pool, stream);
+}
+
+hipError_t scratch_free(void *p, hipStream_t stream) { return hipFreeAsync(p, stream); }
+
 int device_cus() { return dev_attr(nullptr).first; }
 int device_lds_limit() { return dev_attr(nullptr).second; }
 
@@ -334,7 +366,7 @@ mg_status mg_plan_create(mg_plan **plan, const mg_grid_desc *g, const mg_kernel_
     void *arena = workspace;
     if (s == MG_OK && !arena) {
         const size_t bytes = plan_arena_bytes(p->st);
-        hipError_t e = hipMallocAsync(&arena, std::max<size_t>(bytes, kArenaAlign), stream);
+        hipError_t e = scratch_alloc(&arena, std::max<size_t>(bytes, kArenaAlign), stream);
         if (e != hipSuccess) {
             arena = nullptr;
             s = set_error(MG_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
@@ -348,7 +380,7 @@ mg_status mg_plan_create(mg_plan **plan, const mg_grid_desc *g, const mg_kernel_
             s = set_error(MG_EDEVICE, "event record failed");
     }
     if (s != MG_OK) {
-        if (p->owned) hipFreeAsync(p->owned, stream);
+        if (p->owned) scratch_free(p->owned, stream);
         if (p->ready) hipEventDestroy(p->ready);
         delete p;
         return s;
@@ -402,7 +434,7 @@ mg_status mg_plan_destroy(mg_plan *plan) {
         hipStream_t st = plan->create_stream;
         for (auto &u : plan->uses)
             if (hipStreamWaitEvent(st, u.second, 0) != hipSuccess) s = MG_EDEVICE;
-        if (hipFreeAsync(plan->owned, st) != hipSuccess) {
+        if (scratch_free(plan->owned, st) != hipSuccess) {
             hipEventSynchronize(plan->ready);
             for (auto &u : plan->uses) hipEventSynchronize(u.second);
             hipFree(plan->owned);
@@ -458,7 +490,7 @@ mg_status one_shot(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
     const size_t pb = plan_arena_bytes(P);
     const size_t cb = gridding ? grid_scratch_bytes(P) : degrid_scratch_bytes(P);
     void *arena = nullptr;
-    hipError_t e = hipMallocAsync(&arena, pb + cb, stream);
+    hipError_t e = scratch_alloc(&arena, pb + cb, stream);
     if (e != hipSuccess) return set_error(MG_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
     s = build_in(P, k, uvw, uvw_dtype, arena, stream);
     void *scratch = static_cast<char *>(arena) + pb;
@@ -467,7 +499,7 @@ mg_status one_shot(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
                      : launch_degrid(P, in, out, scratch, stream);
     if (s == MG_OK && d_nskipped)
         hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(64), 0, stream, P.counters, d_nskipped);
-    hipFreeAsync(arena, stream);
+    scratch_free(arena, stream);
     return s;
 }
 }  // namespace

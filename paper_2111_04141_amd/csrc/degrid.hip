@@ -720,7 +720,7 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, voi
     uint32_t *queues = static_cast<uint32_t *>(scratch);
     hipError_t e = hipSuccess;
     if (!queues) {
-        e = hipMallocAsync((void **)&queues, degrid_scratch_bytes(P), stream);
+        e = scratch_alloc((void **)&queues, degrid_scratch_bytes(P), stream);
         if (e != hipSuccess) return set_error(MG_ENOMEM, "degrid: work queue allocation failed");
     }
     hipLaunchKernelGGL(clear_queue_kernel, dim3(1), dim3(256), 0, stream, queues, np);
@@ -753,7 +753,7 @@ mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, voi
         p0 = p1;
     }
     if (e == hipSuccess) e = hipGetLastError();
-    if (!scratch) hipFreeAsync(queues, stream);
+    if (!scratch) scratch_free(queues, stream);
     if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("degrid kernels: ") + hipGetErrorString(e));
     return MG_OK;
 }

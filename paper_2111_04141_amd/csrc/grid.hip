@@ -930,7 +930,7 @@ mg_status launch_grid(const PlanState &P, const void *vis, void *grid, void *scr
     hipError_t e = hipSuccess;
     void *own = nullptr;
     if (!scratch) {
-        e = hipMallocAsync(&own, grid_scratch_bytes(P), stream);
+        e = scratch_alloc(&own, grid_scratch_bytes(P), stream);
         if (e != hipSuccess) return set_error(MG_ENOMEM, "grid: scratch allocation failed");
         scratch = own;
     }
@@ -973,7 +973,7 @@ mg_status launch_grid(const PlanState &P, const void *vis, void *grid, void *scr
         p0 = p1;
     }
     if (e == hipSuccess) e = hipGetLastError();
-    if (own) hipFreeAsync(own, stream);
+    if (own) scratch_free(own, stream);
     if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("grid kernels: ") + hipGetErrorString(e));
     return MG_OK;
 }

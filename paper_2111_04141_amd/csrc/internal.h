@@ -130,6 +130,15 @@ mg_status launch_grid(const PlanState &P, const void *vis, void *grid, void *scr
 mg_status launch_degrid(const PlanState &P, const void *grid, void *vis_out, void *scratch,
                         hipStream_t stream);
 
+// Stream-ordered scratch from the library's memory pool of the current
+// device, which keeps up to kPoolKeepBytes of freed memory cached between
+// calls (the device's default pool returns it at every synchronisation,
+// which made one-shot calls after a synchronisation pay for mapping their
+// scratch again) (api.hip).
+constexpr uint64_t kPoolKeepBytes = uint64_t(8) << 30;
+hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t stream);
+hipError_t scratch_free(void *p, hipStream_t stream);
+
 // Workgroups of `kernel` (threads per workgroup, dynamic LDS bytes) that fit
 // on the current device at once; device attributes and occupancy are queried
 // once per (device, kernel, threads, lds) and cached (api.hip).
