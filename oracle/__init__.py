@@ -48,6 +48,13 @@ def _load():
     lib.orc_grid_window_par.restype = C.c_int64
     lib.orc_max_threads.argtypes = []
     lib.orc_max_threads.restype = C.c_int32
+    lib.orc_hybrid_grid_window.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                           C.c_double, C.c_int32, dp, C.c_int64, dp, C.c_int32,
+                                           dp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp]
+    lib.orc_hybrid_grid_window.restype = C.c_int64
+    lib.orc_prune_columns.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                      dp, dp, dp]
+    lib.orc_prune_columns.restype = C.c_int64
     _lib = lib
     return lib
 
@@ -175,6 +182,50 @@ def grid_par(g: Geometry, taps, uvw, vis, window=None, out=None, nthreads: int =
     if sk < 0:
         raise ValueError("oracle: invalid geometry")
     return out, int(sk)
+
+
+def hybrid_grid(g: Geometry, taps, uvw, vis, window=None, out=None):
+    """Hybrid Gridding Step (separable geometry only): the kernel along u,
+    nearest neighbour onto the beta-oversampled v axis.  Grid complex128
+    [npol, beta nv, nu] (or the window (u0, v0, wu, wv) of it, v0 and wv in
+    rows of the oversampled axis).  Returns (grid, nskipped)."""
+    assert g.kind == "separable"
+    lib = _load()
+    uvw = _uvw64(uvw)
+    vis = np.ascontiguousarray(np.asarray(vis, np.complex128))
+    if vis.ndim == 1:
+        vis = vis[:, None]
+    npol = vis.shape[1]
+    rows = g.beta * g.nv
+    u0, v0, wu, wv = window if window is not None else (0, 0, g.nu, rows)
+    if out is None:
+        out = np.zeros((npol, wv, wu), np.complex128)
+    assert out.dtype == np.complex128 and out.flags.c_contiguous and out.shape == (npol, wv, wu)
+    t = np.ascontiguousarray(np.asarray(taps, np.float64))
+    sk = lib.orc_hybrid_grid_window(g.nu, g.nv, g.beta, float(g.scale_u), float(g.scale_v),
+                                    int(g.support), _ptr(t), uvw.shape[0], _ptr(uvw), npol,
+                                    _ptr(vis.view(np.float64)), u0, v0, wu, wv,
+                                    _ptr(out.view(np.float64)))
+    if sk < 0:
+        raise ValueError("oracle: invalid geometry")
+    return out, int(sk)
+
+
+def prune_columns(grid_in, alpha: int, ztaps, support_z: int):
+    """Column pruning: every column of grid_in [npol, M, ncols] circularly
+    convolved with the pruning kernel (table of alpha Sz + 1 values) and
+    downsampled by alpha.  Returns complex128 [npol, M / alpha, ncols]."""
+    lib = _load()
+    G = np.ascontiguousarray(np.asarray(grid_in, np.complex128))
+    npol, M, ncols = G.shape
+    out = np.zeros((npol, M // alpha, ncols), np.complex128)
+    z = np.ascontiguousarray(np.asarray(ztaps, np.float64))
+    assert z.shape[0] >= alpha * support_z + 1
+    rc = lib.orc_prune_columns(npol, M, ncols, alpha, support_z, _ptr(z),
+                               _ptr(G.view(np.float64)), _ptr(out.view(np.float64)))
+    if rc < 0:
+        raise ValueError("oracle: invalid pruning geometry")
+    return out
 
 
 def max_threads() -> int:

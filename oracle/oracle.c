@@ -40,6 +40,9 @@
  * footprint reaches it, so each cell receives its contributions in the same
  * order as in orc_grid_window and the two agree bit for bit.
  *
+ * Hybrid Gridding and column pruning (NEXT to the convolutional gridder, at
+ * the end of this file) follow the same rules; their pins tie them to it.
+ *
  * Parity pins (in tests/): delta kernel at integer cells, brute-force
  * footprint enumeration, the equivalence theorem (NN onto the beta grid,
  * then a discrete convolution), equal-offset exactness against a direct DFT
@@ -413,4 +416,110 @@ int32_t orc_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------
+ * Hybrid Gridding (Algorithm "The studied Hybrid Gridding Algorithm",
+ * Section 2.4.4): the Gridding Step convolves with C_hy = C_co(u) rect(v),
+ * i.e. along u the oversampled separable kernel of support S sampled at the
+ * integer cells (exactly as in the convolutional gridder above), along v
+ * nearest-neighbour interpolation onto the v axis oversampled by beta.  The
+ * output grid has nv * beta rows (row q = the nearest pixel of the
+ * beta-oversampled v axis, q = floor(beta x_v + 1/2), x_v = v scale_v +
+ * nv/2, the same rule as for the convolutional gridder) and nu columns; the
+ * origin u = v = 0 is at column nu/2, row beta nv / 2.  A record is gridded
+ * if uvw is finite, its u footprint lies inside [0, nu) and 0 <= q < beta
+ * nv.  out: complex128 [npol][wv][wu], the window [u0, u0 + wu) x
+ * [v0, v0 + wv) of the [npol][beta nv][nu] grid, ACCUMULATED.  Returns the
+ * number of skipped records, or ORC_EINVAL. */
+int64_t orc_hybrid_grid_window(int32_t nu, int32_t nv, int32_t beta, double scale_u,
+                               double scale_v, int32_t support, const double *taps,
+                               int64_t nrec, const double *uvw, int32_t npol, const double *vis,
+                               int32_t u0, int32_t v0, int32_t wu, int32_t wv, double *out)
+{
+    if (nu <= 0 || nv <= 0 || beta <= 0 || support <= 0 || npol < 1 ||
+        ((int64_t)beta * support) % 2)
+        return ORC_EINVAL;
+    const int64_t rows = (int64_t)beta * nv;
+    int64_t skipped = 0;
+    for (int64_t r = 0; r < nrec; ++r) {
+        const double u = uvw[3 * r], v = uvw[3 * r + 1], w = uvw[3 * r + 2];
+        if (!isfinite(u) || !isfinite(v) || !isfinite(w)) {
+            ++skipped;
+            continue;
+        }
+        axis_index au = index_axis(u, scale_u, nu, beta, support);
+        double x = v * scale_v;
+        x = x + (double)(nv / 2);
+        double xb = x * (double)beta;
+        xb = xb + 0.5;
+        const double fq = floor(xb);
+        if (!au.ok || !(fq >= 0.0) || !(fq < (double)rows)) {
+            ++skipped;
+            continue;
+        }
+        const int64_t q = (int64_t)fq;
+        const int64_t cv = q - v0;
+        if (cv < 0 || cv >= wv)
+            continue;
+        for (int32_t i = 0; i < support; ++i) {
+            const int64_t cu = au.k_lo + i - u0;
+            if (cu < 0 || cu >= wu)
+                continue;
+            const double wr = taps[au.t0 + (int64_t)i * beta];
+            for (int32_t pol = 0; pol < npol; ++pol) {
+                const double *V = vis + 2 * (r * npol + pol);
+                double *G = out + 2 * (((int64_t)pol * wv + cv) * wu + cu);
+                G[0] += wr * V[0];
+                G[1] += wr * V[1];
+            }
+        }
+    }
+    return skipped;
+}
+
+/* Column pruning (Convolution-Based FFT Pruning of Algorithm "A General
+ * Algorithm for Convolution-based FFT Pruning in one dimension", Section
+ * 2.5.2, applied down every column, as the Column Pruner of Section 7.1):
+ * each column of M = nrows values is circularly convolved with the pruning
+ * kernel and downsampled by alpha,
+ *   out[j] = sum_{s=0}^{Sz-1} sum_{a=0}^{alpha-1} c(alpha (s - Sz/2) + a)
+ *            in[(alpha (j - Sz/2 + s) + a) mod M],   j = 0 .. M/alpha - 1,
+ * with c(d) = ztaps[d + alpha Sz / 2], a table of alpha Sz + 1 real values
+ * (entry e at offset (e - alpha Sz/2) / alpha output samples; the last entry
+ * is not used).  in: complex128 [npol][M][ncols]; out: complex128
+ * [npol][M / alpha][ncols], OVERWRITTEN.  Requires M divisible by alpha and
+ * Sz even.  Returns 0 or ORC_EINVAL. */
+int64_t orc_prune_columns(int32_t npol, int64_t nrows, int32_t ncols, int32_t alpha,
+                          int32_t support_z, const double *ztaps, const double *in,
+                          double *out)
+{
+    if (npol < 1 || nrows < 1 || ncols < 1 || alpha < 1 || support_z < 1 ||
+        nrows % alpha || support_z % 2)
+        return ORC_EINVAL;
+    const int64_t nout = nrows / alpha;
+    const int64_t half = (int64_t)alpha * support_z / 2;
+    for (int32_t pol = 0; pol < npol; ++pol) {
+        for (int64_t j = 0; j < nout; ++j) {
+            for (int32_t col = 0; col < ncols; ++col) {
+                double sr = 0.0, si = 0.0;
+                for (int32_t s = 0; s < support_z; ++s) {
+                    for (int32_t a = 0; a < alpha; ++a) {
+                        const int64_t d = (int64_t)alpha * (s - support_z / 2) + a;
+                        const double c = ztaps[d + half];
+                        int64_t row = ((int64_t)alpha * (j - support_z / 2 + s) + a) % nrows;
+                        if (row < 0)
+                            row += nrows;
+                        const double *x = in + 2 * (((int64_t)pol * nrows + row) * ncols + col);
+                        sr += c * x[0];
+                        si += c * x[1];
+                    }
+                }
+                double *o = out + 2 * (((int64_t)pol * nout + j) * ncols + col);
+                o[0] = sr;
+                o[1] = si;
+            }
+        }
+    }
+    return 0;
 }
