@@ -218,6 +218,71 @@ mg_status mg_grid_static(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t
 /* Bytes of the static scratch of mg_grid_static. */
 size_t mg_grid_static_capacity(void);
 
+/* ---- Hybrid Gridding and column pruning ----
+ *
+ * Hybrid Gridding (Algorithm "The studied Hybrid Gridding Algorithm",
+ * Section 2.4.4) splits the convolutional Gridding Step in one dimension:
+ * along u a record is convolved with the separable kernel (S taps at the
+ * integer cells, the index rule above), along v it is moved to the nearest
+ * pixel of the beta-oversampled v axis, row q = floor(beta x_v + 1/2) with
+ * x_v = v scale_v + nv/2 (nearest-neighbour interpolation, C_hy = C_co(u)
+ * rect(v)).  Output grid: [npol][beta nv][nu] complex64, u fastest, column
+ * nu/2 and row beta nv / 2 are u = v = 0.  A record is gridded if uvw is
+ * finite, its u footprint lies inside [0, nu) and 0 <= q < beta nv;
+ * otherwise it is skipped and counted.  Kernel: separable only, support
+ * 1..32, taps F32/F16/BF16 (FP32 arithmetic).  Grid entry points ADD into
+ * the grid.  A hybrid plan bins the records once by tile of the hybrid grid
+ * (the Gridder then takes chunks of one tile); its memory is the caller's
+ * workspace (mg_hybrid_plan_workspace_size bytes, 256-byte aligned, kept
+ * alive until the plan is destroyed and its work has completed), or, with
+ * workspace == NULL, a stream-ordered allocation released on the creating
+ * stream by mg_hybrid_plan_destroy (calls on other streams must be ordered
+ * before it).  Errors: MG_EINVAL (bad descriptor, non-separable kernel,
+ * support above 32), MG_ENOMEM, MG_EDEVICE. */
+typedef struct mg_hybrid_plan mg_hybrid_plan;
+
+mg_status mg_hybrid_plan_workspace_size(const mg_grid_desc *g, const mg_kernel_desc *k,
+                                        int64_t nrec, size_t *bytes);
+
+mg_status mg_hybrid_plan_create(mg_hybrid_plan **plan, const mg_grid_desc *g,
+                                const mg_kernel_desc *k, int64_t nrec, const void *uvw,
+                                mg_dtype uvw_dtype, void *workspace, hipStream_t stream);
+
+/* grid_hy += G_hy vis; vis [nrec][npol] complex64 in the create call's
+ * order, grid_hy [npol][beta nv][nu] complex64.  Allocates nothing. */
+mg_status mg_hybrid_plan_grid(const mg_hybrid_plan *plan, const void *vis, void *grid_hy,
+                              hipStream_t stream);
+
+/* Records skipped by the hybrid rule (waits for the plan's creation). */
+mg_status mg_hybrid_plan_nskipped(const mg_hybrid_plan *plan, int64_t *nskipped);
+
+mg_status mg_hybrid_plan_destroy(mg_hybrid_plan *plan);
+
+/* One-shot Hybrid Gridding (bin + grid; scratch allocated and released
+ * stream-ordered inside the call).  *d_nskipped (device, may be NULL) is
+ * INCREMENTED by the skipped count. */
+mg_status mg_hybrid_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                         const void *uvw, mg_dtype uvw_dtype, const void *vis, void *grid_hy,
+                         int64_t *d_nskipped, hipStream_t stream);
+
+/* Column pruning, the Pruning Step of Hybrid Gridding (Convolution-Based FFT
+ * Pruning, Algorithm of Section 2.5.2, down every column as the Column
+ * Pruner of Section 7.1; its output equation, Section 7.1.1): every column
+ * of M = nrows values is circularly convolved with the pruning kernel and
+ * downsampled by alpha,
+ *   out[j] = sum_{s=0}^{Sz-1} sum_{a=0}^{alpha-1} c(alpha (s - Sz/2) + a)
+ *            in[(alpha (j - Sz/2 + s) + a) mod M],   j < M / alpha,
+ * c(d) = ztaps[d + alpha Sz/2] (DEVICE, FP32, alpha Sz + 1 entries; entry e
+ * at offset (e - alpha Sz/2)/alpha output samples; the last is not used).
+ * in: [npol][nrows][ncols] complex64; out: [npol][nrows/alpha][ncols]
+ * complex64, OVERWRITTEN.  For Hybrid Gridding: nrows = beta nv, ncols =
+ * nu, alpha = beta/2 (oversampling 2 after pruning), Sz even in 2..16.
+ * Errors: MG_EINVAL (nrows not a multiple of alpha, Sz odd or above 16,
+ * null pointer), MG_EDEVICE.  Allocates nothing. */
+mg_status mg_prune_columns(int32_t npol, int64_t nrows, int32_t ncols, int32_t alpha,
+                           int32_t support_z, const float *ztaps, const void *in, void *out,
+                           hipStream_t stream);
+
 /* ---- serving: continuous batching of gridding jobs ----
  *
  * A server owns a pool of HIP streams (default priority) on one device and a

@@ -88,6 +88,13 @@ def lib():
     L.mg_grid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
     L.mg_degrid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
     L.mg_grid_static.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
+    L.mg_hybrid_plan_workspace_size.argtypes = [gd, kd, i64, C.POINTER(C.c_size_t)]
+    L.mg_hybrid_plan_create.argtypes = [C.POINTER(vp), gd, kd, i64, vp, i32, vp, vp]
+    L.mg_hybrid_plan_grid.argtypes = [vp, vp, vp, vp]
+    L.mg_hybrid_plan_nskipped.argtypes = [vp, C.POINTER(i64)]
+    L.mg_hybrid_plan_destroy.argtypes = [vp]
+    L.mg_hybrid_grid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
+    L.mg_prune_columns.argtypes = [i32, i64, i32, i32, i32, vp, vp, vp, vp]
     L.mg_grid_static_capacity.argtypes = []
     L.mg_grid_static_capacity.restype = C.c_size_t
     L.mg_server_create.argtypes = [C.POINTER(vp), C.c_size_t, i32, i32, i32]
@@ -99,7 +106,9 @@ def lib():
     for f in ("mg_compute_indices", "mg_plan_workspace_size", "mg_plan_create",
               "mg_plan_grid", "mg_plan_degrid",
               "mg_plan_nskipped", "mg_plan_bytes", "mg_plan_destroy", "mg_grid", "mg_degrid",
-              "mg_grid_static",
+              "mg_grid_static", "mg_hybrid_plan_workspace_size", "mg_hybrid_plan_create",
+              "mg_hybrid_plan_grid", "mg_hybrid_plan_nskipped", "mg_hybrid_plan_destroy",
+              "mg_hybrid_grid", "mg_prune_columns",
               "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait",
               "mg_server_get_stats", "mg_server_destroy"):
         getattr(L, f).restype = i32
@@ -440,3 +449,108 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# Hybrid Gridding and column pruning
+# ---------------------------------------------------------------------------
+
+def _check_hybrid_grid(g: torch.Tensor, spec: GridSpec):
+    shape = (spec.npol, spec.beta * spec.nv, spec.nu)
+    if (not g.is_cuda or g.dtype != torch.complex64 or not g.is_contiguous()
+            or tuple(g.shape) != shape):
+        raise ValueError(f"hybrid grid must be a contiguous complex64 {list(shape)} device tensor")
+
+
+def hybrid_grid(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, vis: torch.Tensor,
+                out: Optional[torch.Tensor] = None, nskipped: Optional[torch.Tensor] = None):
+    """One-shot Hybrid Gridding Step: out [npol, beta nv, nu] += G_hy vis."""
+    dt = _check_uvw(uvw)
+    n = uvw.shape[0]
+    _check_vis(vis, n, spec.npol)
+    if out is None:
+        out = torch.zeros(spec.npol, spec.beta * spec.nv, spec.nu, dtype=torch.complex64,
+                          device=uvw.device)
+    _check_hybrid_grid(out, spec)
+    gd, kd = spec.desc(), bank.desc()
+    _check(lib().mg_hybrid_grid(C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt, vis.data_ptr(),
+                                out.data_ptr(), _ptr(nskipped), _stream_ptr(uvw.device)),
+           "mg_hybrid_grid")
+    return out
+
+
+class HybridPlan:
+    """Bin the records once by tile of the hybrid grid, then run the Hybrid
+    Gridding Step many times; the plan's memory is a torch workspace."""
+
+    def __init__(self, spec: GridSpec, bank: KernelBank, uvw: torch.Tensor):
+        dt = _check_uvw(uvw)
+        self.spec, self.bank = spec, bank
+        self.nrec = uvw.shape[0]
+        self.device = uvw.device
+        gd, kd = spec.desc(), bank.desc()
+        v = C.c_size_t()
+        _check(lib().mg_hybrid_plan_workspace_size(C.byref(gd), C.byref(kd), self.nrec,
+                                                   C.byref(v)), "mg_hybrid_plan_workspace_size")
+        self.workspace = torch.empty(int(v.value), dtype=torch.uint8, device=uvw.device)
+        self._h = C.c_void_p()
+        _check(lib().mg_hybrid_plan_create(C.byref(self._h), C.byref(gd), C.byref(kd), self.nrec,
+                                           uvw.data_ptr(), dt, self.workspace.data_ptr(),
+                                           _stream_ptr(uvw.device)), "mg_hybrid_plan_create")
+
+    def grid(self, vis: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        _check_vis(vis, self.nrec, self.spec.npol)
+        if out is None:
+            out = torch.zeros(self.spec.npol, self.spec.beta * self.spec.nv, self.spec.nu,
+                              dtype=torch.complex64, device=self.device)
+        _check_hybrid_grid(out, self.spec)
+        _check(lib().mg_hybrid_plan_grid(self._h, vis.data_ptr(), out.data_ptr(),
+                                         _stream_ptr(self.device)), "mg_hybrid_plan_grid")
+        return out
+
+    @property
+    def nskipped(self) -> int:
+        v = C.c_int64()
+        _check(lib().mg_hybrid_plan_nskipped(self._h, C.byref(v)), "mg_hybrid_plan_nskipped")
+        return int(v.value)
+
+    def close(self):
+        if self._h:
+            lib().mg_hybrid_plan_destroy(self._h)
+            self._h = C.c_void_p()
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def prune_columns(grid_in: torch.Tensor, alpha: int, ztaps: torch.Tensor, support_z: int,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Column pruning: every column of grid_in [npol, M, ncols] circularly
+    convolved with the pruning kernel (FP32 device table of alpha Sz + 1
+    values) and downsampled by alpha; returns [npol, M / alpha, ncols]."""
+    if (not grid_in.is_cuda or grid_in.dtype != torch.complex64 or not grid_in.is_contiguous()
+            or grid_in.dim() != 3):
+        raise ValueError("grid_in must be a contiguous complex64 [npol, M, ncols] device tensor")
+    npol, M, ncols = grid_in.shape
+    if (not ztaps.is_cuda or ztaps.dtype != torch.float32 or not ztaps.is_contiguous()
+            or ztaps.numel() < alpha * support_z + 1):
+        raise ValueError("ztaps must be a contiguous float32 device tensor of alpha*Sz+1 values")
+    if out is None:
+        out = torch.empty(npol, M // alpha, ncols, dtype=torch.complex64, device=grid_in.device)
+    if (not out.is_contiguous() or out.dtype != torch.complex64
+            or tuple(out.shape) != (npol, M // alpha, ncols)):
+        raise ValueError("out must be a contiguous complex64 [npol, M/alpha, ncols] tensor")
+    _check(lib().mg_prune_columns(npol, M, ncols, int(alpha), int(support_z), ztaps.data_ptr(),
+                                  grid_in.data_ptr(), out.data_ptr(),
+                                  _stream_ptr(grid_in.device)), "mg_prune_columns")
+    return out

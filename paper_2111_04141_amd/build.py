@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmigrid.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "plan.hip", "grid.hip", "degrid.hip", "serve.hip"]
+SOURCES = ["api.hip", "plan.hip", "grid.hip", "degrid.hip", "serve.hip", "hybrid.hip"]
 
 CFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1,0 +1,703 @@
+// Hybrid Gridding Step and column pruning.
+//
+// Hybrid Gridding (Algorithm "The studied Hybrid Gridding Algorithm",
+// Section 2.4.4) splits the Gridding Step of convolutional gridding in one
+// dimension: along u a record is convolved with the oversampled separable
+// kernel (S taps at the integer cells, the same rule as the convolutional
+// gridder), along v it is moved to the nearest pixel of the beta-oversampled
+// v axis (nearest-neighbour interpolation, C_hy = C_co(u) rect(v)).  The
+// output is an nu x (beta nv) grid per polarisation, [npol][beta nv][nu],
+// origin at column nu/2, row beta nv / 2.  A record updates S cells of one
+// row instead of S^2 cells.  The Pruning Step then downsamples every column
+// by alpha with a convolution (Convolution-Based FFT Pruning, Section 2.5.2;
+// the Column Pruner of Section 7.1).
+//
+// gfx950 design.
+//  * Plan (sort once, grid many times): records are binned by tile of 32
+//    columns x 32 oversampled rows and cut into chunks of at most R records;
+//    each record keeps (k_lo_u | o_u << 16, row) and its input index.
+//  * Gridder: a workgroup takes a chunk.  Its records' S x 1 footprints lie
+//    in the tile's region (32 rows x (31 + S) columns), accumulated in LDS as
+//    32-bit fixed point, like the window gridders' regions: the chunk first
+//    bounds its partial sums (2 max|tap| sum over its records of the largest
+//    visibility component), picks the power-of-two scale that maps the bound
+//    to at most 2^30, and every update is one rounded conversion and one
+//    integer LDS atomic.  Lane l of a wave takes component c = l mod 8
+//    (polarisation c/2, real or imaginary part) of tap i = l / 8 of the
+//    wave's record, so a record's S x 8 updates are one wave instruction for
+//    S <= 8 (consecutive LDS words: no bank conflicts).  At the end of the
+//    chunk the region is added to the grid with one float atomic per touched
+//    word.  A chunk holding a non-finite visibility (or whose bound
+//    overflows) adds straight to the grid in FP32.
+//  * Column pruner: one thread per (polarisation, column) and run of output
+//    rows keeps S_z accumulators in registers as a ring (the chunk
+//    calculation of Section 7.1.5): every input value is read once, with
+//    coalesced rows, and multiplied by the S_z coefficients its offset
+//    needs, which are uniform across the wave (scalar operands).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int kHyTU = 32;          // tile columns (u cells)
+constexpr int kHyTV = 32;          // tile rows (rows of the oversampled v axis)
+constexpr int kHyThreads = 256;
+constexpr int kHyMaxS = 32;
+constexpr int kHyWaves = kHyThreads / kWave;
+
+struct HyGeom {
+    int32_t nu, nv, npol, beta, S;
+    int32_t ntu, ntv;              // tiles per axis
+    int32_t rows;                  // beta * nv
+    double scale_u, scale_v;
+};
+
+// The hybrid index rule: the u axis as the convolutional gridder (first cell
+// k_lo_u, phase o_u), the v axis the nearest pixel of the beta-oversampled
+// axis, q = floor(beta x_v + 1/2), each operation rounded as written.
+template <typename T>
+__device__ inline bool hy_index(const HyGeom &g, T u_, T v_, T w_, int32_t *ku, int32_t *ou,
+                                int32_t *q) {
+#pragma clang fp contract(off)
+    const double u = (double)u_, v = (double)v_, w = (double)w_;
+    if (!(isfinite(u) && isfinite(v) && isfinite(w))) return false;
+    if (!index_axis(u, g.scale_u, g.nu, g.beta, g.S, ku, ou)) return false;
+    double x = v * g.scale_v;
+    x = x + (double)(g.nv / 2);
+    double xb = x * (double)g.beta;
+    xb = xb + 0.5;
+    const double fq = floor(xb);
+    if (!(fq >= 0.0) || !(fq < (double)g.rows)) return false;
+    *q = (int32_t)fq;
+    return true;
+}
+
+__device__ inline uint32_t hy_bucket(const HyGeom &g, int32_t ku, int32_t q) {
+    return (uint32_t)(q / kHyTV) * (uint32_t)g.ntu + (uint32_t)(ku / kHyTU);
+}
+
+constexpr uint32_t kNoBucket = 0xffffffffu;
+
+template <typename T>
+__global__ __launch_bounds__(256) void hy_count_kernel(HyGeom g, int64_t nrec,
+                                                       const T *__restrict__ uvw,
+                                                       uint32_t *__restrict__ hist,
+                                                       int64_t *__restrict__ counters) {
+    __shared__ uint32_t s_skip;
+    if (threadIdx.x == 0) s_skip = 0;
+    __syncthreads();
+    uint32_t skipped = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int64_t r0 = first; r0 < nrec; r0 += stride) {
+        const int64_t r = r0 + (threadIdx.x & 63);
+        uint32_t b = kNoBucket;
+        if (r < nrec) {
+            int32_t ku, ou, q;
+            if (hy_index<T>(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], &ku, &ou, &q))
+                b = hy_bucket(g, ku, q);
+            else
+                ++skipped;
+        }
+        wave_counter_add(hist, b, b != kNoBucket, false);
+    }
+    if (skipped) atomicAdd(&s_skip, skipped);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_skip)
+        atomicAdd((unsigned long long *)&counters[0], (unsigned long long)s_skip);
+}
+
+// Exclusive scan of the bucket counts and of their chunk counts (ceil(c/R)),
+// one workgroup: bstart, cursor (= bstart), cstart; counters[1] = valid
+// records, counters[2] = chunks.
+__global__ __launch_bounds__(256) void hy_scan_kernel(const uint32_t *__restrict__ hist, int64_t nb,
+                                                      uint32_t R, uint32_t *__restrict__ bstart,
+                                                      uint32_t *__restrict__ cursor,
+                                                      uint32_t *__restrict__ cstart,
+                                                      int64_t *__restrict__ counters) {
+    constexpr int kItems = 16;
+    __shared__ uint32_t s_rec[256], s_chk[256];
+    uint32_t carry_r = 0, carry_c = 0;
+    for (int64_t base = 0; base < nb; base += 256 * kItems) {
+        uint32_t cr[kItems], cc[kItems];
+        uint32_t tr = 0, tc = 0;
+        const int64_t b0 = base + (int64_t)threadIdx.x * kItems;
+        for (int k = 0; k < kItems; ++k) {
+            const uint32_t c = (b0 + k < nb) ? hist[b0 + k] : 0u;
+            cr[k] = c;
+            cc[k] = (c + R - 1) / R;
+            tr += cr[k];
+            tc += cc[k];
+        }
+        s_rec[threadIdx.x] = tr;
+        s_chk[threadIdx.x] = tc;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const uint32_t ar = (threadIdx.x >= (unsigned)off) ? s_rec[threadIdx.x - off] : 0u;
+            const uint32_t ac = (threadIdx.x >= (unsigned)off) ? s_chk[threadIdx.x - off] : 0u;
+            __syncthreads();
+            s_rec[threadIdx.x] += ar;
+            s_chk[threadIdx.x] += ac;
+            __syncthreads();
+        }
+        uint32_t run_r = carry_r + s_rec[threadIdx.x] - tr;
+        uint32_t run_c = carry_c + s_chk[threadIdx.x] - tc;
+        for (int k = 0; k < kItems; ++k) {
+            if (b0 + k < nb) {
+                bstart[b0 + k] = run_r;
+                cursor[b0 + k] = run_r;
+                cstart[b0 + k] = run_c;
+            }
+            run_r += cr[k];
+            run_c += cc[k];
+        }
+        carry_r += s_rec[255];
+        carry_c += s_chk[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cstart[nb] = carry_c;
+        counters[1] = carry_r;
+        counters[2] = carry_c;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void hy_scatter_kernel(HyGeom g, int64_t nrec,
+                                                         const T *__restrict__ uvw,
+                                                         uint32_t *__restrict__ cursor,
+                                                         uint2 *__restrict__ meta,
+                                                         uint32_t *__restrict__ perm) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int64_t r0 = first; r0 < nrec; r0 += stride) {
+        const int64_t r = r0 + (threadIdx.x & 63);
+        uint32_t b = kNoBucket;
+        int32_t ku = 0, ou = 0, q = 0;
+        if (r < nrec && hy_index<T>(g, uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], &ku, &ou, &q))
+            b = hy_bucket(g, ku, q);
+        const bool act = b != kNoBucket;
+        const uint32_t pos = wave_counter_add(cursor, b, act, true);
+        if (act) {
+            meta[pos] = make_uint2((uint32_t)ku | ((uint32_t)ou << 16), (uint32_t)q);
+            perm[pos] = (uint32_t)r;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void hy_chunks_kernel(int64_t nb, uint32_t R,
+                                                        const uint32_t *__restrict__ hist,
+                                                        const uint32_t *__restrict__ bstart,
+                                                        const uint32_t *__restrict__ cstart,
+                                                        Chunk *__restrict__ chunks) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = hist[b], s = bstart[b], k0 = cstart[b];
+        for (uint32_t k = 0; k * R < c; ++k)
+            chunks[k0 + k] = Chunk{s + k * R, min(R, c - k * R), (uint32_t)b, 0u};
+    }
+}
+
+// The plan's tap table as FP32, phase-major (entry o S + i = caller's entry
+// o + 1 + i beta), and the largest |tap| (non-negative floats order like
+// their bits).
+template <typename TapT>
+__global__ __launch_bounds__(256) void hy_taps_kernel(int32_t beta, int32_t S,
+                                                      const TapT *__restrict__ src,
+                                                      float *__restrict__ dst,
+                                                      float *__restrict__ tmax) {
+    float m = 0.0f;
+    for (int e = threadIdx.x; e < beta * S; e += blockDim.x) {
+        const int o = e / S, i = e % S;
+        const float t = TapTraits<TapT>::real(src, (int64_t)o + 1 + (int64_t)i * beta);
+        dst[e] = t;
+        m = fmaxf(m, fabsf(t));
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int *>(tmax), __float_as_uint(m));
+}
+
+__global__ void hy_fill_kernel(uint32_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__device__ inline int32_t hy_round(float x) {
+    int32_t r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// The Hybrid Gridding Step for the chunks of a plan (see the file comment).
+__global__ __launch_bounds__(kHyThreads) void hy_grid_kernel(
+    HyGeom g, const uint2 *__restrict__ meta, const uint32_t *__restrict__ perm,
+    const float *__restrict__ taps, const float *__restrict__ tmaxp,
+    const Chunk *__restrict__ chunks, const int64_t *__restrict__ counters,
+    const float *__restrict__ vis, float *__restrict__ grid) {
+    extern __shared__ int32_t region[];   // [kHyTV][RW][8]
+    __shared__ float s_part[kHyWaves];
+    __shared__ int s_bad[kHyWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane & 7;               // component: polarisation c / 2, part c % 2
+    const int i0 = lane >> 3;             // tap of the lane (plus multiples of 8)
+    const int S = g.S, npol = g.npol;
+    const int RW = kHyTU + S - 1;
+    const int words = kHyTV * RW * 8;
+    const bool comp_on = c < 2 * npol;
+    const float tmax = *tmaxp;
+    const uint32_t nchunks = (uint32_t)counters[2];
+    for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
+        const Chunk ch = chunks[ci];
+        const int tu0 = (int)(ch.bucket % (uint32_t)g.ntu) * kHyTU;
+        const int tv0 = (int)(ch.bucket / (uint32_t)g.ntu) * kHyTV;
+        // bound of the chunk's partial sums
+        float part = 0.0f;
+        bool bad = false;
+        for (uint32_t r = ch.start + threadIdx.x; r < ch.start + ch.len; r += kHyThreads) {
+            const float *v = vis + (size_t)perm[r] * 2 * npol;
+            float m = 0.0f;
+            for (int k = 0; k < 2 * npol; ++k) {
+                const float x = v[k];
+                bad = bad || !isfinite(x);
+                m = fmaxf(m, fabsf(x));
+            }
+            part += m;
+        }
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        const bool wbad = __any(bad);
+        if (lane == 0) {
+            s_part[wave] = part;
+            s_bad[wave] = wbad ? 1 : 0;
+        }
+        for (int k = threadIdx.x; k < words; k += kHyThreads) region[k] = 0;
+        __syncthreads();
+        float bound = 0.0f;
+        int anybad = 0;
+        for (int w = 0; w < kHyWaves; ++w) {
+            bound += s_part[w];
+            anybad |= s_bad[w];
+        }
+        bound = 2.0f * tmax * bound * 1.0001f + 1e-30f;
+        const bool use_lds = !anybad && isfinite(bound);
+        int scale = 0;
+        if (use_lds) {
+            int e = 0;
+            frexpf(bound, &e);
+            scale = max(-120, min(120, 30 - e));
+        }
+        const float fs = ldexpf(1.0f, scale);
+
+        // records of the chunk, the waves taking every fourth one
+        for (uint32_t r = ch.start + wave; r < ch.start + ch.len; r += kHyWaves) {
+            const uint2 m = meta[r];
+            const uint32_t src = perm[r];
+            const int ku = (int)(m.x & 0xffffu), ou = (int)(m.x >> 16), q = (int)m.y;
+            const float x = comp_on ? vis[(size_t)src * 2 * npol + c] * fs : 0.0f;
+            for (int i = i0; i < S; i += 8) {
+                const float val = taps[ou * S + i] * x;
+                if (!comp_on) continue;
+                if (use_lds) {
+                    atomicAdd(&region[((q - tv0) * RW + (ku + i - tu0)) * 8 + c], hy_round(val));
+                } else {
+                    float *dst = grid + ((((size_t)(c >> 1) * g.rows + q) * g.nu + ku + i) * 2 +
+                                         (c & 1));
+                    unsafeAtomicAdd(dst, val);
+                }
+            }
+        }
+        __syncthreads();
+        if (use_lds) {
+            // word k = ((row RW + col) 8 + comp)
+            for (int k = threadIdx.x; k < words; k += kHyThreads) {
+                const int32_t qv = region[k];
+                if (qv == 0) continue;
+                const int comp = k & 7, cell = k >> 3;
+                const int row = cell / RW, col = cell - row * RW;
+                if ((comp >> 1) >= npol || tv0 + row >= g.rows || tu0 + col >= g.nu) continue;
+                float *dst = grid + ((((size_t)(comp >> 1) * g.rows + tv0 + row) * g.nu + tu0 +
+                                      col) * 2 + (comp & 1));
+                unsafeAtomicAdd(dst, ldexpf((float)qv, -scale));
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Column pruner: out[pol][j][col] = sum_{s, a} c(alpha (s - SZ/2) + a)
+// in[pol][(alpha (j - SZ/2 + s) + a) mod M][col], c(d) = ztab[d + alpha SZ/2].
+// A thread takes one column and J consecutive outputs; input block b (rows
+// alpha b .. alpha b + alpha - 1) feeds outputs b - SZ/2 + 1 .. b + SZ/2;
+// output j lives in ring slot (j - j0 + SZ - 1) mod SZ, which makes every
+// slot index a compile-time constant of the unrolled loop, and is complete
+// (written and cleared) once block j + SZ/2 - 1 has been added.
+template <int SZ>
+__global__ __launch_bounds__(256) void prune_columns_kernel(const float2 *__restrict__ in,
+                                                            float2 *__restrict__ out,
+                                                            int64_t M, int32_t ncols,
+                                                            int32_t alpha, int32_t J,
+                                                            const float *__restrict__ ztab) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pol = blockIdx.z;
+    const int64_t Mb = M / alpha;                      // output rows
+    const int64_t j0 = (int64_t)blockIdx.y * J;
+    const int64_t j_end = min<int64_t>(j0 + J, Mb);
+    if (col >= ncols || j0 >= Mb) return;
+    const float2 *src = in + (size_t)pol * M * ncols + col;
+    float2 *dst = out + (size_t)pol * Mb * ncols + col;
+    const int half = alpha * SZ / 2;
+    float2 acc[SZ];
+#pragma unroll
+    for (int k = 0; k < SZ; ++k) acc[k] = make_float2(0.0f, 0.0f);
+    const int64_t b0 = j0 - SZ / 2;
+    const int64_t b1 = j_end - 1 + SZ / 2;             // last block
+    for (int64_t bb = b0; bb <= b1; bb += SZ) {
+#pragma unroll
+        for (int t = 0; t < SZ; ++t) {
+            const int64_t b = bb + t;
+            if (b > b1) break;
+            int64_t bw = b % Mb;                       // circular convolution
+            if (bw < 0) bw += Mb;
+            const float2 *row = src + (size_t)(bw * alpha) * ncols;
+            for (int a = 0; a < alpha; ++a) {
+                const float2 x = row[(size_t)a * ncols];
+                // block b feeds output j = b + SZ/2 - s with coefficient
+                // c(alpha (s - SZ/2) + a), slot (t - s - 1) mod SZ
+#pragma unroll
+                for (int s = 0; s < SZ; ++s) {
+                    const float w = ztab[alpha * (s - SZ / 2) + a + half];
+                    float2 &y = acc[((t - s - 1) % SZ + SZ) % SZ];
+                    y.x = fmaf(w, x.x, y.x);
+                    y.y = fmaf(w, x.y, y.y);
+                }
+            }
+            const int64_t jc = b - SZ / 2 + 1;         // complete output
+            if (jc >= j0 && jc < j_end) dst[(size_t)jc * ncols] = acc[t];
+            acc[t] = make_float2(0.0f, 0.0f);
+        }
+    }
+}
+
+template <int SZ>
+void launch_prune(const float2 *in, float2 *out, int npol, int64_t M, int ncols, int alpha,
+                  const float *ztab, hipStream_t stream) {
+    constexpr int J = 64;
+    const int64_t Mb = M / alpha;
+    const dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)((Mb + J - 1) / J),
+                    (unsigned)npol);
+    hipLaunchKernelGGL(prune_columns_kernel<SZ>, grid, dim3(256), 0, stream, in, out, M, ncols,
+                       alpha, J, ztab);
+}
+
+int grid_blocks_hy(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(8192, b));
+}
+
+}  // namespace
+}  // namespace mg
+
+struct mg_hybrid_plan {
+    mg::HyGeom g{};
+    mg_dtype tap_dtype = MG_F32;
+    int64_t nrec = 0, nb = 0, max_chunks = 0;
+    uint32_t R = 1024;
+    // arena arrays
+    float *taps = nullptr;
+    float *tmax = nullptr;
+    uint2 *meta = nullptr;
+    uint32_t *perm = nullptr;
+    mg::Chunk *chunks = nullptr;
+    uint32_t *hist = nullptr, *bstart = nullptr, *cursor = nullptr, *cstart = nullptr;
+    int64_t *counters = nullptr;
+    size_t bytes = 0;
+    void *owned = nullptr;
+    hipStream_t create_stream = nullptr;
+};
+
+namespace mg {
+namespace {
+
+mg_status hy_check(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec, const void *uvw,
+                   mg_dtype uvw_dtype) {
+    if (!g || !k) return set_error(MG_EINVAL, "null descriptor");
+    if (k->kind != MG_KERNEL_SEPARABLE)
+        return set_error(MG_EINVAL, "hybrid gridding takes a separable kernel");
+    if (g->nu < 1 || g->nv < 1 || g->nu > kMaxN || g->nv > kMaxN)
+        return set_error(MG_EINVAL, "grid size must be in [1, 65535]");
+    if (g->npol < 1 || g->npol > 4) return set_error(MG_EINVAL, "npol must be in 1..4");
+    if (g->beta < 1 || g->beta > kMaxBeta) return set_error(MG_EINVAL, "beta must be in 1..256");
+    if (!std::isfinite(g->scale_u) || !std::isfinite(g->scale_v))
+        return set_error(MG_EINVAL, "scale must be finite");
+    if (nrec < 0 || nrec > 0x7ffffffeLL) return set_error(MG_EINVAL, "nrec must be in [0, 2^31-2]");
+    if (nrec > 0 && !uvw) return set_error(MG_EINVAL, "null uvw");
+    if (uvw_dtype != MG_F32 && uvw_dtype != MG_F64)
+        return set_error(MG_EINVAL, "uvw dtype must be MG_F32 or MG_F64");
+    if (k->tap_dtype != MG_F32 && k->tap_dtype != MG_F16 && k->tap_dtype != MG_BF16)
+        return set_error(MG_EINVAL, "tap dtype must be MG_F32, MG_F16 or MG_BF16");
+    if (!k->taps) return set_error(MG_EINVAL, "null taps");
+    if (k->support < 1 || k->support > kHyMaxS)
+        return set_error(MG_EINVAL, "hybrid support must be in 1..32");
+    if (((int64_t)g->beta * k->support) % 2) return set_error(MG_EINVAL, "beta * support must be even");
+    if (k->ntaps < (int64_t)g->beta * k->support + 1)
+        return set_error(MG_EINVAL, "separable table shorter than beta*S+1");
+    return MG_OK;
+}
+
+void hy_prepare(mg_hybrid_plan &P, const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec) {
+    P.g.nu = g->nu;
+    P.g.nv = g->nv;
+    P.g.npol = g->npol;
+    P.g.beta = g->beta;
+    P.g.S = k->support;
+    P.g.rows = g->beta * g->nv;
+    P.g.ntu = (g->nu + kHyTU - 1) / kHyTU;
+    P.g.ntv = (P.g.rows + kHyTV - 1) / kHyTV;
+    P.g.scale_u = g->scale_u;
+    P.g.scale_v = g->scale_v;
+    P.tap_dtype = k->tap_dtype;
+    P.nrec = nrec;
+    P.nb = (int64_t)P.g.ntu * P.g.ntv;
+    P.R = (uint32_t)std::max<int64_t>(64, std::min<int64_t>(1024, nrec / 4096));
+    P.max_chunks = P.nb + nrec / P.R + 1;
+}
+
+template <typename F>
+size_t hy_walk(const mg_hybrid_plan &P, F &&place) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += arena_round(bytes);
+        return at;
+    };
+    const size_t n = (size_t)P.nrec + kRecPad;
+    place(0, take(sizeof(float) * (size_t)P.g.beta * P.g.S));
+    place(1, take(sizeof(float)));
+    place(2, take(sizeof(uint2) * n));
+    place(3, take(sizeof(uint32_t) * n));
+    place(4, take(sizeof(Chunk) * (size_t)P.max_chunks));
+    place(5, take(sizeof(uint32_t) * (size_t)P.nb));
+    place(6, take(sizeof(uint32_t) * (size_t)P.nb));
+    place(7, take(sizeof(uint32_t) * (size_t)P.nb));
+    place(8, take(sizeof(uint32_t) * (size_t)(P.nb + 1)));
+    place(9, take(sizeof(int64_t) * 4));
+    return off;
+}
+
+void hy_carve(mg_hybrid_plan &P, void *arena) {
+    char *base = static_cast<char *>(arena);
+    P.bytes = hy_walk(P, [&](int what, size_t at) {
+        void *p = base + at;
+        switch (what) {
+        case 0: P.taps = static_cast<float *>(p); break;
+        case 1: P.tmax = static_cast<float *>(p); break;
+        case 2: P.meta = static_cast<uint2 *>(p); break;
+        case 3: P.perm = static_cast<uint32_t *>(p); break;
+        case 4: P.chunks = static_cast<Chunk *>(p); break;
+        case 5: P.hist = static_cast<uint32_t *>(p); break;
+        case 6: P.bstart = static_cast<uint32_t *>(p); break;
+        case 7: P.cursor = static_cast<uint32_t *>(p); break;
+        case 8: P.cstart = static_cast<uint32_t *>(p); break;
+        default: P.counters = static_cast<int64_t *>(p); break;
+        }
+    });
+}
+
+mg_status hy_build(mg_hybrid_plan &P, const mg_kernel_desc *k, const void *uvw, mg_dtype dt,
+                   hipStream_t stream) {
+    hipLaunchKernelGGL(hy_fill_kernel, dim3(1), dim3(64), 0, stream,
+                       reinterpret_cast<uint32_t *>(P.counters), (int64_t)8);
+    hipLaunchKernelGGL(hy_fill_kernel, dim3(1), dim3(64), 0, stream,
+                       reinterpret_cast<uint32_t *>(P.tmax), (int64_t)1);
+    hipLaunchKernelGGL(hy_fill_kernel, dim3(grid_blocks_hy(P.nb)), dim3(256), 0, stream, P.hist,
+                       P.nb);
+    if (P.tap_dtype == MG_F16)
+        hipLaunchKernelGGL(hy_taps_kernel<__half>, dim3(1), dim3(256), 0, stream, P.g.beta, P.g.S,
+                           (const __half *)k->taps, P.taps, P.tmax);
+    else if (P.tap_dtype == MG_BF16)
+        hipLaunchKernelGGL(hy_taps_kernel<__hip_bfloat16>, dim3(1), dim3(256), 0, stream, P.g.beta,
+                           P.g.S, (const __hip_bfloat16 *)k->taps, P.taps, P.tmax);
+    else
+        hipLaunchKernelGGL(hy_taps_kernel<float>, dim3(1), dim3(256), 0, stream, P.g.beta, P.g.S,
+                           (const float *)k->taps, P.taps, P.tmax);
+    const int gb = grid_blocks_hy(P.nrec);
+    if (P.nrec > 0) {
+        if (dt == MG_F32)
+            hipLaunchKernelGGL(hy_count_kernel<float>, dim3(gb), dim3(256), 0, stream, P.g, P.nrec,
+                               (const float *)uvw, P.hist, P.counters);
+        else
+            hipLaunchKernelGGL(hy_count_kernel<double>, dim3(gb), dim3(256), 0, stream, P.g, P.nrec,
+                               (const double *)uvw, P.hist, P.counters);
+    }
+    hipLaunchKernelGGL(hy_scan_kernel, dim3(1), dim3(256), 0, stream, P.hist, P.nb, P.R, P.bstart,
+                       P.cursor, P.cstart, P.counters);
+    if (P.nrec > 0) {
+        if (dt == MG_F32)
+            hipLaunchKernelGGL(hy_scatter_kernel<float>, dim3(gb), dim3(256), 0, stream, P.g,
+                               P.nrec, (const float *)uvw, P.cursor, P.meta, P.perm);
+        else
+            hipLaunchKernelGGL(hy_scatter_kernel<double>, dim3(gb), dim3(256), 0, stream, P.g,
+                               P.nrec, (const double *)uvw, P.cursor, P.meta, P.perm);
+    }
+    hipLaunchKernelGGL(hy_chunks_kernel, dim3(grid_blocks_hy(P.nb)), dim3(256), 0, stream, P.nb,
+                       P.R, P.hist, P.bstart, P.cstart, P.chunks);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("hybrid plan kernels: ") + hipGetErrorString(e));
+    return MG_OK;
+}
+
+mg_status hy_grid(const mg_hybrid_plan &P, const void *vis, void *grid, hipStream_t stream) {
+    if (P.nrec == 0) return MG_OK;
+    const size_t lds = sizeof(int32_t) * kHyTV * (kHyTU + P.g.S - 1) * 8;
+    const int groups = resident_groups((const void *)hy_grid_kernel, kHyThreads, lds);
+    hipLaunchKernelGGL(hy_grid_kernel, dim3(groups), dim3(kHyThreads), lds, stream, P.g, P.meta,
+                       P.perm, P.taps, P.tmax, P.chunks, P.counters, (const float *)vis,
+                       (float *)grid);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("hybrid grid kernel: ") + hipGetErrorString(e));
+    return MG_OK;
+}
+
+__global__ void hy_add_count_kernel(const int64_t *src, int64_t *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst += *src;
+}
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+mg_status mg_hybrid_plan_workspace_size(const mg_grid_desc *g, const mg_kernel_desc *k,
+                                        int64_t nrec, size_t *bytes) {
+    if (!bytes) return set_error(MG_EINVAL, "null bytes output");
+    *bytes = 0;
+    mg_status s = hy_check(g, k, nrec, reinterpret_cast<const void *>(1), MG_F32);
+    if (s != MG_OK) return s;
+    mg_hybrid_plan P;
+    hy_prepare(P, g, k, nrec);
+    *bytes = hy_walk(P, [](int, size_t) {});
+    return MG_OK;
+}
+
+mg_status mg_hybrid_plan_create(mg_hybrid_plan **plan, const mg_grid_desc *g,
+                                const mg_kernel_desc *k, int64_t nrec, const void *uvw,
+                                mg_dtype uvw_dtype, void *workspace, hipStream_t stream) {
+    if (!plan) return set_error(MG_EINVAL, "null plan output");
+    *plan = nullptr;
+    mg_status s = hy_check(g, k, nrec, uvw, uvw_dtype);
+    if (s != MG_OK) return s;
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kArenaAlign) != 0)
+        return set_error(MG_EINVAL, "workspace must be 256-byte aligned");
+    mg_hybrid_plan *p = new (std::nothrow) mg_hybrid_plan;
+    if (!p) return set_error(MG_ENOMEM, "host allocation failed");
+    hy_prepare(*p, g, k, nrec);
+    p->create_stream = stream;
+    void *arena = workspace;
+    if (!arena) {
+        const size_t bytes = hy_walk(*p, [](int, size_t) {});
+        const hipError_t e = scratch_alloc(&arena, bytes, stream);
+        if (e != hipSuccess) {
+            delete p;
+            return set_error(MG_ENOMEM, std::string("hybrid plan allocation: ") + hipGetErrorString(e));
+        }
+        p->owned = arena;
+    }
+    hy_carve(*p, arena);
+    s = hy_build(*p, k, uvw, uvw_dtype, stream);
+    if (s != MG_OK) {
+        if (p->owned) scratch_free(p->owned, stream);
+        delete p;
+        return s;
+    }
+    *plan = p;
+    return MG_OK;
+}
+
+mg_status mg_hybrid_plan_grid(const mg_hybrid_plan *plan, const void *vis, void *grid,
+                              hipStream_t stream) {
+    if (!plan) return set_error(MG_EINVAL, "null plan");
+    if (plan->nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
+    if (!grid) return set_error(MG_EINVAL, "null grid");
+    return hy_grid(*plan, vis, grid, stream);
+}
+
+mg_status mg_hybrid_plan_nskipped(const mg_hybrid_plan *plan, int64_t *nskipped) {
+    if (!plan || !nskipped) return set_error(MG_EINVAL, "null argument");
+    if (hipStreamSynchronize(plan->create_stream) != hipSuccess)
+        return set_error(MG_EDEVICE, "stream sync failed");
+    int64_t v = 0;
+    if (hipMemcpy(&v, plan->counters, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+        return set_error(MG_EDEVICE, "counter copy failed");
+    *nskipped = v;
+    return MG_OK;
+}
+
+mg_status mg_hybrid_plan_destroy(mg_hybrid_plan *plan) {
+    if (!plan) return MG_OK;
+    // a library-owned arena is released on the creating stream: calls on
+    // other streams must have been ordered before the destroy by the caller
+    if (plan->owned) scratch_free(plan->owned, plan->create_stream);
+    delete plan;
+    return MG_OK;
+}
+
+mg_status mg_hybrid_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                         const void *uvw, mg_dtype uvw_dtype, const void *vis, void *grid,
+                         int64_t *d_nskipped, hipStream_t stream) {
+    mg_status s = hy_check(g, k, nrec, uvw, uvw_dtype);
+    if (s != MG_OK) return s;
+    if (nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
+    if (!grid) return set_error(MG_EINVAL, "null grid");
+    mg_hybrid_plan P;
+    hy_prepare(P, g, k, nrec);
+    void *arena = nullptr;
+    const hipError_t e = scratch_alloc(&arena, hy_walk(P, [](int, size_t) {}), stream);
+    if (e != hipSuccess) return set_error(MG_ENOMEM, std::string("hybrid scratch: ") + hipGetErrorString(e));
+    hy_carve(P, arena);
+    s = hy_build(P, k, uvw, uvw_dtype, stream);
+    if (s == MG_OK) s = hy_grid(P, vis, grid, stream);
+    if (s == MG_OK && d_nskipped)
+        hipLaunchKernelGGL(hy_add_count_kernel, dim3(1), dim3(64), 0, stream, P.counters, d_nskipped);
+    scratch_free(arena, stream);
+    return s;
+}
+
+mg_status mg_prune_columns(int32_t npol, int64_t nrows, int32_t ncols, int32_t alpha,
+                           int32_t support_z, const float *ztaps, const void *in, void *out,
+                           hipStream_t stream) {
+    if (npol < 1 || npol > 4 || nrows < 1 || ncols < 1 || alpha < 1)
+        return set_error(MG_EINVAL, "bad pruning geometry");
+    if (nrows % alpha) return set_error(MG_EINVAL, "nrows must be a multiple of alpha");
+    if (support_z < 2 || support_z > 16 || support_z % 2)
+        return set_error(MG_EINVAL, "pruning support must be even, 2..16");
+    if (nrows / alpha > 0x7fffffffLL) return set_error(MG_EINVAL, "too many output rows");
+    if (!ztaps || !in || !out) return set_error(MG_EINVAL, "null pointer");
+    const float2 *src = static_cast<const float2 *>(in);
+    float2 *dst = static_cast<float2 *>(out);
+    switch (support_z) {
+    case 2: launch_prune<2>(src, dst, npol, nrows, ncols, alpha, ztaps, stream); break;
+    case 4: launch_prune<4>(src, dst, npol, nrows, ncols, alpha, ztaps, stream); break;
+    case 6: launch_prune<6>(src, dst, npol, nrows, ncols, alpha, ztaps, stream); break;
+    case 8: launch_prune<8>(src, dst, npol, nrows, ncols, alpha, ztaps, stream); break;
+    case 10: launch_prune<10>(src, dst, npol, nrows, ncols, alpha, ztaps, stream); break;
+    case 12: launch_prune<12>(src, dst, npol, nrows, ncols, alpha, ztaps, stream); break;
+    case 14: launch_prune<14>(src, dst, npol, nrows, ncols, alpha, ztaps, stream); break;
+    default: launch_prune<16>(src, dst, npol, nrows, ncols, alpha, ztaps, stream); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("column pruner: ") + hipGetErrorString(e));
+    return MG_OK;
+}
+
+}  // extern "C"

@@ -19,44 +19,6 @@ namespace {
 
 constexpr uint32_t kInvalidBucket = 0xffffffffu;
 
-// Wave-aggregated counter increment.  Lanes with `active` add 1 to
-// counters[key]; lanes sharing a key are served by one atomic issued by the
-// lowest of them.  Returns, for each active lane, the counter's value before
-// the group's add plus the lane's rank within its group (so the lanes of a
-// group get consecutive values in lane order).  Records arrive in
-// measurement-set order, where consecutive channels of a baseline share a
-// bucket, so one atomic per group replaces up to 64 serialised ones.  The
-// groups are formed first; then every group's leader issues its atomic in
-// one vector instruction, so the wave waits for one atomic round trip.
-__device__ inline uint32_t wave_counter_add(uint32_t *counters, uint32_t key, bool active,
-                                            bool need_value) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint64_t pending = __ballot(active);
-    int leader = lane;      // this lane's group leader
-    uint32_t rank = 0;      // position within the group
-    uint32_t count = 0;     // group size (leaders)
-    while (pending) {
-        const int l = __builtin_ctzll(pending);
-        const uint32_t lkey = __builtin_amdgcn_readlane(key, l);
-        const uint64_t group = __ballot(active && key == lkey) & pending;
-        if ((group >> lane) & 1ull) {
-            leader = l;
-            rank = (uint32_t)__popcll(group & lt);
-        }
-        if (lane == l) count = (uint32_t)__popcll(group);
-        pending &= ~group;
-    }
-    uint32_t base = 0;
-    if (active && leader == lane) {
-        if (need_value) base = atomicAdd(&counters[key], count);
-        else atomicAdd(&counters[key], count);
-    }
-    if (!need_value) return 0;
-    base = (uint32_t)__shfl((int)base, leader, 64);
-    return base + rank;
-}
-
 // ---------------------------------------------------------------------------
 // index rule -> bucket histogram and skipped count; the scatter evaluates the
 // rule again (reading uvw costs what storing and re-reading its results
