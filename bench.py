@@ -95,9 +95,12 @@ class Timer:
         return [ev[i].elapsed_time(ev[i + 1]) for i in range(n)]
 
     def protocol(self, fn, trials=3, calls=20):
-        """The thesis's protocol: `trials` runs of `calls` back-to-back calls;
-        the minimum trial mean, plus the mean and median of all calls (ms)."""
+        """The thesis's protocol: `trials` runs of `calls` back-to-back calls
+        after one untimed call (which also builds any library plan, e.g. the
+        FFT's); the minimum trial mean, plus the mean and median of all calls
+        (ms)."""
         import numpy as np
+        fn()
         per = [self.calls(fn, calls) for _ in range(trials)]
         flat = np.array([x for t in per for x in t])
         return {"mean_ms": float(flat.mean()), "min_trial_mean_ms": float(min(np.mean(t) for t in per)),
@@ -180,6 +183,73 @@ def separable_leg(api, W, torch, dev, stream, wl, name, autograd=False):
     log(f"[bench] {name}: plan grid {pg['mean_ms']:.3f} ms, degrid {pd['mean_ms']:.3f} ms, "
         f"one-shot {one['mean_ms']:.3f} ms, plan build {out['plan_build_ms']:.3f} ms")
     del grid, vis, uvw, vout
+    torch.cuda.empty_cache()
+    return out
+
+
+def hybrid_leg(api, W, torch, dev, stream, wl, name):
+    """Hybrid Gridding against convolutional gridding on the same records
+    (a separable workload): the Gridder Advantage (the ratio of the two
+    gridders' rates, Section 3.5.5, records per second over a prepared plan),
+    the column pruner (alpha = beta/2, S_z = 2S, the kernel's own taps as the
+    pruning kernel) against the HBM roof, the Column Pruning Gain (inverse
+    FFT of the hybrid grid over pruner plus inverse FFT of the pruned grid,
+    Section 3.5.6; FFTs by the platform library through torch) and the
+    Minimum Record Density D(co, hy) (Section 8.2.1) from these timings."""
+    import numpy as np
+    timer = Timer(torch, stream)
+    spec = api.GridSpec(wl.n, wl.n, 4, wl.beta, wl.scale, wl.scale)
+    bank = api.KernelBank("separable", torch.from_numpy(wl.taps.astype(np.float32)).to(dev),
+                          support=wl.support)
+    uvw = torch.from_numpy(wl.uvw).to(dev)
+    vis = W.vis_normal_torch(wl.nrec, 4, W.SEED_VIS, dev)
+    n, beta, S = wl.n, wl.beta, wl.support
+    alpha = beta // 2
+    conv = torch.zeros(4, n, n, dtype=torch.complex64, device=dev)
+    hyg = torch.zeros(4, beta * n, n, dtype=torch.complex64, device=dev)
+    cp = api.Plan(spec, bank, uvw)
+    hp = api.HybridPlan(spec, bank, uvw)
+    nval = wl.nrec - hp.nskipped
+    tc = timer.protocol(lambda: cp.grid(vis, out=conv))
+    th = timer.protocol(lambda: hp.grid(vis, out=hyg))
+    z = torch.from_numpy(wl.taps.astype(np.float32)).to(dev)
+    pruned = torch.empty(4, 2 * n, n, dtype=torch.complex64, device=dev)
+    tp = timer.protocol(lambda: api.prune_columns(hyg, alpha, z, 2 * S, out=pruned))
+    f_inp = timer.protocol(lambda: torch.fft.ifft2(hyg), trials=3, calls=5)
+    f_out1 = timer.protocol(lambda: torch.fft.ifft2(pruned), trials=3, calls=5)
+    f_conv = timer.protocol(lambda: torch.fft.ifft2(conv), trials=3, calls=5)
+    cp.close()
+    hp.close()
+    rate_co = nval / (tc["mean_ms"] * 1e-3)
+    rate_hy = nval / (th["mean_ms"] * 1e-3)
+    fin_co = f_conv["mean_ms"] * 1e-3
+    fin_hy = (tp["mean_ms"] + f_out1["mean_ms"]) * 1e-3
+    denom = 1.0 / rate_co - 1.0 / rate_hy
+    r_eq = (fin_hy - fin_co) / denom if denom > 0 else None
+    nn = beta * n
+    prune_bytes = 4 * 8 * (beta * n * n + 2 * n * n)
+    out = {"workload": name, "records": wl.nrec, "valid_records": nval,
+           "grid": [4, n, n], "hybrid_grid": [4, beta * n, n], "pruned_grid": [4, 2 * n, n],
+           "kernel": f"separable {S}x{S}, beta {beta}; hybrid S x 1; pruning alpha {alpha}, "
+                     f"S_z {2 * S}",
+           "conv_plan_grid": tc, "hybrid_plan_grid": th,
+           "conv_records_per_s": rate_co, "hybrid_records_per_s": rate_hy,
+           "gridder_advantage": rate_hy / rate_co,
+           "column_pruner": tp,
+           "column_pruner_hbm_frac": prune_bytes / (HBM_PEAK_GBS * 1e9) / (tp["mean_ms"] * 1e-3),
+           "ifft_hybrid_grid": f_inp, "ifft_pruned_grid": f_out1, "ifft_conv_grid": f_conv,
+           "column_pruning_gain": f_inp["mean_ms"] / (tp["mean_ms"] + f_out1["mean_ms"]),
+           "column_pruner_footprint": tp["mean_ms"] / (tp["mean_ms"] + f_out1["mean_ms"]),
+           "min_record_density_co_hy_pct": (100.0 * r_eq / (nn * nn)) if r_eq is not None else None,
+           "min_record_density_note": "D(co, hy) = R / N_nn^2 with fin(co) = IFFT of the "
+                                      "N x N grid, fin(hy) = pruner + IFFT of the N x 2N grid "
+                                      "(correction excluded from both)"}
+    log(f"[bench] hybrid {name}: conv grid {tc['mean_ms']:.3f} ms, hybrid grid "
+        f"{th['mean_ms']:.3f} ms (advantage {out['gridder_advantage']:.2f}x), pruner "
+        f"{tp['mean_ms']:.3f} ms, IFFT inp/out1/conv {f_inp['mean_ms']:.3f}/"
+        f"{f_out1['mean_ms']:.3f}/{f_conv['mean_ms']:.3f} ms, pruning gain "
+        f"{out['column_pruning_gain']:.2f}")
+    del conv, hyg, pruned, vis, uvw
     torch.cuda.empty_cache()
     return out
 
@@ -337,7 +407,7 @@ def main():
                     help="skip the small, autograd and precision workload legs")
     ap.add_argument("--only-headline", action="store_true",
                     help="headline step and dominant unit only (profiling runs)")
-    ap.add_argument("--only-leg", choices=["small", "autograd", "precision", "serving"],
+    ap.add_argument("--only-leg", choices=["small", "autograd", "precision", "serving", "hybrid"],
                     help="run one of the other workloads alone (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -367,6 +437,11 @@ def main():
                               "autograd-sep7-2048-10M", autograd=True)
         elif args.only_leg == "precision":
             r = precision_leg(api, W, torch, dev, stream, steps=args.steps)
+        elif args.only_leg == "hybrid":
+            r = {"small": hybrid_leg(api, W, torch, dev, stream, W.config_small(),
+                                     "small-sep7-1024-100800"),
+                 "autograd": hybrid_leg(api, W, torch, dev, stream, W.config_autograd(),
+                                        "autograd-sep7-2048-10M")}
         else:
             r = serving_leg(dev, args.serving_jobs)
         print(json.dumps(r), flush=True)
@@ -527,6 +602,11 @@ def main():
         result["autograd"] = separable_leg(api, W, torch, dev, stream, W.config_autograd(),
                                            "autograd-sep7-2048-10M", autograd=True)
         result["precision_full"] = precision_leg(api, W, torch, dev, stream, steps=3)
+        result["hybrid"] = {
+            "small": hybrid_leg(api, W, torch, dev, stream, W.config_small(),
+                                "small-sep7-1024-100800"),
+            "autograd": hybrid_leg(api, W, torch, dev, stream, W.config_autograd(),
+                                   "autograd-sep7-2048-10M")}
 
     if args.serving_jobs > 0:
         result["serving"] = serving_leg(dev, args.serving_jobs)

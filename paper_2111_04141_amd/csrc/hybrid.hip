@@ -38,6 +38,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,7 +50,7 @@ namespace mg {
 namespace {
 
 constexpr int kHyTU = 32;          // tile columns (u cells)
-constexpr int kHyTV = 32;          // tile rows (rows of the oversampled v axis)
+constexpr int kHyTV = 16;          // tile rows (rows of the oversampled v axis)
 constexpr int kHyThreads = 256;
 constexpr int kHyMaxS = 32;
 constexpr int kHyWaves = kHyThreads / kWave;
@@ -239,54 +240,136 @@ __device__ inline int32_t hy_round(float x) {
 }
 
 // The Hybrid Gridding Step for the chunks of a plan (see the file comment).
+// A chunk's records (metadata and visibilities, gathered through the
+// permutation with all loads in flight) are staged in LDS first, which also
+// gives the chunk's bound; the waves then take every fourth record, four at
+// a time, reading everything they need from LDS.
+constexpr int kHyMaxR = 512;      // records per chunk (plan R is at most this)
+constexpr int kHyUnroll = 4;
+
+template <int NI>   // taps per lane: ceil(S / 8)
 __global__ __launch_bounds__(kHyThreads) void hy_grid_kernel(
     HyGeom g, const uint2 *__restrict__ meta, const uint32_t *__restrict__ perm,
     const float *__restrict__ taps, const float *__restrict__ tmaxp,
     const Chunk *__restrict__ chunks, const int64_t *__restrict__ counters,
     const float *__restrict__ vis, float *__restrict__ grid) {
-    extern __shared__ int32_t region[];   // [kHyTV][RW][8]
+    // LDS: staged metadata [R], visibilities [R][8], tap table [beta S],
+    // then the fixed-point region [kHyTV][RW][8]
+    extern __shared__ int32_t lds[];
+    uint2 *st_meta = reinterpret_cast<uint2 *>(lds);
+    float *st_vis = reinterpret_cast<float *>(lds + 2 * kHyMaxR);
+    float *st_tab = st_vis + 8 * kHyMaxR;
+    const int S = g.S, npol = g.npol;
+    const int ntab = (g.beta * S + 3) & ~3;
+    int32_t *region = reinterpret_cast<int32_t *>(st_tab + ntab);
     __shared__ float s_part[kHyWaves];
     __shared__ int s_bad[kHyWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = lane & 7;               // component: polarisation c / 2, part c % 2
     const int i0 = lane >> 3;             // tap of the lane (plus multiples of 8)
-    const int S = g.S, npol = g.npol;
     const int RW = kHyTU + S - 1;
-    const int words = kHyTV * RW * 8;
     const bool comp_on = c < 2 * npol;
     const float tmax = *tmaxp;
+    __shared__ int s_box[kHyWaves][4];
+    for (int k = threadIdx.x; k < g.beta * S; k += kHyThreads) st_tab[k] = taps[k];
     const uint32_t nchunks = (uint32_t)counters[2];
+    constexpr int kPer = kHyMaxR / kHyThreads;
+    // the permutation entries and metadata of a chunk's records are loaded
+    // one chunk ahead (they arrive while the previous chunk is gridded)
+    uint32_t src[kPer];
+    uint2 mrec[kPer];
+    auto prefetch = [&](uint32_t cj) {
+        Chunk cn{0u, 0u, 0u, 0u};
+        if (cj < nchunks) cn = chunks[cj];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int j = threadIdx.x + k * kHyThreads;
+            const bool on = j < (int)cn.len;
+            src[k] = on ? perm[cn.start + j] : 0u;
+            mrec[k] = on ? meta[cn.start + j] : make_uint2(0u, 0u);
+        }
+    };
+    prefetch(blockIdx.x);
     for (uint32_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
         const Chunk ch = chunks[ci];
         const int tu0 = (int)(ch.bucket % (uint32_t)g.ntu) * kHyTU;
         const int tv0 = (int)(ch.bucket / (uint32_t)g.ntu) * kHyTV;
-        // bound of the chunk's partial sums
+        const int len = (int)ch.len;
+        // stage the chunk's visibilities (all loads in flight), its bound and
+        // the bounding box of its footprints
         float part = 0.0f;
         bool bad = false;
-        for (uint32_t r = ch.start + threadIdx.x; r < ch.start + ch.len; r += kHyThreads) {
-            const float *v = vis + (size_t)perm[r] * 2 * npol;
+        int rmin = kHyTV, rmax = -1, cmin = kHyTU, cmax = -1;
+        float4 va[kPer], vb[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int j = threadIdx.x + k * kHyThreads;
+            va[k] = vb[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (j >= len) continue;
+            const float *v = vis + (size_t)src[k] * 2 * npol;
+            if (npol == 4) {
+                va[k] = reinterpret_cast<const float4 *>(v)[0];
+                vb[k] = reinterpret_cast<const float4 *>(v)[1];
+            } else {
+                float xs[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) xs[q] = (q < 2 * npol) ? v[q] : 0.0f;
+                va[k] = make_float4(xs[0], xs[1], xs[2], xs[3]);
+                vb[k] = make_float4(xs[4], xs[5], xs[6], xs[7]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int j = threadIdx.x + k * kHyThreads;
+            if (j >= len) continue;
+            st_meta[j] = mrec[k];
+            const int row = (int)mrec[k].y - tv0, col = (int)(mrec[k].x & 0xffffu) - tu0;
+            rmin = min(rmin, row);
+            rmax = max(rmax, row);
+            cmin = min(cmin, col);
+            cmax = max(cmax, col);
+            const float xs[8] = {va[k].x, va[k].y, va[k].z, va[k].w,
+                                 vb[k].x, vb[k].y, vb[k].z, vb[k].w};
             float m = 0.0f;
-            for (int k = 0; k < 2 * npol; ++k) {
-                const float x = v[k];
-                bad = bad || !isfinite(x);
-                m = fmaxf(m, fabsf(x));
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                bad = bad || !isfinite(xs[q]);
+                m = fmaxf(m, fabsf(xs[q]));
             }
             part += m;
         }
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        prefetch(ci + gridDim.x);
+        for (int off = 32; off > 0; off >>= 1) {
+            part += __shfl_xor(part, off);
+            rmin = min(rmin, __shfl_xor(rmin, off));
+            rmax = max(rmax, __shfl_xor(rmax, off));
+            cmin = min(cmin, __shfl_xor(cmin, off));
+            cmax = max(cmax, __shfl_xor(cmax, off));
+        }
         const bool wbad = __any(bad);
         if (lane == 0) {
             s_part[wave] = part;
             s_bad[wave] = wbad ? 1 : 0;
+            s_box[wave][0] = rmin;
+            s_box[wave][1] = rmax;
+            s_box[wave][2] = cmin;
+            s_box[wave][3] = cmax;
         }
-        for (int k = threadIdx.x; k < words; k += kHyThreads) region[k] = 0;
         __syncthreads();
         float bound = 0.0f;
         int anybad = 0;
+        rmin = kHyTV, rmax = -1, cmin = kHyTU, cmax = -1;
         for (int w = 0; w < kHyWaves; ++w) {
             bound += s_part[w];
             anybad |= s_bad[w];
+            rmin = min(rmin, s_box[w][0]);
+            rmax = max(rmax, s_box[w][1]);
+            cmin = min(cmin, s_box[w][2]);
+            cmax = max(cmax, s_box[w][3]);
         }
+        // the touched part of the region: rows rmin..rmax, columns
+        // cmin..cmax + S - 1 (a chunk has at least one record)
+        const int bw = cmax + S - cmin, bh = rmax - rmin + 1;
         bound = 2.0f * tmax * bound * 1.0001f + 1e-30f;
         const bool use_lds = !anybad && isfinite(bound);
         int scale = 0;
@@ -294,42 +377,89 @@ __global__ __launch_bounds__(kHyThreads) void hy_grid_kernel(
             int e = 0;
             frexpf(bound, &e);
             scale = max(-120, min(120, 30 - e));
+            for (int k = threadIdx.x; k < bh * bw * 8; k += kHyThreads) {
+                const int cell = k >> 3, r = cell / bw, cc = cell - r * bw;
+                region[((rmin + r) * RW + cmin + cc) * 8 + (k & 7)] = 0;
+            }
         }
-        const float fs = ldexpf(1.0f, scale);
+        // the staged visibilities carry the chunk's scale (exact powers of
+        // two), so the accumulators are in units of the quantum
+        {
+            const float fs = ldexpf(1.0f, scale);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int j = threadIdx.x + k * kHyThreads;
+                if (j >= len) continue;
+                reinterpret_cast<float4 *>(st_vis)[2 * j] =
+                    make_float4(va[k].x * fs, va[k].y * fs, va[k].z * fs, va[k].w * fs);
+                reinterpret_cast<float4 *>(st_vis)[2 * j + 1] =
+                    make_float4(vb[k].x * fs, vb[k].y * fs, vb[k].z * fs, vb[k].w * fs);
+            }
+        }
+        __syncthreads();
 
-        // records of the chunk, the waves taking every fourth one
-        for (uint32_t r = ch.start + wave; r < ch.start + ch.len; r += kHyWaves) {
-            const uint2 m = meta[r];
-            const uint32_t src = perm[r];
-            const int ku = (int)(m.x & 0xffffu), ou = (int)(m.x >> 16), q = (int)m.y;
-            const float x = comp_on ? vis[(size_t)src * 2 * npol + c] * fs : 0.0f;
-            for (int i = i0; i < S; i += 8) {
-                const float val = taps[ou * S + i] * x;
-                if (!comp_on) continue;
-                if (use_lds) {
-                    atomicAdd(&region[((q - tv0) * RW + (ku + i - tu0)) * 8 + c], hy_round(val));
-                } else {
-                    float *dst = grid + ((((size_t)(c >> 1) * g.rows + q) * g.nu + ku + i) * 2 +
-                                         (c & 1));
-                    unsafeAtomicAdd(dst, val);
+        // the waves take every fourth record, kHyUnroll at a time; lane
+        // (tap i0 + 8 t, component c) adds one word per record
+        auto records = [&](auto fixed_t) {
+            constexpr bool FIXED = decltype(fixed_t)::value;
+            for (int j0 = wave; j0 < len; j0 += kHyWaves * kHyUnroll) {
+                uint32_t mx[kHyUnroll], mq[kHyUnroll];
+                float x[kHyUnroll];
+#pragma unroll
+                for (int u = 0; u < kHyUnroll; ++u) {
+                    const int j = min(j0 + u * kHyWaves, len - 1);
+                    const uint2 m = st_meta[j];
+                    mx[u] = uniform_u32(m.x);
+                    mq[u] = uniform_u32(m.y);
+                    x[u] = st_vis[8 * j + c];
+                }
+#pragma unroll
+                for (int u = 0; u < kHyUnroll; ++u) {
+                    if (j0 + u * kHyWaves >= len) break;
+                    const int ku = (int)(mx[u] & 0xffffu), ou = (int)(mx[u] >> 16);
+                    const int q = (int)mq[u];
+#pragma unroll
+                    for (int t = 0; t < NI; ++t) {
+                        const int i = i0 + 8 * t;
+                        if (i >= S) continue;
+                        const float val = st_tab[ou * S + i] * x[u];
+                        if (!comp_on) continue;
+                        if constexpr (FIXED) {
+                            atomicAdd(&region[((q - tv0) * RW + (ku - tu0) + i) * 8 + c],
+                                      hy_round(val));
+                        } else {
+                            float *dst = grid + ((((size_t)(c >> 1) * g.rows + q) * g.nu + ku + i) *
+                                                     2 + (c & 1));
+                            unsafeAtomicAdd(dst, val);
+                        }
+                    }
+                }
+            }
+        };
+        if (use_lds)
+            records(std::true_type{});
+        else
+            records(std::false_type{});
+        __syncthreads();
+        if (use_lds) {
+            // polarisation by polarisation over the touched box, consecutive
+            // threads on consecutive words of a grid row (re, im of
+            // consecutive cells)
+            const int per_pol = bh * bw * 2;
+            for (int pol = 0; pol < npol; ++pol) {
+                for (int k = threadIdx.x; k < per_pol; k += kHyThreads) {
+                    const int part = k & 1, bc = k >> 1;
+                    const int r = bc / bw;
+                    const int row = rmin + r, col = cmin + (bc - r * bw);
+                    const int32_t qv = region[(row * RW + col) * 8 + 2 * pol + part];
+                    if (qv == 0 || tv0 + row >= g.rows || tu0 + col >= g.nu) continue;
+                    float *dst = grid + ((((size_t)pol * g.rows + tv0 + row) * g.nu + tu0 + col) *
+                                             2 + part);
+                    unsafeAtomicAdd(dst, ldexpf((float)qv, -scale));
                 }
             }
         }
         __syncthreads();
-        if (use_lds) {
-            // word k = ((row RW + col) 8 + comp)
-            for (int k = threadIdx.x; k < words; k += kHyThreads) {
-                const int32_t qv = region[k];
-                if (qv == 0) continue;
-                const int comp = k & 7, cell = k >> 3;
-                const int row = cell / RW, col = cell - row * RW;
-                if ((comp >> 1) >= npol || tv0 + row >= g.rows || tu0 + col >= g.nu) continue;
-                float *dst = grid + ((((size_t)(comp >> 1) * g.rows + tv0 + row) * g.nu + tu0 +
-                                      col) * 2 + (comp & 1));
-                unsafeAtomicAdd(dst, ldexpf((float)qv, -scale));
-            }
-            __syncthreads();
-        }
     }
 }
 
@@ -467,7 +597,7 @@ void hy_prepare(mg_hybrid_plan &P, const mg_grid_desc *g, const mg_kernel_desc *
     P.tap_dtype = k->tap_dtype;
     P.nrec = nrec;
     P.nb = (int64_t)P.g.ntu * P.g.ntv;
-    P.R = (uint32_t)std::max<int64_t>(64, std::min<int64_t>(1024, nrec / 4096));
+    P.R = (uint32_t)std::max<int64_t>(64, std::min<int64_t>(kHyMaxR, nrec / 4096));
     P.max_chunks = P.nb + nrec / P.R + 1;
 }
 
@@ -557,11 +687,20 @@ mg_status hy_build(mg_hybrid_plan &P, const mg_kernel_desc *k, const void *uvw, 
 
 mg_status hy_grid(const mg_hybrid_plan &P, const void *vis, void *grid, hipStream_t stream) {
     if (P.nrec == 0) return MG_OK;
-    const size_t lds = sizeof(int32_t) * kHyTV * (kHyTU + P.g.S - 1) * 8;
-    const int groups = resident_groups((const void *)hy_grid_kernel, kHyThreads, lds);
-    hipLaunchKernelGGL(hy_grid_kernel, dim3(groups), dim3(kHyThreads), lds, stream, P.g, P.meta,
-                       P.perm, P.taps, P.tmax, P.chunks, P.counters, (const float *)vis,
-                       (float *)grid);
+    const size_t lds = sizeof(int32_t) * (size_t)(2 * kHyMaxR + 8 * kHyMaxR +
+                                                  ((P.g.beta * P.g.S + 3) & ~3) +
+                                                  kHyTV * (kHyTU + P.g.S - 1) * 8);
+    auto launch = [&](auto kern) {
+        const int groups = resident_groups((const void *)kern, kHyThreads, lds);
+        hipLaunchKernelGGL(kern, dim3(groups), dim3(kHyThreads), lds, stream, P.g, P.meta,
+                           P.perm, P.taps, P.tmax, P.chunks, P.counters, (const float *)vis,
+                           (float *)grid);
+    };
+    const int ni = (P.g.S + 7) / 8;
+    if (ni == 1) launch(hy_grid_kernel<1>);
+    else if (ni == 2) launch(hy_grid_kernel<2>);
+    else if (ni == 3) launch(hy_grid_kernel<3>);
+    else launch(hy_grid_kernel<4>);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("hybrid grid kernel: ") + hipGetErrorString(e));
     return MG_OK;
