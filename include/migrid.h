@@ -283,6 +283,45 @@ mg_status mg_prune_columns(int32_t npol, int64_t nrows, int32_t ncols, int32_t a
                            int32_t support_z, const float *ztaps, const void *in, void *out,
                            hipStream_t stream);
 
+/* ---- imaging chain: origin shift, inverse FFT, Correction Step ----
+ *
+ * The IFFT and Correction Steps of the studied algorithms (Section 2.4.5;
+ * Section 2.4.4 for Hybrid Gridding).  For centred grids of even sizes the
+ * image is the unnormalised inverse transform with e^{+j2pi}, centred,
+ *   I[y][x] = sum_k G[kv][ku] exp(+j2pi((ku - nx/2)(x - nx/2)/nx
+ *                                        + (kv - ny/2)(y - ny/2)/ny)),
+ * times separable correctors corr_x[x] corr_y[y]. */
+
+/* Corrector vector (device, n floats): h(l) = 1 / ((1/phases) sum_e T[e]
+ * cos(2pi ((e - E/2)/beta) l) s(l)), l = (i - n/2)/n, where T is a
+ * symmetric table of E + 1 = table_len values (DEVICE, FP32) whose entry e
+ * lies (e - E/2)/beta cells from the centre, and s(l) = sinc(l/beta) (the
+ * nearest-pixel snap onto the beta-oversampled grid) if nn_sinc, else 1.
+ * Convolutional gridding (corrector h_co): T the kernel's beta S + 1 taps,
+ * phases = beta.  Pruned hybrid v axis (h_pr): T the pruning kernel's
+ * alpha Sz + 1 taps, phases = alpha.  Computed in FP64. */
+mg_status mg_corrector(int32_t n, int32_t beta, int32_t table_len, int32_t phases,
+                       int32_t nn_sinc, const float *table, float *corr, hipStream_t stream);
+
+typedef struct mg_imager mg_imager;
+
+/* An imager for [npol][ny][nx] grids (nx, ny even): holds a batched C2C FFT
+ * plan of the platform library (which allocates its own work area).  One
+ * stream at a time per imager. */
+mg_status mg_imager_create(mg_imager **im, int32_t npol, int32_t nx, int32_t ny);
+
+/* image = rows [y0, y0 + out_ny) of the centred inverse transform of grid
+ * ([npol][ny][nx] complex64, device, read only), times corr_x[x] (nx
+ * floats) and corr_y[y - y0] (out_ny floats), into image ([npol][out_ny][nx]
+ * complex64).  work: [npol][ny][nx] complex64 scratch (may equal image when
+ * y0 = 0 and out_ny = ny).  A pruned hybrid grid (2 nv rows, nu columns)
+ * takes y0 = nv/2, out_ny = nv (the central half of its doubled field). */
+mg_status mg_imager_exec(mg_imager *im, const void *grid, void *work, void *image,
+                         const float *corr_x, const float *corr_y, int32_t y0, int32_t out_ny,
+                         hipStream_t stream);
+
+mg_status mg_imager_destroy(mg_imager *im);
+
 /* ---- serving: continuous batching of gridding jobs ----
  *
  * A server owns a pool of HIP streams (default priority) on one device and a

@@ -95,6 +95,10 @@ def lib():
     L.mg_hybrid_plan_destroy.argtypes = [vp]
     L.mg_hybrid_grid.argtypes = [gd, kd, i64, vp, i32, vp, vp, vp, vp]
     L.mg_prune_columns.argtypes = [i32, i64, i32, i32, i32, vp, vp, vp, vp]
+    L.mg_corrector.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp]
+    L.mg_imager_create.argtypes = [C.POINTER(vp), i32, i32, i32]
+    L.mg_imager_exec.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp]
+    L.mg_imager_destroy.argtypes = [vp]
     L.mg_grid_static_capacity.argtypes = []
     L.mg_grid_static_capacity.restype = C.c_size_t
     L.mg_server_create.argtypes = [C.POINTER(vp), C.c_size_t, i32, i32, i32]
@@ -108,7 +112,8 @@ def lib():
               "mg_plan_nskipped", "mg_plan_bytes", "mg_plan_destroy", "mg_grid", "mg_degrid",
               "mg_grid_static", "mg_hybrid_plan_workspace_size", "mg_hybrid_plan_create",
               "mg_hybrid_plan_grid", "mg_hybrid_plan_nskipped", "mg_hybrid_plan_destroy",
-              "mg_hybrid_grid", "mg_prune_columns",
+              "mg_hybrid_grid", "mg_prune_columns", "mg_corrector", "mg_imager_create",
+              "mg_imager_exec", "mg_imager_destroy",
               "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait",
               "mg_server_get_stats", "mg_server_destroy"):
         getattr(L, f).restype = i32
@@ -554,3 +559,63 @@ def prune_columns(grid_in: torch.Tensor, alpha: int, ztaps: torch.Tensor, suppor
                                   grid_in.data_ptr(), out.data_ptr(),
                                   _stream_ptr(grid_in.device)), "mg_prune_columns")
     return out
+
+
+# ---------------------------------------------------------------------------
+# imaging chain
+# ---------------------------------------------------------------------------
+
+def corrector(n: int, beta: int, table: torch.Tensor, phases: int,
+              nn_sinc: bool = True) -> torch.Tensor:
+    """Corrector vector h(l), l = (i - n/2)/n (mg_corrector); table: FP32
+    device tensor of E + 1 symmetric values spaced 1/beta cells."""
+    if not table.is_cuda or table.dtype != torch.float32 or not table.is_contiguous():
+        raise ValueError("table must be a contiguous float32 device tensor")
+    out = torch.empty(n, dtype=torch.float32, device=table.device)
+    _check(lib().mg_corrector(int(n), int(beta), table.numel(), int(phases), int(nn_sinc),
+                              table.data_ptr(), out.data_ptr(), _stream_ptr(table.device)),
+           "mg_corrector")
+    return out
+
+
+class Imager:
+    """Origin shift + batched inverse FFT + separable correction of centred
+    [npol, ny, nx] grids (mg_imager_*)."""
+
+    def __init__(self, npol: int, nx: int, ny: int, device="cuda"):
+        self.npol, self.nx, self.ny = int(npol), int(nx), int(ny)
+        self.device = torch.device(device)
+        self._h = C.c_void_p()
+        _check(lib().mg_imager_create(C.byref(self._h), self.npol, self.nx, self.ny),
+               "mg_imager_create")
+        self.work = torch.empty(self.npol, self.ny, self.nx, dtype=torch.complex64,
+                                device=self.device)
+
+    def image(self, grid: torch.Tensor, corr_x: torch.Tensor, corr_y: torch.Tensor,
+              y0: int = 0, out_ny: Optional[int] = None,
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out_ny = self.ny if out_ny is None else int(out_ny)
+        if (grid.dtype != torch.complex64 or not grid.is_contiguous()
+                or tuple(grid.shape) != (self.npol, self.ny, self.nx)):
+            raise ValueError(f"grid must be complex64 [{self.npol}, {self.ny}, {self.nx}]")
+        if corr_x.numel() != self.nx or corr_y.numel() != out_ny:
+            raise ValueError("corrector lengths must be nx and out_ny")
+        if out is None:
+            out = torch.empty(self.npol, out_ny, self.nx, dtype=torch.complex64,
+                              device=self.device)
+        _check(lib().mg_imager_exec(self._h, grid.data_ptr(), self.work.data_ptr(),
+                                    out.data_ptr(), corr_x.data_ptr(), corr_y.data_ptr(),
+                                    int(y0), out_ny, _stream_ptr(self.device)),
+               "mg_imager_exec")
+        return out
+
+    def close(self):
+        if self._h:
+            lib().mg_imager_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
