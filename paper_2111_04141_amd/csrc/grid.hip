@@ -63,6 +63,7 @@ static_assert(2 * kBatch - 1 <= kRecPad, "record read-ahead runs past the paddin
 // also waits for the next batch's loads on every iteration.
 __device__ inline void wait_scalar_loads() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
+
 // Nearest integer (halves round up) in one instruction: the fixed-point
 // commit of an accumulator that is already in units of the quantum.
 __device__ inline int32_t round_to_fixed(float x) {
@@ -147,6 +148,15 @@ __device__ inline uint32_t next_chunk(uint32_t *queue, uint32_t *slot) {
 // multi-wave instances are held to four waves per SIMD: beyond 128 VGPRs the
 // eight-slot instance ran a third slower at three waves per SIMD).
 constexpr int window_waves(int team) { return team == 1 ? 4 : 8; }
+// Largest support of each window instance and its LDS region: 8 planes
+// (polarisations x re/im) of int32, each plane kWindowTile + S - 1 cells
+// square at most.  The plane stride is a compile-time constant, so the eight
+// commits of a slot address one base with immediate offsets.
+constexpr int kWindowTile = 16;
+constexpr int window_smax(int kmax) { return kmax == 1 ? 8 : kmax == 4 ? 16 : 32; }
+constexpr int window_plane(int kmax) {
+    return (kWindowTile + window_smax(kmax) - 1) * (kWindowTile + window_smax(kmax) - 1);
+}
 
 template <int KMAX, int TEAM, bool SEP, typename TapT>
 __global__ __launch_bounds__(kWave * window_waves(TEAM))
@@ -158,7 +168,8 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
     const int32_t *__restrict__ uinfo, uint32_t *__restrict__ queue, GridParams prm) {
     constexpr int NW = window_waves(TEAM);
     constexpr int NTEAMS = NW / TEAM;
-    extern __shared__ int32_t region[];   // [8][RH][RW]: (pol, re/im) planes
+    constexpr int PS = window_plane(KMAX);   // plane stride (cells)
+    extern __shared__ int32_t region[];   // [8][PS], plane q holding [RH][RW]
     __shared__ uint32_t s_next;
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);   // bytes per tap
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
@@ -207,7 +218,8 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
         const bool use_lds = (info & kUnitFixed) != 0;
         const int scale = unit_scale(info);
         if (use_lds) {
-            for (int i = threadIdx.x; i < 8 * plane_cells; i += NW * kWave) region[i] = 0;
+            for (int q = 0; q < 8; ++q)
+                for (int i = threadIdx.x; i < plane_cells; i += NW * kWave) region[q * PS + i] = 0;
             __syncthreads();
         }
         // adds a slot's sums to its cell (fixed point: rounded to the nearest
@@ -215,10 +227,11 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
         auto commit = [&](float (&sums)[8], uint32_t cell_uv) {
             const uint32_t cu_ = cell_uv & 0xffffu, cv_ = cell_uv >> 16;
             if (use_lds) {
-                int32_t *dst = &region[(int)(cv_ - cv0) * RW + (int)(cu_ - cu0)];
+                // row times width in the 24-bit multiplier (full rate)
+                int32_t *dst = &region[__umul24(cv_ - cv0, (uint32_t)RW) + (cu_ - cu0)];
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    atomicAdd(&dst[q * plane_cells], round_to_fixed(sums[q]));
+                    atomicAdd(&dst[q * PS], round_to_fixed(sums[q]));
             } else {
 #pragma unroll
                 for (int pol = 0; pol < 4; ++pol) {
@@ -255,8 +268,12 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
 #pragma unroll
                 for (int k = 0; k < KD; ++k) {
                     const int j = k * kWave + lane;
-                    const uint32_t sidx = (uint32_t)(member * q_ + j);
+                    uint32_t sidx = (uint32_t)(member * q_ + j);
                     if (j < q_ && sidx < (uint32_t)nslots) valid_bits |= 1u << k;
+                    // a spare lane mirrors a real slot: it follows the same
+                    // cells and reads the same (in-bounds) taps, and its sums
+                    // are never committed
+                    else sidx %= (uint32_t)nslots;
                     // slot (su, sv) owns the cells congruent to it mod S
                     const uint32_t sv = sidx / (uint32_t)S;
                     suv[k] = (sidx - sv * (uint32_t)S) | (sv << 16);
@@ -276,33 +293,30 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
                     if (kuv == prev_kuv) return;
                     prev_kuv = kuv;
                     const uint32_t ku = meta_ku(m), kv = meta_kv(m);
-                    uint32_t moved_bits = 0;
+                    const uint32_t kmu = ku % (uint32_t)S, kmv = kv % (uint32_t)S;
 #pragma unroll
                     for (int k = 0; k < KD; ++k) {
-                        const uint32_t d = cell[k] - kuv;   // a borrow only where du < 0
-                        if (max(d & 0xffffu, d >> 16) >= (uint32_t)S) moved_bits |= 1u << k;
-                    }
-                    moved_bits &= valid_bits;
-                    if (__ballot(moved_bits != 0) != 0) {
-                        const uint32_t kmu = ku % (uint32_t)S, kmv = kv % (uint32_t)S;
+                        // the slot's cell has left the footprint (a borrow
+                        // only where du < 0); the test runs on the exec mask
+                        const uint32_t d = cell[k] - kuv;
+                        if (max(d & 0xffffu, d >> 16) >= (uint32_t)S) {
+                            if (((valid_bits >> k) & 1u) && cell[k] != kNoCell)
+                                commit(acc[k], cell[k]);
 #pragma unroll
-                        for (int k = 0; k < KD; ++k) {
-                            if ((moved_bits >> k) & 1u) {
-                                if (cell[k] != kNoCell) commit(acc[k], cell[k]);
-#pragma unroll
-                                for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-                                int du = (int)(suv[k] & 0xffffu) - (int)kmu;
-                                int dv = (int)(suv[k] >> 16) - (int)kmv;
-                                du += (du < 0) ? S : 0;
-                                dv += (dv < 0) ? S : 0;
-                                const uint32_t nu_ = ku + (uint32_t)du, nv_ = kv + (uint32_t)dv;
-                                cell[k] = nu_ | (nv_ << 16);
-                                if constexpr (SEP) {
-                                    lo[k] = nu_ * su_step;
-                                    lov[k] = nv_ * sv_step;
-                                } else {
-                                    lo[k] = nv_ * sv_step + nu_ * su_step;
-                                }
+                            for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
+                            int du = (int)(suv[k] & 0xffffu) - (int)kmu;
+                            int dv = (int)(suv[k] >> 16) - (int)kmv;
+                            du += (du < 0) ? S : 0;
+                            dv += (dv < 0) ? S : 0;
+                            const uint32_t nu_ = ku + (uint32_t)du, nv_ = kv + (uint32_t)dv;
+                            cell[k] = nu_ | (nv_ << 16);
+                            // cells < 2^16 and steps < 2^10: the 24-bit
+                            // multiplier (full rate) is exact
+                            if constexpr (SEP) {
+                                lo[k] = __umul24(nu_, su_step);
+                                lov[k] = __umul24(nv_, sv_step);
+                            } else {
+                                lo[k] = __umul24(nv_, sv_step) + __umul24(nu_, su_step);
                             }
                         }
                     }
@@ -311,15 +325,6 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
                         rv = kv * sv_step;
                     } else {
                         ru = kv * sv_step + ku * su_step;
-                    }
-                    // lanes without a slot read the footprint's first tap: their
-                    // offset term follows the record's
-#pragma unroll
-                    for (int k = 0; k < KD; ++k) {
-                        if (!((valid_bits >> k) & 1u)) {
-                            lo[k] = ru;
-                            lov[k] = rv;
-                        }
                     }
                 };
 
@@ -437,8 +442,8 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
             const int step_u = kThreads % RW, step_v = kThreads / RW;
             const int ru0 = (int)threadIdx.x % RW, rv0 = (int)threadIdx.x / RW;
             for (int pol = 0; pol < npol; ++pol) {
-                const int32_t *qre = region + (2 * pol) * plane_cells;
-                const int32_t *qim = qre + plane_cells;
+                const int32_t *qre = region + (2 * pol) * PS;
+                const int32_t *qim = qre + PS;
                 float *gp = grid + 2 * (((int64_t)pol * prm.nv + cv0) * prm.nu + cu0);
                 int ru_ = ru0, rv_ = rv0;
                 for (int j = threadIdx.x; j < plane_cells; j += kThreads) {
@@ -875,15 +880,14 @@ inline int region_blocks(int T, int S) {
 template <bool SEP, typename TapT>
 hipError_t launch_class(int cls, const GridPtrs &a, const GridParams &prm, int smax, int tile,
                         hipStream_t stream) {
-    // LDS region of the window gridders: 8 words per cell of the largest
-    // region (tile plus halo)
-    const size_t lds = (cls <= 2) ? sizeof(int32_t) * 8 * (size_t)(tile + smax - 1) *
-                                        (size_t)(tile + smax - 1)
-                                  : 0;
+    // LDS region of the window gridders: 8 planes of the instance's fixed
+    // stride (tile plus the class's largest halo)
+    if (cls <= 2 && (tile != kWindowTile || smax > window_smax(cls == 0 ? 1 : cls == 1 ? 4 : 8)))
+        return hipErrorInvalidValue;
     switch (cls) {
-    case 0: launch_window<1, 1, SEP, TapT>(a, prm, lds, stream); break;
-    case 1: launch_window<4, 1, SEP, TapT>(a, prm, lds, stream); break;
-    case 2: launch_window<8, 2, SEP, TapT>(a, prm, lds, stream); break;
+    case 0: launch_window<1, 1, SEP, TapT>(a, prm, sizeof(int32_t) * 8 * window_plane(1), stream); break;
+    case 1: launch_window<4, 1, SEP, TapT>(a, prm, sizeof(int32_t) * 8 * window_plane(4), stream); break;
+    case 2: launch_window<8, 2, SEP, TapT>(a, prm, sizeof(int32_t) * 8 * window_plane(8), stream); break;
     default:
         if (region_blocks(tile, smax) > 7 * 16) return hipErrorInvalidValue;
         launch_block<7, 16, SEP, TapT>(a, prm, stream);
