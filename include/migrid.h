@@ -322,6 +322,40 @@ mg_status mg_imager_exec(mg_imager *im, const void *grid, void *work, void *imag
 
 mg_status mg_imager_destroy(mg_imager *im);
 
+/* ---- kernel generation: W-projection kernel bank ----
+ *
+ * Plane p of the bank tabulates the GCF convolved with the transform of the
+ * inverse W-term at w_p (Section 1.7.1, W-projection; the W-term g_w and
+ * gbar_w = 1 / g_w of Section 1.3):
+ *   K_p = F[ c(l) c(m) gbar_{w_p}(l, m) ],
+ *   gbar_w(l, m) = exp(+j2pi w (sqrt(1 - l^2 - m^2) - 1)),
+ * with c the image-domain taper of the separable GCF whose base_len =
+ * beta*S0 + 1 symmetric FP64 taps (DEVICE) put entry t at
+ * (t - beta*S0/2)/beta cells, and F the transform with exp(-j2pi(ul + vm)).
+ * Discretisation: M = 2 beta S_p points per axis at beta/M field units,
+ * physical direction cosine = field units x fov (the radians the uv grid's
+ * field spans, i.e. its cells-per-wavelength scale); plane p keeps the
+ * central beta S_p + 1 samples per axis, row (v offset) major: the layout
+ * the gridders take.  The bank is normalised so its largest |tap| is 1.  At
+ * w = 0 a plane is the outer product of the (zero-padded) base taps.
+ * Computed in FP64 (the platform library's Z2Z FFT) and stored as out_dtype
+ * (MG_F32: complex64; MG_F16 / MG_BF16: re, im pairs). */
+mg_status mg_wkernel_bank_size(int32_t nplanes, const int32_t *plane_support, int32_t beta,
+                               int64_t *bank_elems, size_t *workspace_bytes);
+
+/* plane_support, plane_w: HOST [nplanes]; bank: DEVICE, bank_elems taps;
+ * plane_offset: HOST output [nplanes], element offset of each plane;
+ * workspace: DEVICE, at least the size mg_wkernel_bank_size reports (FP64
+ * image grids and tapers), passed with its size.  Creates and destroys FFT
+ * plans of the platform library and returns once the bank is written (it
+ * synchronises `stream`).  Errors: MG_EINVAL (sizes out of range, beta*S
+ * odd or above 4096, a plane narrower than the base kernel, fov not
+ * positive, non-finite w, null pointers, workspace too small), MG_EDEVICE. */
+mg_status mg_wkernel_bank(int32_t nplanes, const int32_t *plane_support, const double *plane_w,
+                          int32_t beta, int32_t base_len, const double *base_taps, double fov,
+                          mg_dtype out_dtype, void *bank, int64_t *plane_offset, void *workspace,
+                          size_t workspace_bytes, hipStream_t stream);
+
 /* ---- serving: continuous batching of gridding jobs ----
  *
  * A server owns a pool of HIP streams (default priority) on one device and a

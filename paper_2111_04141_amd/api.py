@@ -99,6 +99,9 @@ def lib():
     L.mg_imager_create.argtypes = [C.POINTER(vp), i32, i32, i32]
     L.mg_imager_exec.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp]
     L.mg_imager_destroy.argtypes = [vp]
+    L.mg_wkernel_bank_size.argtypes = [i32, vp, i32, C.POINTER(i64), C.POINTER(C.c_size_t)]
+    L.mg_wkernel_bank.argtypes = [i32, vp, vp, i32, i32, vp, C.c_double, i32, vp, vp, vp,
+                                  C.c_size_t, vp]
     L.mg_grid_static_capacity.argtypes = []
     L.mg_grid_static_capacity.restype = C.c_size_t
     L.mg_server_create.argtypes = [C.POINTER(vp), C.c_size_t, i32, i32, i32]
@@ -113,7 +116,7 @@ def lib():
               "mg_grid_static", "mg_hybrid_plan_workspace_size", "mg_hybrid_plan_create",
               "mg_hybrid_plan_grid", "mg_hybrid_plan_nskipped", "mg_hybrid_plan_destroy",
               "mg_hybrid_grid", "mg_prune_columns", "mg_corrector", "mg_imager_create",
-              "mg_imager_exec", "mg_imager_destroy",
+              "mg_imager_exec", "mg_imager_destroy", "mg_wkernel_bank_size", "mg_wkernel_bank",
               "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait",
               "mg_server_get_stats", "mg_server_destroy"):
         getattr(L, f).restype = i32
@@ -619,3 +622,48 @@ class Imager:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# kernel generation
+# ---------------------------------------------------------------------------
+
+def wkernel_bank(plane_support: Sequence[int], plane_w: Sequence[float], beta: int,
+                 base_taps: torch.Tensor, fov: float, dtype: str = "f32"):
+    """W-projection kernel bank built on the device (mg_wkernel_bank).
+
+    base_taps: float64 device tensor of the separable GCF's beta*S0 + 1
+    taps; plane_support / plane_w: per-plane support and w (wavelengths);
+    fov: radians spanned by the grid's field.  Returns (taps, offsets):
+    taps a device tensor of the bank (complex64 for "f32", [n, 2] float16
+    or bfloat16 pairs for "f16" / "bf16"), offsets the planes' element
+    offsets (list), ready for KernelBank("wproj", ...)."""
+    if (not base_taps.is_cuda or base_taps.dtype != torch.float64
+            or not base_taps.is_contiguous() or base_taps.dim() != 1):
+        raise ValueError("base_taps must be a contiguous float64 device vector")
+    np_ = len(plane_support)
+    if len(plane_w) != np_:
+        raise ValueError("plane_support and plane_w must have the same length")
+    sup = (C.c_int32 * np_)(*[int(x) for x in plane_support])
+    ws = (C.c_double * np_)(*[float(x) for x in plane_w])
+    n = C.c_int64()
+    wb = C.c_size_t()
+    L = lib()
+    _check(L.mg_wkernel_bank_size(np_, sup, int(beta), C.byref(n), C.byref(wb)),
+           "mg_wkernel_bank_size")
+    dev = base_taps.device
+    if dtype == "f32":
+        bank = torch.empty(n.value, dtype=torch.complex64, device=dev)
+        code = MG_F32
+    elif dtype in ("f16", "bf16"):
+        bank = torch.empty(n.value, 2, dtype=torch.float16 if dtype == "f16" else torch.bfloat16,
+                           device=dev)
+        code = MG_F16 if dtype == "f16" else MG_BF16
+    else:
+        raise ValueError("dtype must be f32, f16 or bf16")
+    work = torch.empty(wb.value, dtype=torch.uint8, device=dev)
+    offs = (C.c_int64 * np_)()
+    _check(L.mg_wkernel_bank(np_, sup, ws, int(beta), base_taps.numel(), base_taps.data_ptr(),
+                             float(fov), code, bank.data_ptr(), offs, work.data_ptr(), wb.value,
+                             _stream_ptr(dev)), "mg_wkernel_bank")
+    return bank, [int(x) for x in offs]

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libmigrid.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.hip", "plan.hip", "grid.hip", "degrid.hip", "serve.hip", "hybrid.hip",
-           "imaging.hip"]
+           "imaging.hip", "wkernel.hip"]
 
 CFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
