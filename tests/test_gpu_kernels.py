@@ -10,8 +10,9 @@ the oracle (oracle/wkernel.py), and the column-pruning aliasing experiment
     device-built bank and imaged on the device, against the direct Fourier
     sum with the W-term;
   * the pruning experiment: device pruner + imager against the FP64 oracle
-    chain, and the measured aliasing of the prolate spheroidal and the
-    least-misfit pruning kernels in FP32."""
+    chain (RMS difference below 1e-5 of the input image's RMS, which the
+    folded rows of amplitude a dominate), and the measured aliasing of the
+    prolate spheroidal and the least-misfit pruning kernels in FP32."""
 import numpy as np
 import pytest
 
@@ -133,7 +134,9 @@ def test_pruning_aliasing_experiment_on_device(torch_cuda, api):
             want = (IM.inverse_transform(Pr[None])[0]
                     * IM.corrector(ny, alpha, T32, alpha, nn_sinc=False)[:, None])
             want = want[ny // 4: 3 * ny // 4]
-            par = H.rel_l2(got, want)
+            # FP32 rounding scales with the whole input (the folded rows
+            # carry amplitude a), not with the kept field
+            par = np.sqrt(np.mean(np.abs(got - want) ** 2)) / np.sqrt(np.mean(img ** 2))
             assert par < 1e-5, (name, a, par)
             d = np.abs(got - orig)
             rows.append((a, name, d[y < 0].max(), d[y >= 0].max(), ref_err))
