@@ -76,7 +76,18 @@ typedef enum {
 
 typedef enum { MG_F32 = 0, MG_F64 = 1, MG_F16 = 2, MG_BF16 = 3 } mg_dtype;
 
-typedef enum { MG_KERNEL_SEPARABLE = 0, MG_KERNEL_WPROJ = 1 } mg_kernel_kind;
+/* MG_KERNEL_WSTACK: W-stacking with the plain gridder (Section 1.7.1,
+ * correction of the W-term in the (l, m)-plane; the W-handling route the
+ * thesis names for its gridders, Section 9.1).  A separable kernel (support,
+ * taps as for MG_KERNEL_SEPARABLE) and L = nplanes layers of spacing
+ * dw = 1 / inv_dw centred on w_j = (j - (L-1)/2) dw: a record goes to layer
+ *   j = floor(w inv_dw + L/2) clamped to [0, L-1]   (FP64, no contraction)
+ * and is gridded onto that layer's own nu x nv grid (index rule, bounds and
+ * skips per layer).  The layers' grids are stacked along v: grid and degrid
+ * buffers are [npol][L][nv][nu] (the same memory as [npol][L nv][nu]), and
+ * L nv must be at most 65535.  mg_compute_indices reports k_lo_v in the
+ * stacked rows (j nv + k_lo_v) and plane -1.  Image with mg_wstack_imager_*. */
+typedef enum { MG_KERNEL_SEPARABLE = 0, MG_KERNEL_WPROJ = 1, MG_KERNEL_WSTACK = 2 } mg_kernel_kind;
 
 /* Grid geometry.  scale_* = cells per wavelength (= N x pixel size in rad,
  * the N*dl = 1 normalisation of Section 2.1.2).  nu, nv in [1, 65535]. */
@@ -93,10 +104,12 @@ typedef struct {
     mg_kernel_kind kind;
     mg_dtype tap_dtype;            /* MG_F32, MG_F16 or MG_BF16 */
     int32_t support;               /* separable: S (1..64) */
-    int32_t nplanes;               /* W-projection: number of planes (1..128) */
+    int32_t nplanes;               /* W-projection: number of planes (1..128);
+                                      W-stacking: number of layers (1..128) */
     const int32_t *plane_support;  /* W-projection: S_p per plane (1..64) */
     const int64_t *plane_offset;   /* W-projection: first complex tap of plane p */
-    double inv_dw;                 /* W-projection: 1 / plane spacing in w */
+    double inv_dw;                 /* W-projection: 1 / plane spacing in w;
+                                      W-stacking: 1 / layer spacing */
     const void *taps;              /* device: the table(s) */
     int64_t ntaps;                 /* elements in taps (real for separable,
                                       complex for W-projection, at most 2^30) */
@@ -321,6 +334,34 @@ mg_status mg_imager_exec(mg_imager *im, const void *grid, void *work, void *imag
                          hipStream_t stream);
 
 mg_status mg_imager_destroy(mg_imager *im);
+
+/* ---- W-stacking image ----
+ *
+ * The image of MG_KERNEL_WSTACK grids (Section 1.7.1, correction of the
+ * W-term in the (l, m)-plane): every layer's centred inverse transform (as
+ * mg_imager_exec), multiplied by the inverse W-term of its layer
+ *   gbar_{w_j}(l, m) = exp(+j2pi w_j (sqrt(1 - l^2 - m^2) - 1)),
+ *   w_j = (j - (L-1)/2) dw,  l = (x - nx/2)/nx fov_x,  m = (y - ny/2)/ny fov_y
+ * (fov = the radians the field spans, the grid's cells-per-wavelength
+ * scale), summed over the layers and multiplied by corr_x[x] corr_y[y].
+ * The screen phase is reduced in FP64, its sine and cosine taken in FP32. */
+typedef struct mg_wstack_imager mg_wstack_imager;
+
+/* An imager for [npol][layers][ny][nx] layer grids (nx, ny even): holds a
+ * batched C2C FFT plan of the platform library (which allocates its own
+ * work area).  One stream at a time per imager. */
+mg_status mg_wstack_imager_create(mg_wstack_imager **im, int32_t npol, int32_t layers,
+                                  int32_t nx, int32_t ny);
+
+/* image ([npol][ny][nx] complex64) from grids ([npol][layers][ny][nx]
+ * complex64, read only); work: scratch of the grids' size, distinct from
+ * image; corr_x: nx floats, corr_y: ny floats (device).  dw: the layer
+ * spacing (1 / inv_dw of the kernel descriptor). */
+mg_status mg_wstack_imager_exec(mg_wstack_imager *im, const void *grids, void *work, void *image,
+                                const float *corr_x, const float *corr_y, double fov_x,
+                                double fov_y, double dw, hipStream_t stream);
+
+mg_status mg_wstack_imager_destroy(mg_wstack_imager *im);
 
 /* ---- kernel generation: W-projection kernel bank ----
  *

@@ -21,7 +21,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "migrid.h")
 
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_EUNSUPPORTED, MG_EBUSY = 0, -1, -2, -3, -4, -5
 MG_F32, MG_F64, MG_F16, MG_BF16 = 0, 1, 2, 3
-MG_KERNEL_SEPARABLE, MG_KERNEL_WPROJ = 0, 1
+MG_KERNEL_SEPARABLE, MG_KERNEL_WPROJ, MG_KERNEL_WSTACK = 0, 1, 2
 
 _TORCH_TO_MG = {torch.float32: MG_F32, torch.float64: MG_F64, torch.float16: MG_F16,
                 torch.bfloat16: MG_BF16}
@@ -102,6 +102,10 @@ def lib():
     L.mg_wkernel_bank_size.argtypes = [i32, vp, i32, C.POINTER(i64), C.POINTER(C.c_size_t)]
     L.mg_wkernel_bank.argtypes = [i32, vp, vp, i32, i32, vp, C.c_double, i32, vp, vp, vp,
                                   C.c_size_t, vp]
+    L.mg_wstack_imager_create.argtypes = [C.POINTER(vp), i32, i32, i32, i32]
+    L.mg_wstack_imager_exec.argtypes = [vp, vp, vp, vp, vp, vp, C.c_double, C.c_double,
+                                        C.c_double, vp]
+    L.mg_wstack_imager_destroy.argtypes = [vp]
     L.mg_grid_static_capacity.argtypes = []
     L.mg_grid_static_capacity.restype = C.c_size_t
     L.mg_server_create.argtypes = [C.POINTER(vp), C.c_size_t, i32, i32, i32]
@@ -117,6 +121,7 @@ def lib():
               "mg_hybrid_plan_grid", "mg_hybrid_plan_nskipped", "mg_hybrid_plan_destroy",
               "mg_hybrid_grid", "mg_prune_columns", "mg_corrector", "mg_imager_create",
               "mg_imager_exec", "mg_imager_destroy", "mg_wkernel_bank_size", "mg_wkernel_bank",
+              "mg_wstack_imager_create", "mg_wstack_imager_exec", "mg_wstack_imager_destroy",
               "mg_server_create", "mg_server_submit", "mg_server_poll", "mg_server_wait",
               "mg_server_get_stats", "mg_server_destroy"):
         getattr(L, f).restype = i32
@@ -165,13 +170,15 @@ class KernelBank:
     separable: taps real [beta*S + 1] (float32 / float16 / bfloat16).
     wproj: taps complex, concatenated planes [sum (beta*S_p+1)^2]; given as a
     complex64 tensor or as a [..., 2] float16 / bfloat16 tensor.
+    wstack: W-stacking, separable taps as above plus `layers` layers of
+    spacing 1 / inv_dw; grids are [npol, layers, nv, nu].
     """
 
     def __init__(self, kind: str, taps: torch.Tensor, support: int = 0,
                  plane_support: Sequence[int] = (), plane_offset: Sequence[int] = (),
-                 inv_dw: float = 0.0):
-        if kind not in ("separable", "wproj"):
-            raise ValueError("kind must be 'separable' or 'wproj'")
+                 inv_dw: float = 0.0, layers: int = 0):
+        if kind not in ("separable", "wproj", "wstack"):
+            raise ValueError("kind must be 'separable', 'wproj' or 'wstack'")
         if not taps.is_cuda:
             raise ValueError("taps must be a device tensor")
         taps = taps.contiguous()
@@ -196,17 +203,21 @@ class KernelBank:
         self.plane_support = [int(s) for s in plane_support]
         self.plane_offset = [int(o) for o in plane_offset]
         self.inv_dw = float(inv_dw)
+        self.layers = int(layers) if kind == "wstack" else 0
+        if kind == "wstack" and self.layers < 1:
+            raise ValueError("wstack needs layers >= 1")
 
     @property
     def support_max(self) -> int:
-        return self.support if self.kind == "separable" else max(self.plane_support)
+        return self.support if self.kind != "wproj" else max(self.plane_support)
 
     def desc(self) -> KernelDesc:
         d = KernelDesc()
-        d.kind = MG_KERNEL_SEPARABLE if self.kind == "separable" else MG_KERNEL_WPROJ
+        d.kind = {"separable": MG_KERNEL_SEPARABLE, "wproj": MG_KERNEL_WPROJ,
+                  "wstack": MG_KERNEL_WSTACK}[self.kind]
         d.tap_dtype = self.tap_dtype
         d.support = self.support
-        d.nplanes = len(self.plane_support)
+        d.nplanes = self.layers if self.kind == "wstack" else len(self.plane_support)
         d.plane_support = C.cast(self._ps, C.POINTER(C.c_int32))
         d.plane_offset = C.cast(self._po, C.POINTER(C.c_int64))
         d.inv_dw = self.inv_dw
@@ -229,11 +240,19 @@ def _check_vis(vis: torch.Tensor, nrec: int, npol: int):
         raise ValueError(f"vis must be a contiguous complex64 [{nrec}, {npol}] device tensor")
 
 
-def _check_grid(g: torch.Tensor, spec: GridSpec):
+def grid_shape(spec: GridSpec, bank: Optional["KernelBank"] = None) -> tuple:
+    """Shape of the grid a call with this bank reads or writes: [npol, nv,
+    nu], or [npol, layers, nv, nu] for W-stacking."""
+    if bank is not None and bank.kind == "wstack":
+        return (spec.npol, bank.layers, spec.nv, spec.nu)
+    return (spec.npol, spec.nv, spec.nu)
+
+
+def _check_grid(g: torch.Tensor, spec: GridSpec, bank: Optional["KernelBank"] = None):
+    shape = grid_shape(spec, bank)
     if (not g.is_cuda or g.dtype != torch.complex64 or not g.is_contiguous()
-            or tuple(g.shape) != (spec.npol, spec.nv, spec.nu)):
-        raise ValueError(f"grid must be a contiguous complex64 "
-                         f"[{spec.npol}, {spec.nv}, {spec.nu}] device tensor")
+            or tuple(g.shape) != shape):
+        raise ValueError(f"grid must be a contiguous complex64 {list(shape)} device tensor")
 
 
 # ---------------------------------------------------------------------------
@@ -266,8 +285,8 @@ def grid(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, vis: torch.Tensor,
     n = uvw.shape[0]
     _check_vis(vis, n, spec.npol)
     if out is None:
-        out = torch.zeros(spec.npol, spec.nv, spec.nu, dtype=torch.complex64, device=uvw.device)
-    _check_grid(out, spec)
+        out = torch.zeros(grid_shape(spec, bank), dtype=torch.complex64, device=uvw.device)
+    _check_grid(out, spec, bank)
     gd, kd = spec.desc(), bank.desc()
     _check(lib().mg_grid(C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt, vis.data_ptr(),
                          out.data_ptr(), _ptr(nskipped), _stream_ptr(uvw.device)), "mg_grid")
@@ -283,8 +302,8 @@ def grid_static(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, vis: torch.
     n = uvw.shape[0]
     _check_vis(vis, n, spec.npol)
     if out is None:
-        out = torch.zeros(spec.npol, spec.nv, spec.nu, dtype=torch.complex64, device=uvw.device)
-    _check_grid(out, spec)
+        out = torch.zeros(grid_shape(spec, bank), dtype=torch.complex64, device=uvw.device)
+    _check_grid(out, spec, bank)
     gd, kd = spec.desc(), bank.desc()
     _check(lib().mg_grid_static(C.byref(gd), C.byref(kd), n, uvw.data_ptr(), dt, vis.data_ptr(),
                                 out.data_ptr(), _ptr(nskipped), _stream_ptr(uvw.device)),
@@ -302,7 +321,7 @@ def degrid(spec: GridSpec, bank: KernelBank, uvw: torch.Tensor, grid_in: torch.T
     """One-shot degridding: returns vis = G^H grid (skipped records get 0)."""
     dt = _check_uvw(uvw)
     n = uvw.shape[0]
-    _check_grid(grid_in, spec)
+    _check_grid(grid_in, spec, bank)
     if out is None:
         out = torch.empty(n, spec.npol, dtype=torch.complex64, device=uvw.device)
     _check_vis(out, n, spec.npol)
@@ -411,15 +430,15 @@ class Plan:
     def grid(self, vis: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         _check_vis(vis, self.nrec, self.spec.npol)
         if out is None:
-            out = torch.zeros(self.spec.npol, self.spec.nv, self.spec.nu, dtype=torch.complex64,
+            out = torch.zeros(grid_shape(self.spec, self.bank), dtype=torch.complex64,
                               device=self.device)
-        _check_grid(out, self.spec)
+        _check_grid(out, self.spec, self.bank)
         _check(lib().mg_plan_grid(self._h, vis.data_ptr(), out.data_ptr(),
                                   _stream_ptr(self.device)), "mg_plan_grid")
         return out
 
     def degrid(self, grid_in: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        _check_grid(grid_in, self.spec)
+        _check_grid(grid_in, self.spec, self.bank)
         if out is None:
             out = torch.empty(self.nrec, self.spec.npol, dtype=torch.complex64,
                               device=self.device)
@@ -667,3 +686,50 @@ def wkernel_bank(plane_support: Sequence[int], plane_w: Sequence[float], beta: i
                              float(fov), code, bank.data_ptr(), offs, work.data_ptr(), wb.value,
                              _stream_ptr(dev)), "mg_wkernel_bank")
     return bank, [int(x) for x in offs]
+
+
+# ---------------------------------------------------------------------------
+# W-stacking image
+# ---------------------------------------------------------------------------
+
+class WStackImager:
+    """Image of W-stacking layer grids [npol, layers, ny, nx]: per-layer
+    inverse FFT, inverse W-term screen of each layer, sum, separable
+    correction (mg_wstack_imager_*)."""
+
+    def __init__(self, npol: int, layers: int, nx: int, ny: int, device="cuda"):
+        self.npol, self.layers, self.nx, self.ny = int(npol), int(layers), int(nx), int(ny)
+        self.device = torch.device(device)
+        self._h = C.c_void_p()
+        _check(lib().mg_wstack_imager_create(C.byref(self._h), self.npol, self.layers, self.nx,
+                                             self.ny), "mg_wstack_imager_create")
+        self.work = torch.empty(self.npol, self.layers, self.ny, self.nx, dtype=torch.complex64,
+                                device=self.device)
+
+    def image(self, grids: torch.Tensor, corr_x: torch.Tensor, corr_y: torch.Tensor,
+              fov_x: float, fov_y: float, dw: float,
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        shape = (self.npol, self.layers, self.ny, self.nx)
+        if grids.dtype != torch.complex64 or not grids.is_contiguous() or tuple(grids.shape) != shape:
+            raise ValueError(f"grids must be complex64 {list(shape)}")
+        if corr_x.numel() != self.nx or corr_y.numel() != self.ny:
+            raise ValueError("corrector lengths must be nx and ny")
+        if out is None:
+            out = torch.empty(self.npol, self.ny, self.nx, dtype=torch.complex64,
+                              device=self.device)
+        _check(lib().mg_wstack_imager_exec(self._h, grids.data_ptr(), self.work.data_ptr(),
+                                           out.data_ptr(), corr_x.data_ptr(), corr_y.data_ptr(),
+                                           float(fov_x), float(fov_y), float(dw),
+                                           _stream_ptr(self.device)), "mg_wstack_imager_exec")
+        return out
+
+    def close(self):
+        if self._h:
+            lib().mg_wstack_imager_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -69,7 +69,15 @@ mg_status check_common(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t n
     if (k->tap_dtype != MG_F32 && k->tap_dtype != MG_F16 && k->tap_dtype != MG_BF16)
         return set_error(MG_EINVAL, "tap dtype must be MG_F32, MG_F16 or MG_BF16");
     if (!k->taps) return set_error(MG_EINVAL, "null taps");
-    if (k->kind == MG_KERNEL_SEPARABLE) {
+    if (k->kind == MG_KERNEL_SEPARABLE || k->kind == MG_KERNEL_WSTACK) {
+        if (k->kind == MG_KERNEL_WSTACK) {
+            if (k->nplanes < 1 || k->nplanes > kMaxPlanes)
+                return set_error(MG_EINVAL, "W-stacking layers must be in 1..128");
+            if ((int64_t)k->nplanes * g->nv > kMaxN)
+                return set_error(MG_EINVAL, "layers x nv must be at most 65535");
+            if (!std::isfinite(k->inv_dw) || k->inv_dw < 0)
+                return set_error(MG_EINVAL, "inv_dw must be finite and >= 0");
+        }
         if (k->support < 1 || k->support > kMaxSupport)
             return set_error(MG_EINVAL, "support must be in 1..64");
         if (((int64_t)g->beta * k->support) % 2)
@@ -123,6 +131,13 @@ DevGeom make_geom(const mg_grid_desc *g, const mg_kernel_desc *k) {
         d.support = k->support;
         d.plane_support[0] = k->support;
         d.plane_offset[0] = 0;
+        if (k->kind == MG_KERNEL_WSTACK) {
+            // the layers' grids stacked along v: one tall separable grid
+            d.layers = k->nplanes;
+            d.layer_nv = g->nv;
+            d.nv = k->nplanes * g->nv;
+            d.inv_dw = k->inv_dw;
+        }
     }
     return d;
 }
@@ -246,7 +261,8 @@ int resident_groups(const void *kernel, int threads, size_t lds) {
 mg_status plan_prepare(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc *k,
                        int64_t nrec) {
     P.geom = make_geom(g, k);
-    P.kind = k->kind;
+    // W-stacking grids like a separable kernel on the stacked layer grids
+    P.kind = k->kind == MG_KERNEL_WSTACK ? MG_KERNEL_SEPARABLE : k->kind;
     P.tap_dtype = k->tap_dtype;
     P.nrec = nrec;
     P.nplanes_eff = (k->kind == MG_KERNEL_WPROJ) ? k->nplanes : 1;
@@ -261,8 +277,8 @@ mg_status plan_prepare(PlanState &P, const mg_grid_desc *g, const mg_kernel_desc
         L.cls = support_class(L.S);
         L.T = tile_for_class(L.cls, g->npol, lds);
         L.log2T = ilog2(L.T);
-        L.ntu = (g->nu + L.T - 1) / L.T;
-        L.ntv = (g->nv + L.T - 1) / L.T;
+        L.ntu = (P.geom.nu + L.T - 1) / L.T;
+        L.ntv = (P.geom.nv + L.T - 1) / L.T;
         L.tmax = 0.0f;   // raised on the device by the tap layout
     }
     // the plan's tap table: planes one after another, phase-major

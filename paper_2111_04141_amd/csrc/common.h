@@ -28,6 +28,8 @@ struct DevGeom {
                                         // plan's table once a plan owns it)
     int64_t conj_base;                  // W-projection: element offset of the
                                         // conjugated copy of the bank
+    int32_t layers;                     // W-stacking: layer count (0 = none);
+    int32_t layer_nv;                   // rows of one layer (nv = layers x layer_nv)
 };
 
 // A plan keeps its own copy of the tap table in phase-major order: for each
@@ -107,6 +109,20 @@ __device__ inline RecIndex index_record(const DevGeom &g, T u_, T v_, T w_) {
         r.S = g.plane_support[p];
     }
     bool okU = index_axis(u, g.scale_u, g.nu, g.beta, r.S, &r.ku, &r.ou);
+    if (g.layers > 0) {
+        // W-stacking: layer j = floor(w inv_dw + L/2) clamped to [0, L-1]
+        // (centred on w_j = (j - (L-1)/2) dw); the record is placed on its
+        // layer's own grid, which occupies rows j layer_nv .. (j+1) layer_nv - 1
+        double a = w * g.inv_dw;
+        a = a + 0.5 * (double)g.layers;
+        const double fj = floor(a);
+        const int32_t j = fj <= 0.0 ? 0
+                          : (fj >= (double)(g.layers - 1) ? g.layers - 1 : (int32_t)fj);
+        bool okV = index_axis(v, g.scale_v, g.layer_nv, g.beta, r.S, &r.kv, &r.ov);
+        r.kv += j * g.layer_nv;
+        r.valid = (okU && okV) ? 1 : 0;
+        return r;
+    }
     bool okV = index_axis(v, g.scale_v, g.nv, g.beta, r.S, &r.kv, &r.ov);
     r.valid = (okU && okV) ? 1 : 0;
     return r;

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
+#include <cmath>
 #include <new>
 #include <string>
 
@@ -24,6 +25,11 @@
 struct mg_imager {
     hipfftHandle plan = 0;
     int32_t npol = 0, nx = 0, ny = 0;
+};
+
+struct mg_wstack_imager {
+    hipfftHandle plan = 0;
+    int32_t npol = 0, layers = 0, nx = 0, ny = 0;
 };
 
 namespace mg {
@@ -87,6 +93,46 @@ __global__ __launch_bounds__(256) void correct_out_kernel(const float2 *__restri
         v.x *= f;
         v.y *= f;
         image[k] = v;
+    }
+}
+
+// W-stacking: image[p][y][x] = (-1)^(x + y + nx/2 + ny/2) cx[x] cy[y]
+//   sum_j work[p][j][y][x] gbar_{w_j}(l_x, m_y),
+// gbar_w = exp(+j2pi w (sqrt(1 - l^2 - m^2) - 1)), w_j = (j - (L-1)/2) dw,
+// l_x = (x - nx/2)/nx fov_x, m_y = (y - ny/2)/ny fov_y.  n - 1 is formed as
+// -r^2 / (1 + sqrt(1 - r^2)) (no cancellation) and each phase, in cycles, is
+// reduced to (-1/2, 1/2] in FP64 before the FP32 sine and cosine.
+__global__ __launch_bounds__(256) void wstack_combine_kernel(
+    const float2 *__restrict__ work, float2 *__restrict__ image, int32_t nx, int32_t ny,
+    int32_t npol, int32_t layers, double dw, double fov_x, double fov_y,
+    const float *__restrict__ cx, const float *__restrict__ cy) {
+    const int64_t plane = (int64_t)ny * nx;
+    const int64_t total = (int64_t)npol * plane;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(k / plane);
+        const int64_t yx = k - (int64_t)p * plane;
+        const int y = (int)(yx / nx);
+        const int x = (int)(yx - (int64_t)y * nx);
+        const double l = (double)(x - nx / 2) / (double)nx * fov_x;
+        const double m = (double)(y - ny / 2) / (double)ny * fov_y;
+        const double r2 = l * l + m * m;
+        const double nm1 = r2 < 1.0 ? -r2 / (1.0 + sqrt(1.0 - r2)) : -1.0;
+        float sr = 0.0f, si = 0.0f;
+        const float2 *src = work + (int64_t)p * layers * plane + yx;
+        for (int j = 0; j < layers; ++j) {
+            const double wj = ((double)j - 0.5 * (double)(layers - 1)) * dw;
+            double cyc = wj * nm1;
+            cyc -= rint(cyc);
+            float sn, cs;
+            sincosf(6.283185307179586f * (float)cyc, &sn, &cs);
+            const float2 v = src[(int64_t)j * plane];
+            sr += v.x * cs - v.y * sn;
+            si += v.x * sn + v.y * cs;
+        }
+        float f = cx[x] * cy[y];
+        if ((x + y + nx / 2 + ny / 2) & 1) f = -f;
+        image[k] = make_float2(sr * f, si * f);
     }
 }
 
@@ -163,6 +209,64 @@ mg_status mg_imager_exec(mg_imager *im, const void *grid, void *work, void *imag
 }
 
 mg_status mg_imager_destroy(mg_imager *im) {
+    if (!im) return MG_OK;
+    if (im->plan) hipfftDestroy(im->plan);
+    delete im;
+    return MG_OK;
+}
+
+mg_status mg_wstack_imager_create(mg_wstack_imager **im, int32_t npol, int32_t layers,
+                                  int32_t nx, int32_t ny) {
+    if (!im) return set_error(MG_EINVAL, "null imager output");
+    *im = nullptr;
+    if (npol < 1 || npol > 4 || layers < 1 || layers > kMaxPlanes || nx < 2 || ny < 2 ||
+        (nx & 1) || (ny & 1))
+        return set_error(MG_EINVAL, "imager sizes must be even, npol 1..4, layers 1..128");
+    mg_wstack_imager *p = new (std::nothrow) mg_wstack_imager;
+    if (!p) return set_error(MG_ENOMEM, "host allocation failed");
+    p->npol = npol;
+    p->layers = layers;
+    p->nx = nx;
+    p->ny = ny;
+    int dims[2] = {ny, nx};
+    const int dist = ny * nx;
+    const hipfftResult r = hipfftPlanMany(&p->plan, 2, dims, nullptr, 1, dist, nullptr, 1, dist,
+                                          HIPFFT_C2C, npol * layers);
+    if (r != HIPFFT_SUCCESS) {
+        delete p;
+        return set_error(MG_EDEVICE, "FFT plan creation failed (" + std::to_string((int)r) + ")");
+    }
+    *im = p;
+    return MG_OK;
+}
+
+mg_status mg_wstack_imager_exec(mg_wstack_imager *im, const void *grids, void *work, void *image,
+                                const float *corr_x, const float *corr_y, double fov_x,
+                                double fov_y, double dw, hipStream_t stream) {
+    if (!im || !grids || !work || !image || !corr_x || !corr_y)
+        return set_error(MG_EINVAL, "null argument");
+    if (!std::isfinite(fov_x) || !std::isfinite(fov_y) || !std::isfinite(dw))
+        return set_error(MG_EINVAL, "fov and dw must be finite");
+    if (work == image) return set_error(MG_EINVAL, "the image needs its own buffer");
+    const int64_t total = (int64_t)im->npol * im->layers * im->ny * im->nx;
+    hipLaunchKernelGGL(shift_in_kernel, dim3(blocks_for(total)), dim3(256), 0, stream,
+                       (const float2 *)grids, (float2 *)work, im->nx, total);
+    if (hipfftSetStream(im->plan, stream) != HIPFFT_SUCCESS)
+        return set_error(MG_EDEVICE, "FFT stream");
+    const hipfftResult r = hipfftExecC2C(im->plan, (hipfftComplex *)work, (hipfftComplex *)work,
+                                         HIPFFT_BACKWARD);
+    if (r != HIPFFT_SUCCESS)
+        return set_error(MG_EDEVICE, "FFT execution failed (" + std::to_string((int)r) + ")");
+    hipLaunchKernelGGL(wstack_combine_kernel,
+                       dim3(blocks_for((int64_t)im->npol * im->ny * im->nx)), dim3(256), 0, stream,
+                       (const float2 *)work, (float2 *)image, im->nx, im->ny, im->npol,
+                       im->layers, dw, fov_x, fov_y, corr_x, corr_y);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("W-stacking kernels: ") + hipGetErrorString(e));
+    return MG_OK;
+}
+
+mg_status mg_wstack_imager_destroy(mg_wstack_imager *im) {
     if (!im) return MG_OK;
     if (im->plan) hipfftDestroy(im->plan);
     delete im;

@@ -233,6 +233,8 @@ mg_status mg_server_submit(mg_server *s, const mg_grid_desc *g, const mg_kernel_
     if (nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
     if (!grid) return set_error(MG_EINVAL, "null grid");
     if (nrec < 0) return set_error(MG_EINVAL, "negative nrec");
+    if (k->kind == MG_KERNEL_WSTACK)
+        return set_error(MG_EUNSUPPORTED, "the server takes separable and W-projection jobs");
     if (k->kind == MG_KERNEL_WPROJ && (k->nplanes < 1 || k->nplanes > kMaxPlanes ||
                                        !k->plane_support || !k->plane_offset))
         return set_error(MG_EINVAL, "bad W-projection planes");
