@@ -41,6 +41,7 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X published (packed FP32)
 FP32_UNPACKED_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6              # vector FP64
 PAPER_P100 = ("Conv Gridder FP32 Npol=4 max 3.62 GRecs/s x 36 = 1.30e11 updates/s "
               "(S=6 real kernel, no w-term; Tesla P100)")
 
@@ -317,6 +318,123 @@ def precision_leg(api, W, torch, dev, stream, steps):
     return out
 
 
+def imaging_leg(api, W, torch, dev, stream, wl, name):
+    """The imaging chain on a convolutional grid of the workload: corrector
+    vector, origin shifts fused around the platform library's batched C2C
+    inverse FFT (one per polarisation) and the separable correction.  The
+    fused shift-in and correct-out kernels stream the grid twice (read and
+    write, 4 x 8 bytes per cell each); the FFT is the library's."""
+    import numpy as np
+    timer = Timer(torch, stream)
+    n = wl.n
+    G = W.vis_normal_torch(4 * n * n, 1, W.SEED_NOISE, dev).reshape(4, n, n)
+    t = torch.from_numpy(wl.taps.astype(np.float32)).to(dev)
+    h = api.corrector(n, wl.beta, t, wl.beta)
+    im = api.Imager(4, n, n)
+    out = torch.empty_like(G)
+    chain = timer.protocol(lambda: im.image(G, h, h, out=out))
+    fft = timer.protocol(lambda: torch.fft.ifft2(G))
+    corr = timer.protocol(lambda: api.corrector(n, wl.beta, t, wl.beta))
+    im.close()
+    grid_bytes = 4 * 8 * n * n
+    # the least traffic of the chain: shift-in, one FFT pass and the
+    # correction each read and write the grid once
+    r = {"workload": name, "grid": [4, n, n], "chain": chain, "library_fft_alone": fft,
+         "corrector": corr,
+         "chain_hbm_frac": 6 * grid_bytes / (HBM_PEAK_GBS * 1e9) / (chain["mean_ms"] * 1e-3),
+         "note": "chain_hbm_frac: 6 x the grid bytes (three read-write passes) over the chain "
+                 "time; torch.fft.ifft2 of the same grid timed alone for comparison"}
+    log(f"[bench] imaging {name}: chain {chain['mean_ms']:.3f} ms, library FFT alone "
+        f"{fft['mean_ms']:.3f} ms, corrector {corr['mean_ms']:.4f} ms")
+    return r
+
+
+def kernel_bank_leg(api, W, torch, dev, wl_wproj):
+    """The W-projection bank of the 32-plane schedule (S 8 -> 64,
+    oversampling 4, the W-projection and precision workloads' bank), built
+    on the device in FP64 (taper, screen, batched Z2Z FFT per plane size,
+    normalisation); the FP64 oracle's time for the same bank is part of the
+    CPU baseline.  Timed on the host clock around a synchronised call (it
+    includes the workspace allocation and about 160 launches), after a first
+    call that creates the FFT plans; the FFT flops use 5 M^2 log2(M^2) per
+    M x M plane."""
+    import numpy as np
+    b = wl_wproj.bank
+    sup = [int(x) for x in b.supports]
+    dw = 1.0 / b.inv_dw
+    ws = [p * dw for p in range(len(sup))]
+    base = W.pswf_taps(7, 4)
+    bt = torch.from_numpy(base).to(dev)
+    api.wkernel_bank(sup, ws, 4, bt, wl_wproj.scale)          # FFT plans made
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.wkernel_bank(sup, ws, 4, bt, wl_wproj.scale)
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t0))
+    flops = sum(5.0 * (8 * s) ** 2 * np.log2((8 * s) ** 2) for s in sup)
+    r = {"schedule": "32 planes, S 8->64, beta 4, FP64 build, complex64 output",
+         "device_ms_min": float(min(times)), "device_ms_median": float(np.median(times)),
+         "fft_flops": flops,
+         "fft_fp64_frac_at_min": flops / (FP64_PEAK_TFLOPS * 1e12) / (min(times) * 1e-3),
+         "note": "launch-bound at this size: the whole bank is 32 planes of at most 512^2 "
+                 "points"}
+    log(f"[bench] kernel bank: device {min(times):.2f} ms (median {np.median(times):.2f})")
+    return r
+
+
+def wstack_leg(api, W, torch, dev, stream, wl, name, layers=16):
+    """W-stacking on the workload's records: gridding onto `layers` layer
+    grids (the plain gridder's kernels on the stacked grid) against gridding
+    the same records onto one grid, and the W-stacking image (batched FFT of
+    every layer and polarisation, screen-and-sum kernel that reads every
+    layer once and writes the image)."""
+    import numpy as np
+    timer = Timer(torch, stream)
+    n = wl.n
+    wmax = float(np.max(np.abs(wl.uvw[:, 2])))
+    dw = 2.0 * wmax / (layers - 1)
+    spec = api.GridSpec(n, n, 4, wl.beta, wl.scale, wl.scale)
+    t = torch.from_numpy(wl.taps.astype(np.float32)).to(dev)
+    plain = api.KernelBank("separable", t, support=wl.support)
+    ws = api.KernelBank("wstack", t, support=wl.support, layers=layers, inv_dw=1.0 / dw)
+    uvw = torch.from_numpy(wl.uvw).to(dev)
+    vis = W.vis_normal_torch(wl.nrec, 4, W.SEED_VIS, dev)
+    pp = api.Plan(spec, plain, uvw)
+    pw = api.Plan(spec, ws, uvw)
+    g1 = torch.zeros(4, n, n, dtype=torch.complex64, device=dev)
+    gl = torch.zeros(4, layers, n, n, dtype=torch.complex64, device=dev)
+    tp = timer.protocol(lambda: pp.grid(vis, out=g1))
+    tw = timer.protocol(lambda: pw.grid(vis, out=gl))
+    nval = wl.nrec - pw.nskipped
+    pp.close()
+    pw.close()
+    h = api.corrector(n, wl.beta, t, wl.beta)
+    im = api.WStackImager(4, layers, n, n)
+    img = torch.empty(4, n, n, dtype=torch.complex64, device=dev)
+    ti = timer.protocol(lambda: im.image(gl, h, h, wl.scale, wl.scale, dw, out=img), calls=5)
+    fft = timer.protocol(lambda: torch.fft.ifft2(gl), calls=5)
+    im.close()
+    upd = nval * wl.support ** 2
+    layer_bytes = 4 * layers * 8 * n * n
+    r = {"workload": name, "layers": layers, "layer_spacing_wavelengths": dw,
+         "grid": [4, layers, n, n], "records": wl.nrec, "valid_records": nval,
+         "plain_plan_grid": tp, "wstack_plan_grid": tw,
+         "wstack_grid_updates_per_s": upd / (tw["mean_ms"] * 1e-3),
+         "wstack_over_plain_grid_time": tw["mean_ms"] / tp["mean_ms"],
+         "image": ti, "library_fft_alone": fft,
+         "image_hbm_frac": (5 * layer_bytes + 4 * 8 * n * n) / (HBM_PEAK_GBS * 1e9)
+                           / (ti["mean_ms"] * 1e-3),
+         "note": "image_hbm_frac: the least traffic of the chain (shift-in and one FFT pass "
+                 "read and write every layer, the screen-and-sum reads every layer and writes "
+                 "the image) over the image time"}
+    log(f"[bench] wstack {name}: {layers} layers, grid {tw['mean_ms']:.3f} ms (plain "
+        f"{tp['mean_ms']:.3f} ms), image {ti['mean_ms']:.3f} ms (FFT alone {fft['mean_ms']:.3f})")
+    return r
+
+
 def serving_leg(dev, njobs):
     """A Poisson trace of uneven gridding jobs through the serving API: the
     jobs one at a time, then at offered loads 0.5, 0.8 and 0.95 (latency),
@@ -377,7 +495,14 @@ def cpu_baseline_leg(api, W, torch, dev, wl, uvw, vis, b, nrec, per_thread):
     oracle.grid_par(geom, taps, uvw_s, vis_s, out=out)
     cpu_s = time.perf_counter() - c0
     log(f"[bench] cpu oracle {upd_s / cpu_s:.3e} updates/s over {cpu_s:.1f}s on {threads} threads")
+    # the same workload's W-projection bank built by the FP64 oracle
+    from oracle import wkernel as WK
+    sup = [int(x) for x in b.supports]
+    c0 = time.perf_counter()
+    WK.wbank(W.pswf_taps(7, 4), 4, sup, [p / b.inv_dw for p in range(len(sup))], wl.scale)
+    bank_ms = 1e3 * (time.perf_counter() - c0)
     return {
+        "kernel_bank_oracle_ms": bank_ms,
         "value": upd_s / cpu_s, "unit": "record x kernel-point updates/s", "cores": threads,
         "kind": "oracle",
         "sample": f"{k} records drawn with seed {W.SEED_SUBSAMPLE} from the {nrec}-record "
@@ -407,7 +532,8 @@ def main():
                     help="skip the small, autograd and precision workload legs")
     ap.add_argument("--only-headline", action="store_true",
                     help="headline step and dominant unit only (profiling runs)")
-    ap.add_argument("--only-leg", choices=["small", "autograd", "precision", "serving", "hybrid"],
+    ap.add_argument("--only-leg", choices=["small", "autograd", "precision", "serving", "hybrid",
+                                           "imaging", "wstack", "bank"],
                     help="run one of the other workloads alone (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -437,6 +563,15 @@ def main():
                               "autograd-sep7-2048-10M", autograd=True)
         elif args.only_leg == "precision":
             r = precision_leg(api, W, torch, dev, stream, steps=args.steps)
+        elif args.only_leg == "imaging":
+            r = imaging_leg(api, W, torch, dev, stream, W.config_autograd(),
+                            "autograd-sep7-2048-10M")
+        elif args.only_leg == "wstack":
+            r = wstack_leg(api, W, torch, dev, stream, W.config_autograd(),
+                           "autograd-sep7-2048-10M")
+        elif args.only_leg == "bank":
+            r = kernel_bank_leg(api, W, torch, dev, W.config_wproj_device(
+                dev, name="wproj-8192-P32-S8to64-134M"))
         elif args.only_leg == "hybrid":
             r = {"small": hybrid_leg(api, W, torch, dev, stream, W.config_small(),
                                      "small-sep7-1024-100800"),
@@ -593,7 +728,8 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_leg(api, W, torch, dev, wl, uvw, vis, b, nrec,
                                                   args.cpu_per_thread)
-    del grid, vis, uvw, wl
+    bank_wl = wl
+    del grid, vis, uvw
     torch.cuda.empty_cache()
 
     if not args.no_legs:
@@ -607,6 +743,10 @@ def main():
                                 "small-sep7-1024-100800"),
             "autograd": hybrid_leg(api, W, torch, dev, stream, W.config_autograd(),
                                    "autograd-sep7-2048-10M")}
+        ag = W.config_autograd()
+        result["imaging"] = imaging_leg(api, W, torch, dev, stream, ag, "autograd-sep7-2048-10M")
+        result["wstack"] = wstack_leg(api, W, torch, dev, stream, ag, "autograd-sep7-2048-10M")
+        result["kernel_bank"] = kernel_bank_leg(api, W, torch, dev, bank_wl)
 
     if args.serving_jobs > 0:
         result["serving"] = serving_leg(dev, args.serving_jobs)

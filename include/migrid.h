@@ -387,9 +387,12 @@ mg_status mg_wkernel_bank_size(int32_t nplanes, const int32_t *plane_support, in
 /* plane_support, plane_w: HOST [nplanes]; bank: DEVICE, bank_elems taps;
  * plane_offset: HOST output [nplanes], element offset of each plane;
  * workspace: DEVICE, at least the size mg_wkernel_bank_size reports (FP64
- * image grids and tapers), passed with its size.  Creates and destroys FFT
- * plans of the platform library and returns once the bank is written (it
- * synchronises `stream`).  Errors: MG_EINVAL (sizes out of range, beta*S
+ * image grids and tapers), passed with its size, in use until the queued
+ * work is done.  The work is queued on `stream` (no host copies, no
+ * synchronisation); the FFT plans of the platform library (one per plane
+ * size and device, created on first use) are kept for the life of the
+ * process and shared, so builds on different streams of one device must not
+ * overlap.  Errors: MG_EINVAL (sizes out of range, beta*S
  * odd or above 4096, a plane narrower than the base kernel, fov not
  * positive, non-finite w, null pointers, workspace too small), MG_EDEVICE. */
 mg_status mg_wkernel_bank(int32_t nplanes, const int32_t *plane_support, const double *plane_w,

@@ -15,16 +15,20 @@
 //                  (T symmetric, so the inverse DFT is real)
 //   screen_kernel  img = c[i] c[j] gbar(l_i, m_j), written straight in the
 //                  transform's order (index 0 = centre)
-//   the platform library's batched Z2Z forward FFT, one batch per distinct M
+//   the platform library's Z2Z forward FFT (one plan per size M and device,
+//                  created on first use and kept for the process)
 //   maxabs_kernel  largest |K| over every plane's kept samples
 //   store_kernel   bank = K / max, converted to the output tap format, row
 //                  (v offset) major.
+// Plane parameters travel as kernel arguments (one launch per plane and
+// step), so the call copies nothing from the host and does not synchronise.
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -87,16 +91,14 @@ __device__ inline int64_t kept_index(int ta, int tb, int M, int half) {
 
 __global__ __launch_bounds__(256) void clear_max_kernel(unsigned long long *mx) { *mx = 0ull; }
 
-__global__ __launch_bounds__(256) void maxabs_kernel(const PlaneJob *__restrict__ jobs,
-                                                     int32_t beta, const double2 *__restrict__ buf,
+__global__ __launch_bounds__(256) void maxabs_kernel(int32_t M, int32_t E,
+                                                     const double2 *__restrict__ buf,
                                                      unsigned long long *mx) {
-    const PlaneJob jb = jobs[blockIdx.y];
-    const int E = beta * jb.S + 1;
-    const int half = beta * jb.S / 2;
+    const int half = (E - 1) / 2;
     double best = 0.0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < E * E; t += gridDim.x * blockDim.x) {
         const int ta = t / E, tb = t - ta * E;
-        const double2 v = buf[jb.img_off + kept_index(ta, tb, jb.M, half)];
+        const double2 v = buf[kept_index(ta, tb, M, half)];
         best = fmax(best, sqrt(v.x * v.x + v.y * v.y));
     }
     // magnitudes are non-negative, so their bit patterns order like the values
@@ -124,30 +126,45 @@ __device__ inline void store_tap<__hip_bfloat16>(__hip_bfloat16 *bank, int64_t i
 }
 
 template <typename OutT>
-__global__ __launch_bounds__(256) void store_kernel(const PlaneJob *__restrict__ jobs, int32_t beta,
+__global__ __launch_bounds__(256) void store_kernel(int32_t M, int32_t E,
                                                     const double2 *__restrict__ buf,
                                                     const unsigned long long *mx,
                                                     OutT *__restrict__ bank) {
-    const PlaneJob jb = jobs[blockIdx.y];
-    const int E = beta * jb.S + 1;
-    const int half = beta * jb.S / 2;
+    const int half = (E - 1) / 2;
     const double m = __longlong_as_double((long long)*mx);
     const double inv = m > 0.0 ? 1.0 / m : 0.0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < E * E; t += gridDim.x * blockDim.x) {
         const int ta = t / E, tb = t - ta * E;
-        const double2 v = buf[jb.img_off + kept_index(ta, tb, jb.M, half)];
-        store_tap<OutT>(bank, jb.bank_off + t, v.x * inv, v.y * inv);
+        const double2 v = buf[kept_index(ta, tb, M, half)];
+        store_tap<OutT>(bank, t, v.x * inv, v.y * inv);
     }
+}
+
+// FFT plans by (device, M), kept for the life of the process.
+std::mutex g_fft_mu;
+std::map<std::pair<int, int>, hipfftHandle> g_fft;
+
+hipfftResult fft_plan(int M, hipfftHandle *h) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HIPFFT_INTERNAL_ERROR;
+    std::lock_guard<std::mutex> lk(g_fft_mu);
+    auto it = g_fft.find({dev, M});
+    if (it != g_fft.end()) {
+        *h = it->second;
+        return HIPFFT_SUCCESS;
+    }
+    const hipfftResult r = hipfftPlan2d(h, M, M, HIPFFT_Z2Z);
+    if (r == HIPFFT_SUCCESS) g_fft[{dev, M}] = *h;
+    return r;
 }
 
 struct Layout {
     std::vector<PlaneJob> jobs;
-    std::map<int, std::vector<int>> by_m;   // M -> planes (FFT batch order)
     int64_t bank_elems = 0;
     int64_t img_elems = 0;
     int64_t taper_elems = 0;
     size_t bytes = 0;
-    size_t off_img = 0, off_taper = 0, off_jobs = 0, off_max = 0;
+    size_t off_img = 0, off_taper = 0, off_max = 0;
 };
 
 mg_status make_layout(int32_t nplanes, const int32_t *sup, int32_t beta, Layout &L) {
@@ -161,19 +178,15 @@ mg_status make_layout(int32_t nplanes, const int32_t *sup, int32_t beta, Layout 
         if (((int64_t)beta * S) % 2) return set_error(MG_EINVAL, "beta * support must be even");
         // the FP64 image grid of a plane is (2 beta S)^2 x 16 bytes
         if ((int64_t)beta * S > 4096) return set_error(MG_EINVAL, "beta * support must be <= 4096");
-        L.jobs[p].S = S;
-        L.jobs[p].M = 2 * beta * S;
-        L.jobs[p].bank_off = L.bank_elems;
+        PlaneJob &j = L.jobs[p];
+        j.S = S;
+        j.M = 2 * beta * S;
+        j.bank_off = L.bank_elems;
         L.bank_elems += (int64_t)(beta * S + 1) * (beta * S + 1);
-        L.by_m[L.jobs[p].M].push_back(p);
+        j.img_off = L.img_elems;
+        L.img_elems += (int64_t)j.M * j.M;
+        L.taper_elems += j.M;
     }
-    // FFT buffer: the planes of one M contiguous (one batched transform)
-    for (auto &kv : L.by_m)
-        for (int p : kv.second) {
-            L.jobs[p].img_off = L.img_elems;
-            L.img_elems += (int64_t)kv.first * kv.first;
-            L.taper_elems += kv.first;
-        }
     size_t off = 0;
     auto take = [&](size_t b) {
         const size_t at = off;
@@ -182,7 +195,6 @@ mg_status make_layout(int32_t nplanes, const int32_t *sup, int32_t beta, Layout 
     };
     L.off_img = take(sizeof(double2) * (size_t)L.img_elems);
     L.off_taper = take(sizeof(double) * (size_t)L.taper_elems);
-    L.off_jobs = take(sizeof(PlaneJob) * (size_t)nplanes);
     L.off_max = take(sizeof(unsigned long long));
     L.bytes = off;
     return MG_OK;
@@ -228,87 +240,61 @@ mg_status mg_wkernel_bank(int32_t nplanes, const int32_t *plane_support, const d
     char *ws = static_cast<char *>(workspace);
     double2 *img = reinterpret_cast<double2 *>(ws + L.off_img);
     double *taper = reinterpret_cast<double *>(ws + L.off_taper);
-    PlaneJob *djobs = reinterpret_cast<PlaneJob *>(ws + L.off_jobs);
     unsigned long long *mx = reinterpret_cast<unsigned long long *>(ws + L.off_max);
 
-    hipError_t e = hipMemcpyAsync(djobs, L.jobs.data(), sizeof(PlaneJob) * nplanes,
-                                  hipMemcpyHostToDevice, stream);
-    // plan every distinct size first (plan creation synchronises the device)
-    std::vector<std::pair<int, hipfftHandle>> plans;
-    mg_status out = MG_OK;
-    for (auto &kv : L.by_m) {
+    hipLaunchKernelGGL(clear_max_kernel, dim3(1), dim3(1), 0, stream, mx);
+    int64_t toff = 0;
+    for (int p = 0; p < nplanes; ++p) {
+        const PlaneJob &j = L.jobs[p];
+        const int M = j.M, E = beta * j.S + 1;
+        double *c = taper + toff;
+        toff += M;
+        double2 *buf = img + j.img_off;
+        hipLaunchKernelGGL(taper_kernel, dim3((M + 255) / 256), dim3(256), 0, stream, M, base_len,
+                           base_taps, c);
+        const int64_t n = (int64_t)M * M;
+        hipLaunchKernelGGL(screen_kernel, dim3((int)std::min<int64_t>((n + 255) / 256, 4096)),
+                           dim3(256), 0, stream, M, beta, plane_w[p], fov, (const double *)c, buf);
         hipfftHandle h = 0;
-        int dims[2] = {kv.first, kv.first};
-        const int dist = kv.first * kv.first;
-        const hipfftResult r = hipfftPlanMany(&h, 2, dims, nullptr, 1, dist, nullptr, 1, dist,
-                                              HIPFFT_Z2Z, (int)kv.second.size());
-        if (r != HIPFFT_SUCCESS) {
-            out = set_error(MG_EDEVICE, "FFT plan creation failed (" + std::to_string((int)r) + ")");
-            break;
+        hipfftResult r = fft_plan(M, &h);
+        if (r == HIPFFT_SUCCESS) {
+            // the plan is shared: its stream is set and the transform queued
+            // under the lock
+            std::lock_guard<std::mutex> lk(g_fft_mu);
+            r = hipfftSetStream(h, stream);
+            if (r == HIPFFT_SUCCESS)
+                r = hipfftExecZ2Z(h, (hipfftDoubleComplex *)buf, (hipfftDoubleComplex *)buf,
+                                  HIPFFT_FORWARD);
         }
-        plans.emplace_back(kv.first, h);
+        if (r != HIPFFT_SUCCESS)
+            return set_error(MG_EDEVICE, "FFT failed (" + std::to_string((int)r) + ")");
+        hipLaunchKernelGGL(maxabs_kernel, dim3((unsigned)std::min(64, (E * E + 255) / 256)),
+                           dim3(256), 0, stream, M, E, (const double2 *)buf, mx);
     }
-    if (out == MG_OK && e == hipSuccess) {
-        int64_t toff = 0;
-        for (auto &kv : L.by_m) {
-            const int M = kv.first;
-            for (int p : kv.second) {
-                // one taper per plane keeps the screen's indexing plain (M
-                // doubles each)
-                double *c = taper + toff;
-                hipLaunchKernelGGL(taper_kernel, dim3((M + 255) / 256), dim3(256), 0, stream, M,
-                                   base_len, base_taps, c);
-                const int64_t n = (int64_t)M * M;
-                const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-                hipLaunchKernelGGL(screen_kernel, dim3(blocks), dim3(256), 0, stream, M, beta,
-                                   plane_w[p], fov, (const double *)c, img + L.jobs[p].img_off);
-                toff += M;
-            }
-        }
-        for (auto &ph : plans) {
-            const int p0 = L.by_m[ph.first].front();
-            if (hipfftSetStream(ph.second, stream) != HIPFFT_SUCCESS ||
-                hipfftExecZ2Z(ph.second, (hipfftDoubleComplex *)(img + L.jobs[p0].img_off),
-                              (hipfftDoubleComplex *)(img + L.jobs[p0].img_off),
-                              HIPFFT_FORWARD) != HIPFFT_SUCCESS) {
-                out = set_error(MG_EDEVICE, "FFT execution failed");
-                break;
-            }
-        }
-    }
-    if (out == MG_OK && e == hipSuccess) {
-        int maxE = 0;
-        for (auto &j : L.jobs) maxE = std::max(maxE, beta * j.S + 1);
-        const dim3 g((unsigned)std::min(64, (maxE * maxE + 255) / 256), (unsigned)nplanes);
-        hipLaunchKernelGGL(clear_max_kernel, dim3(1), dim3(1), 0, stream, mx);
-        hipLaunchKernelGGL(maxabs_kernel, g, dim3(256), 0, stream, (const PlaneJob *)djobs, beta,
-                           (const double2 *)img, mx);
+    for (int p = 0; p < nplanes; ++p) {
+        const PlaneJob &j = L.jobs[p];
+        const int M = j.M, E = beta * j.S + 1;
+        const double2 *buf = img + j.img_off;
+        const dim3 g((unsigned)std::min(256, (E * E + 255) / 256));
         switch (out_dtype) {
         case MG_F16:
-            hipLaunchKernelGGL(store_kernel<__half>, g, dim3(256), 0, stream,
-                               (const PlaneJob *)djobs, beta, (const double2 *)img,
-                               (const unsigned long long *)mx, (__half *)bank);
+            hipLaunchKernelGGL(store_kernel<__half>, g, dim3(256), 0, stream, M, E, buf,
+                               (const unsigned long long *)mx,
+                               (__half *)bank + 2 * j.bank_off);
             break;
         case MG_BF16:
-            hipLaunchKernelGGL(store_kernel<__hip_bfloat16>, g, dim3(256), 0, stream,
-                               (const PlaneJob *)djobs, beta, (const double2 *)img,
-                               (const unsigned long long *)mx, (__hip_bfloat16 *)bank);
+            hipLaunchKernelGGL(store_kernel<__hip_bfloat16>, g, dim3(256), 0, stream, M, E, buf,
+                               (const unsigned long long *)mx,
+                               (__hip_bfloat16 *)bank + 2 * j.bank_off);
             break;
         default:
-            hipLaunchKernelGGL(store_kernel<float>, g, dim3(256), 0, stream,
-                               (const PlaneJob *)djobs, beta, (const double2 *)img,
-                               (const unsigned long long *)mx, (float *)bank);
+            hipLaunchKernelGGL(store_kernel<float>, g, dim3(256), 0, stream, M, E, buf,
+                               (const unsigned long long *)mx, (float *)bank + 2 * j.bank_off);
             break;
         }
-        e = hipGetLastError();
     }
-    // the plans own work areas the transforms use: finish before freeing them
-    const hipError_t es = hipStreamSynchronize(stream);
-    for (auto &ph : plans) hipfftDestroy(ph.second);
-    if (out != MG_OK) return out;
-    if (e != hipSuccess || es != hipSuccess)
-        return set_error(MG_EDEVICE, std::string("kernel bank: ") +
-                                         hipGetErrorString(e != hipSuccess ? e : es));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(MG_EDEVICE, std::string("kernel bank: ") + hipGetErrorString(e));
     for (int p = 0; p < nplanes; ++p) plane_offset[p] = L.jobs[p].bank_off;
     return MG_OK;
 }
