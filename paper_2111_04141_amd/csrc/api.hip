@@ -228,6 +228,11 @@ hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t stream) {
             if (e != hipSuccess) return e;
             uint64_t keep = kPoolKeepBytes;
             hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            // a block freed on one stream must not be handed to another
+            // stream by making that stream wait for the first: concurrent
+            // callers (the server's job streams) would be chained together
+            int no = 0;
+            hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowInternalDependencies, &no);
             g_pools[dev] = pool;
         }
     }
@@ -497,17 +502,23 @@ mg_status static_scratch(void **out) {
 }
 
 // One-shot calls: plan and call scratch in one stream-ordered allocation.
+// The one-shot pipeline (index, sort, gather, grid or degrid) in `arena`,
+// which holds at least plan_arena_bytes + the call's scratch bytes; with a
+// null arena the bytes come from the library's pool for this call.
 mg_status one_shot(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
                    const void *uvw, mg_dtype uvw_dtype, bool gridding, const void *in, void *out,
-                   int64_t *d_nskipped, hipStream_t stream) {
+                   int64_t *d_nskipped, hipStream_t stream, void *arena = nullptr) {
     PlanState P;
     mg_status s = plan_prepare(P, g, k, nrec);
     if (s != MG_OK) return s;
     const size_t pb = plan_arena_bytes(P);
     const size_t cb = gridding ? grid_scratch_bytes(P) : degrid_scratch_bytes(P);
-    void *arena = nullptr;
-    hipError_t e = scratch_alloc(&arena, pb + cb, stream);
-    if (e != hipSuccess) return set_error(MG_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+    void *own = nullptr;
+    if (!arena) {
+        hipError_t e = scratch_alloc(&own, pb + cb, stream);
+        if (e != hipSuccess) return set_error(MG_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+        arena = own;
+    }
     s = build_in(P, k, uvw, uvw_dtype, arena, stream);
     void *scratch = static_cast<char *>(arena) + pb;
     if (s == MG_OK)
@@ -515,10 +526,11 @@ mg_status one_shot(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
                      : launch_degrid(P, in, out, scratch, stream);
     if (s == MG_OK && d_nskipped)
         hipLaunchKernelGGL(add_count_kernel, dim3(1), dim3(64), 0, stream, P.counters, d_nskipped);
-    scratch_free(arena, stream);
+    if (own) scratch_free(own, stream);
     return s;
 }
 }  // namespace
+
 
 mg_status mg_grid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec, const void *uvw,
                   mg_dtype uvw_dtype, const void *vis, void *grid, int64_t *d_nskipped,
@@ -570,3 +582,28 @@ mg_status mg_degrid(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec
 }
 
 }  // extern "C"
+
+mg_status mg::grid_in_arena(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                        const void *uvw, mg_dtype uvw_dtype, const void *vis, void *grid,
+                        void **arena, size_t *arena_bytes, hipStream_t stream) {
+    mg_status s = check_common(g, k, nrec, uvw, uvw_dtype);
+    if (s != MG_OK) return s;
+    if (nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
+    if (!grid) return set_error(MG_EINVAL, "null grid");
+    PlanState P;
+    s = plan_prepare(P, g, k, nrec);
+    if (s != MG_OK) return s;
+    const size_t need = plan_arena_bytes(P) + grid_scratch_bytes(P);
+    if (need > *arena_bytes) {
+        // grow by at least half, in the stream's order: the old arena is
+        // released after the stream's earlier work
+        const size_t cap = std::max(need, *arena_bytes + *arena_bytes / 2);
+        void *p = nullptr;
+        const hipError_t e = scratch_alloc(&p, cap, stream);
+        if (e != hipSuccess) return set_error(MG_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+        if (*arena) scratch_free(*arena, stream);
+        *arena = p;
+        *arena_bytes = cap;
+    }
+    return one_shot(g, k, nrec, uvw, uvw_dtype, true, vis, grid, nullptr, stream, *arena);
+}

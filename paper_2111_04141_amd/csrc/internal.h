@@ -139,6 +139,14 @@ constexpr uint64_t kPoolKeepBytes = uint64_t(8) << 30;
 hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t stream);
 hipError_t scratch_free(void *p, hipStream_t stream);
 
+// mg_grid with the plan and scratch in a caller-held arena that grows (in
+// `stream`'s order, never shrinking) when a call needs more: the serving
+// streams each keep one, so jobs allocate nothing once the arenas have grown
+// (api.hip).
+mg_status grid_in_arena(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nrec,
+                        const void *uvw, mg_dtype uvw_dtype, const void *vis, void *grid,
+                        void **arena, size_t *arena_bytes, hipStream_t stream);
+
 // Workgroups of `kernel` (threads per workgroup, dynamic LDS bytes) that fit
 // on the current device at once; device attributes and occupancy are queried
 // once per (device, kernel, threads, lds) and cached (api.hip).

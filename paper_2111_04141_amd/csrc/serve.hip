@@ -52,6 +52,8 @@ struct mg_server {
     size_t budget = 0;
     int max_slots = 1;
     std::vector<hipStream_t> streams;
+    std::vector<void *> arenas;         // per stream: plan and scratch of its jobs
+    std::vector<size_t> arena_bytes;
     hipStream_t gate = nullptr;        // orders submit-time event waits
     size_t next_stream = 0;
     std::mutex mu;
@@ -148,14 +150,16 @@ void scheduler_loop(mg_server *s) {
             j.acct.state = kJobRunning;
             s->running.push_back(j.id);
             s->stats.max_running = std::max<int32_t>(s->stats.max_running, (int32_t)s->running.size());
-            hipStream_t st = s->streams[s->next_stream++ % s->streams.size()];
+            const size_t si = s->next_stream++ % s->streams.size();
+            hipStream_t st = s->streams[si];
             hipEvent_t ev = take_event(s);
             hipEvent_t ready = j.ready_ev;
             lk.unlock();
             mg_status rc = MG_OK;
             if (ready && hipStreamWaitEvent(st, ready, 0) != hipSuccess) rc = MG_EDEVICE;
             if (rc == MG_OK)
-                rc = mg_grid(&j.g, &j.k, j.nrec, j.uvw, j.uvw_dtype, j.vis, j.grid, nullptr, st);
+                rc = grid_in_arena(&j.g, &j.k, j.nrec, j.uvw, j.uvw_dtype, j.vis, j.grid,
+                                   &s->arenas[si], &s->arena_bytes[si], st);
             if (rc == MG_OK && (!ev || hipEventRecord(ev, st) != hipSuccess)) rc = MG_EDEVICE;
             lk.lock();
             if (rc != MG_OK) {
@@ -211,7 +215,11 @@ mg_status mg_server_create(mg_server **srv, size_t hbm_budget_bytes, int32_t max
     for (int i = 0; i < nstreams + 1 && ok; ++i) {
         hipStream_t st;
         ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
-        if (ok && i < nstreams) s->streams.push_back(st);
+        if (ok && i < nstreams) {
+            s->streams.push_back(st);
+            s->arenas.push_back(nullptr);
+            s->arena_bytes.push_back(0);
+        }
         if (ok && i == nstreams) s->gate = st;
     }
     hipSetDevice(prev);
@@ -326,9 +334,10 @@ mg_status mg_server_destroy(mg_server *s) {
     }
     s->cv_work.notify_one();
     if (s->worker.joinable()) s->worker.join();
-    for (hipStream_t st : s->streams) {
-        hipStreamSynchronize(st);
-        hipStreamDestroy(st);
+    for (size_t i = 0; i < s->streams.size(); ++i) {
+        if (s->arenas[i]) scratch_free(s->arenas[i], s->streams[i]);
+        hipStreamSynchronize(s->streams[i]);
+        hipStreamDestroy(s->streams[i]);
     }
     if (s->gate) {
         hipStreamSynchronize(s->gate);
