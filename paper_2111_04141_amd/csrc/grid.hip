@@ -85,6 +85,11 @@ struct GridParams {
     int32_t p_lo, p_hi;       // planes handled by this launch
 };
 
+// Two 16-bit lanes of a 32-bit word (packed 16-bit integer arithmetic).
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+__device__ inline u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ inline uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
 // Visibilities of one record, 4 polarisations.
 struct RecVis {
     float vr[4], vi[4];
@@ -207,6 +212,7 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
         }
         const uint32_t cu0 = ((tile % (uint32_t)gl.ntu) << gl.log2T) + umin;
         const uint32_t cv0 = ((tile / (uint32_t)gl.ntu) << gl.log2T) + vmin;
+        const uint32_t corg = cu0 | (cv0 << 16);
         const int RW = (int)(uend - umin);
         const int RH = (int)(vend - vmin);
         const int plane_cells = RH * RW;
@@ -227,8 +233,11 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
         auto commit = [&](float (&sums)[8], uint32_t cell_uv) {
             const uint32_t cu_ = cell_uv & 0xffffu, cv_ = cell_uv >> 16;
             if (use_lds) {
-                // row times width in the 24-bit multiplier (full rate)
-                int32_t *dst = &region[__umul24(cv_ - cv0, (uint32_t)RW) + (cu_ - cu0)];
+                // the cell relative to the region origin, both halves at once
+                // (neither borrows: the cell lies inside the region); row times
+                // width in the 24-bit multiplier (full rate)
+                const uint32_t rel = cell_uv - corg;
+                int32_t *dst = &region[__umul24(rel >> 16, (uint32_t)RW) + (rel & 0xffffu)];
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
                     atomicAdd(&dst[q * PS], round_to_fixed(sums[q]));
@@ -294,6 +303,10 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
                     prev_kuv = kuv;
                     const uint32_t ku = meta_ku(m), kv = meta_kv(m);
                     const uint32_t kmu = ku % (uint32_t)S, kmv = kv % (uint32_t)S;
+                    // (u, v) pairs in 16-bit halves: the footprint origin, its
+                    // residues mod S and S itself
+                    const u16x2 korg = as_u16x2(kuv), kres = as_u16x2(kmu | (kmv << 16)),
+                                ss = as_u16x2((uint32_t)S | ((uint32_t)S << 16));
 #pragma unroll
                     for (int k = 0; k < KD; ++k) {
                         // the slot's cell has left the footprint (a borrow
@@ -304,12 +317,15 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
                                 commit(acc[k], cell[k]);
 #pragma unroll
                             for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-                            int du = (int)(suv[k] & 0xffffu) - (int)kmu;
-                            int dv = (int)(suv[k] >> 16) - (int)kmv;
-                            du += (du < 0) ? S : 0;
-                            dv += (dv < 0) ? S : 0;
-                            const uint32_t nu_ = ku + (uint32_t)du, nv_ = kv + (uint32_t)dv;
-                            cell[k] = nu_ | (nv_ << 16);
+                            // the cell congruent to the slot in the footprint:
+                            // origin + (slot - origin mod S) mod S, per half; a
+                            // negative difference wraps above 2^15, and adding S
+                            // brings it back below S, so the smaller of the two
+                            // is the residue
+                            const u16x2 dd = as_u16x2(suv[k]) - kres;
+                            const u16x2 cc = korg + __builtin_elementwise_min(dd, dd + ss);
+                            cell[k] = as_u32(cc);
+                            const uint32_t nu_ = cell[k] & 0xffffu, nv_ = cell[k] >> 16;
                             // cells < 2^16 and steps < 2^10: the 24-bit
                             // multiplier (full rate) is exact
                             if constexpr (SEP) {
@@ -339,7 +355,9 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
                                            0.0f);
                     } else {
                         const char *tb = tbase + (size_t)m.toff * kElem;
-                        return TapTraits<TapT>::cplx((const TapT *)(tb + (lo[k] - ru)), 0);
+                        uint32_t o = lo[k] - ru;
+                        asm volatile("" : "+v"(o));   // keeps the offset 32-bit: scalar-base load
+                        return TapTraits<TapT>::cplx((const TapT *)(tb + o), 0);
                     }
                 };
                 auto madd = [&](const int k, const float2 w, const RecVis &f) {
