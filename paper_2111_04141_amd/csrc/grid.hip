@@ -89,6 +89,11 @@ struct GridParams {
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 __device__ inline u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ inline uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+// a.u b.u + a.v b.v + c (modulo 2^32) in one instruction, for a and b holding
+// (u, v) in their 16-bit halves
+__device__ inline uint32_t dot_uv(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_udot2(as_u16x2(a), as_u16x2(b), c, false);
+}
 
 // Visibilities of one record, 4 polarisations.
 struct RecVis {
@@ -162,6 +167,8 @@ constexpr int window_smax(int kmax) { return kmax == 1 ? 8 : kmax == 4 ? 16 : 32
 constexpr int window_plane(int kmax) {
     return (kWindowTile + window_smax(kmax) - 1) * (kWindowTile + window_smax(kmax) - 1);
 }
+// dynamic LDS of a window instance: the region and the unit slot
+constexpr size_t window_lds(int kmax) { return sizeof(int32_t) * (8 * (size_t)window_plane(kmax) + 1); }
 
 template <int KMAX, int TEAM, bool SEP, typename TapT>
 __global__ __launch_bounds__(kWave * window_waves(TEAM))
@@ -174,8 +181,10 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
     constexpr int NW = window_waves(TEAM);
     constexpr int NTEAMS = NW / TEAM;
     constexpr int PS = window_plane(KMAX);   // plane stride (cells)
-    extern __shared__ int32_t region[];   // [8][PS], plane q holding [RH][RW]
-    __shared__ uint32_t s_next;
+    // [8][PS], plane q holding [RH][RW], then the workgroup's unit slot (the
+    // region starts at LDS address 0, so commit addresses need no base)
+    extern __shared__ int32_t region[];
+    uint32_t *const s_next = reinterpret_cast<uint32_t *>(region + 8 * PS);
     constexpr uint32_t kElem = SEP ? sizeof(TapT) : 2 * sizeof(TapT);   // bytes per tap
     const int wave = (int)uniform_u32(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -188,7 +197,7 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
     const uint32_t ubase = bucket_cfirst[gl.base];
     const uint2 *gunits = units + ubase;
     const uint32_t nunits = group_nunits[prm.p_lo];
-    for (uint32_t it = next_chunk(queue, &s_next); it < nunits; it = next_chunk(queue, &s_next)) {
+    for (uint32_t it = next_chunk(queue, s_next); it < nunits; it = next_chunk(queue, s_next)) {
         const uint2 un = gunits[it];
         const uint32_t c0 = un.x, c1 = un.x + un.y;
         // the item's region: union of its chunks' k_lo ranges (relative to
@@ -212,8 +221,11 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
         }
         const uint32_t cu0 = ((tile % (uint32_t)gl.ntu) << gl.log2T) + umin;
         const uint32_t cv0 = ((tile / (uint32_t)gl.ntu) << gl.log2T) + vmin;
-        const uint32_t corg = cu0 | (cv0 << 16);
         const int RW = (int)(uend - umin);
+        // byte offset in a region plane of cell (u, v): 4 (u - cu0) + 4 RW (v - cv0),
+        // as one dot product of the packed cell with (4, 4 RW) plus a constant
+        const uint32_t rstep = 4u | ((uint32_t)(4 * RW) << 16);
+        const uint32_t rbias = 0u - 4u * (cu0 + (uint32_t)RW * cv0);
         const int RH = (int)(vend - vmin);
         const int plane_cells = RH * RW;
 
@@ -233,11 +245,10 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
         auto commit = [&](float (&sums)[8], uint32_t cell_uv) {
             const uint32_t cu_ = cell_uv & 0xffffu, cv_ = cell_uv >> 16;
             if (use_lds) {
-                // the cell relative to the region origin, both halves at once
-                // (neither borrows: the cell lies inside the region); row times
-                // width in the 24-bit multiplier (full rate)
-                const uint32_t rel = cell_uv - corg;
-                int32_t *dst = &region[__umul24(rel >> 16, (uint32_t)RW) + (rel & 0xffffu)];
+                // (the products are below 2^24 and the sum is the cell's
+                // in-region offset, so the wrap of the bias cancels)
+                int32_t *dst = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(region) +
+                                                           dot_uv(cell_uv, rstep, rbias));
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
                     atomicAdd(&dst[q * PS], round_to_fixed(sums[q]));
@@ -262,6 +273,8 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
             // offset terms per cell step (bytes; phase-major table)
             const uint32_t su_step = kElem;
             const uint32_t sv_step = SEP ? kElem : (uint32_t)S * kElem;
+            // the same steps packed (u, v) for the dot product with a cell
+            const uint32_t uv_step = su_step | (sv_step << 16);
 
             // this wave's slots: member * q + k * 64 + lane (q = ceil(S^2 / TEAM));
             // per-lane flags are bit fields (bit k = slot k).  The slot count
@@ -325,14 +338,13 @@ __attribute__((amdgpu_waves_per_eu(TEAM > 1 ? 4 : 1))) void grid_window_kernel(
                             const u16x2 dd = as_u16x2(suv[k]) - kres;
                             const u16x2 cc = korg + __builtin_elementwise_min(dd, dd + ss);
                             cell[k] = as_u32(cc);
-                            const uint32_t nu_ = cell[k] & 0xffffu, nv_ = cell[k] >> 16;
-                            // cells < 2^16 and steps < 2^10: the 24-bit
-                            // multiplier (full rate) is exact
+                            // cells < 2^16 and steps < 2^10: the products
+                            // and their sum are exact
                             if constexpr (SEP) {
-                                lo[k] = __umul24(nu_, su_step);
-                                lov[k] = __umul24(nv_, sv_step);
+                                lo[k] = dot_uv(cell[k], su_step, 0u);
+                                lov[k] = dot_uv(cell[k], sv_step << 16, 0u);
                             } else {
-                                lo[k] = __umul24(nv_, sv_step) + __umul24(nu_, su_step);
+                                lo[k] = dot_uv(cell[k], uv_step, 0u);
                             }
                         }
                     }
@@ -903,9 +915,9 @@ hipError_t launch_class(int cls, const GridPtrs &a, const GridParams &prm, int s
     if (cls <= 2 && (tile != kWindowTile || smax > window_smax(cls == 0 ? 1 : cls == 1 ? 4 : 8)))
         return hipErrorInvalidValue;
     switch (cls) {
-    case 0: launch_window<1, 1, SEP, TapT>(a, prm, sizeof(int32_t) * 8 * window_plane(1), stream); break;
-    case 1: launch_window<4, 1, SEP, TapT>(a, prm, sizeof(int32_t) * 8 * window_plane(4), stream); break;
-    case 2: launch_window<8, 2, SEP, TapT>(a, prm, sizeof(int32_t) * 8 * window_plane(8), stream); break;
+    case 0: launch_window<1, 1, SEP, TapT>(a, prm, window_lds(1), stream); break;
+    case 1: launch_window<4, 1, SEP, TapT>(a, prm, window_lds(4), stream); break;
+    case 2: launch_window<8, 2, SEP, TapT>(a, prm, window_lds(8), stream); break;
     default:
         if (region_blocks(tile, smax) > 7 * 16) return hipErrorInvalidValue;
         launch_block<7, 16, SEP, TapT>(a, prm, stream);
