@@ -1,5 +1,6 @@
 """GPU parity over geometry variants the workload generators do not reach:
-non-square grids whose sides are not multiples of the tile, odd and large
+non-square grids whose sides are not multiples of the tile, the largest
+grid side (65535 cells) along u and along v, odd and large
 oversampling factors, odd supports, S = 1, separable kernels of large
 support (the block kernels' real-tap path), W-projection banks with odd
 plane supports in every support class, FP16 banks, and records on and
@@ -36,6 +37,10 @@ CASES = [
     # at the class's largest slot count
     ("wproj-class2-all", "wproj", 300, 300, 4, list(range(17, 33)), 4, "f32"),
     ("sep-S31-b2", "sep", 300, 290, 2, [31], 4, "f32"),
+    # the largest grid side (cells up to 65534 in the packed 16-bit halves of
+    # the gridders' cell words), along u and along v
+    ("sep-S7-max-u", "sep", 65535, 40, 2, [7], 2, "f32"),
+    ("wproj-max-v", "wproj", 48, 65535, 2, [5, 9, 17, 33], 2, "f32"),
 ]
 
 

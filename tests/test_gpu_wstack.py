@@ -78,6 +78,38 @@ def test_indices_bit_exact(torch_cuda, api):
     assert int(got["nskipped"].item()) == ref["nskipped"] > 0
 
 
+def test_stacked_rows_at_the_16_bit_limit(torch_cuda, api):
+    """8 layers of 8191 rows: stacked rows up to 65527, the top of the
+    gridders' 16-bit cell halves; a random separable 7-tap kernel."""
+    torch = torch_cuda
+    layers, dw, nu, nv, beta, S = 8, 1.0, 64, 8191, 2, 7
+    rng = np.random.Generator(np.random.PCG64(23))
+    nrec = 20000
+    u = rng.uniform(-nu / 2 - 3, nu / 2 + 3, nrec)
+    v = rng.uniform(-nv / 2 - 3, nv / 2 + 3, nrec)
+    w = rng.uniform(-layers / 2 - 1, layers / 2 + 1, nrec) * dw
+    v[:2000] = rng.uniform(nv / 2 - 6, nv / 2, 2000)           # the top rows
+    w[:2000] = rng.uniform(layers / 2 - 1, layers / 2, 2000) * dw   # of the top layer
+    uvw = np.stack([u, v, w], 1)
+    vis = (rng.standard_normal((nrec, 2)) + 1j * rng.standard_normal((nrec, 2)))
+    taps = rng.uniform(-1.0, 1.0, beta * S + 1)
+    spec = api.GridSpec(nu, nv, 2, beta, 1.0, 1.0)
+    bank = api.KernelBank("wstack", torch.from_numpy(taps.astype(np.float32)).cuda(),
+                          support=S, layers=layers, inv_dw=1 / dw)
+    G = api.grid(spec, bank, torch.from_numpy(uvw).cuda(),
+                 torch.from_numpy(vis.astype(np.complex64)).cuda())
+    torch.cuda.synchronize()
+    geom = oracle.Geometry(nu=nu, nv=nv, beta=beta, scale_u=1.0, scale_v=1.0, support=S)
+    taps_q = taps.astype(np.float32).astype(np.float64)
+    ref, sk = WS.grid_layers(geom, taps_q, uvw, vis, layers, 1 / dw)
+    assert 0 < sk < nrec
+    top = ref[:, layers - 1, nv - 8:, :]
+    assert np.abs(top).max() > 0     # the top layer's top rows are reached
+    err = H.rel_l2(G.cpu().numpy(), ref)
+    print(f"[wstack] {layers} x {nv} stacked rows: rel-L2 {err:.2e}", flush=True)
+    assert err < TOL
+
+
 def test_grid_and_degrid_small_workload(torch_cuda, api):
     torch = torch_cuda
     layers = 8
