@@ -435,7 +435,8 @@ mg_status mg_server_create(mg_server **srv, size_t hbm_budget_bytes, int32_t max
  * starting, so the caller need not synchronise.  Returns MG_ENOMEM (nothing
  * queued) if the job alone exceeds the budget, MG_EINVAL for bad arguments
  * (as mg_grid), MG_EBUSY while the server shuts down.  *job_id receives the
- * job's id. */
+ * job's id.  Every kernel kind of mg_grid is accepted (a W-stacking job's
+ * grid holds its stacked layers, as for mg_grid). */
 mg_status mg_server_submit(mg_server *srv, const mg_grid_desc *g, const mg_kernel_desc *k,
                            int64_t nrec, const void *uvw, mg_dtype uvw_dtype, const void *vis,
                            void *grid, hipEvent_t inputs_ready, uint64_t *job_id);

@@ -351,7 +351,7 @@ class Server:
         dt = _check_uvw(uvw)
         n = uvw.shape[0]
         _check_vis(vis, n, spec.npol)
-        _check_grid(grid_out, spec)
+        _check_grid(grid_out, spec, bank)
         # inputs are produced on torch's current stream: the job's stream waits
         # for an event recorded there (no host synchronisation)
         ev = torch.cuda.Event()

@@ -82,10 +82,12 @@ size_t job_footprint(const mg_grid_desc *g, const mg_kernel_desc *k, int64_t nre
                      mg_dtype uvw_dtype) {
     const size_t n = (size_t)nrec + kRecPad;
     const int np = k->kind == MG_KERNEL_WPROJ ? k->nplanes : 1;
-    const size_t tiles8 = (size_t)((g->nu + 7) / 8) * (size_t)((g->nv + 7) / 8);
+    // W-stacking: the layers are stacked along v, one plane of buckets
+    const size_t rows = (size_t)g->nv * (k->kind == MG_KERNEL_WSTACK ? (size_t)k->nplanes : 1u);
+    const size_t tiles8 = (size_t)((g->nu + 7) / 8) * ((rows + 7) / 8);
     const size_t nb = (size_t)np * tiles8;                      // buckets (tiles >= 8)
     const size_t caller = n * 3 * dtype_bytes(uvw_dtype) + n * g->npol * 8 +
-                          (size_t)g->npol * g->nu * g->nv * 8;
+                          (size_t)g->npol * g->nu * rows * 8;
     // the plan's table (no larger than the caller's) and its conjugate copy
     const size_t taps = (size_t)k->ntaps * dtype_bytes(k->tap_dtype) *
                         (k->kind == MG_KERNEL_WPROJ ? 4 : 1);
@@ -241,8 +243,8 @@ mg_status mg_server_submit(mg_server *s, const mg_grid_desc *g, const mg_kernel_
     if (nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
     if (!grid) return set_error(MG_EINVAL, "null grid");
     if (nrec < 0) return set_error(MG_EINVAL, "negative nrec");
-    if (k->kind == MG_KERNEL_WSTACK)
-        return set_error(MG_EUNSUPPORTED, "the server takes separable and W-projection jobs");
+    if (k->kind == MG_KERNEL_WSTACK && (k->nplanes < 1 || k->nplanes > 128))
+        return set_error(MG_EINVAL, "W-stacking layers must be in [1, 128]");
     if (k->kind == MG_KERNEL_WPROJ && (k->nplanes < 1 || k->nplanes > kMaxPlanes ||
                                        !k->plane_support || !k->plane_offset))
         return set_error(MG_EINVAL, "bad W-projection planes");

@@ -11,7 +11,8 @@ mg_grid, plans and mg_wstack_imager_*) against the oracle (oracle/wstack.py):
   * the W-stacking image (per-layer inverse FFT, screens, sum, correction)
     against the FP64 oracle chain over the central half of the field;
   * a point source with w terms, gridded, stacked and imaged on the device,
-    against the direct Fourier sum with the W-term."""
+    against the direct Fourier sum with the W-term;
+  * W-stacking jobs served by mg_server_* beside a separable job."""
 import numpy as np
 import pytest
 
@@ -143,6 +144,40 @@ def test_grid_and_degrid_small_workload(torch_cuda, api):
     err = H.rel_l2(out.cpu().numpy(), want)
     print(f"[wstack] plan degrid: rel-L2 {err:.2e}", flush=True)
     assert err < TOL
+
+
+def test_served_wstack_jobs_match_the_oracle(torch_cuda, api):
+    """W-stacking jobs through the server, alongside a plain separable job on
+    the same records: each served grid against the oracle."""
+    torch = torch_cuda
+    layers = 4
+    wl, uvw, dw = _small_wstack(layers)
+    vis = W.vis_normal(wl.nrec, 4, seed=84)
+    spec = H.grid_spec(wl)
+    uvw_d = torch.from_numpy(wl.uvw).cuda()
+    vis_d = torch.from_numpy(vis).cuda()
+    wbank = _bank(api, torch, wl, layers, dw)
+    sbank = api.KernelBank("separable", torch.from_numpy(wl.taps.astype(np.float32)).cuda(),
+                           support=wl.support)
+    g_w = [torch.zeros(4, layers, wl.n, wl.n, dtype=torch.complex64, device="cuda")
+           for _ in range(2)]
+    g_s = torch.zeros(4, wl.n, wl.n, dtype=torch.complex64, device="cuda")
+    with api.Server(16 << 30, max_slots=4, nstreams=3) as srv:
+        ids = [srv.submit(spec, wbank, uvw_d, vis_d, g_w[0]),
+               srv.submit(spec, sbank, uvw_d, vis_d, g_s),
+               srv.submit(spec, wbank, uvw_d, vis_d, g_w[1])]
+        for i in ids:
+            srv.wait(i)
+    torch.cuda.synchronize()
+    taps = H.oracle_taps(wl)
+    geom = H.oracle_geom(wl)
+    ref_w, _ = WS.grid_layers(geom, taps, uvw, vis, layers, 1 / dw)
+    ref_s, _ = oracle.grid(geom, taps, uvw, vis)
+    for g in g_w:
+        err = H.rel_l2(g.cpu().numpy(), ref_w)
+        print(f"[wstack] served, {layers} layers: rel-L2 {err:.2e}", flush=True)
+        assert err < TOL
+    assert H.rel_l2(g_s.cpu().numpy(), ref_s) < TOL
 
 
 def test_image_small_workload(torch_cuda, api):
