@@ -517,11 +517,79 @@ __global__ __launch_bounds__(256) void prune_columns_kernel(const float2 *__rest
     }
 }
 
+// The same map for a compile-time alpha.  A thread's J = 5 SZ + 1 outputs
+// need exactly 6 SZ input blocks, so the unrolled block loop has no exit
+// test and every block's alpha row loads are independent of the previous
+// block's multiply-adds (the loads run ahead); blocks past the thread's last
+// output wrap around the grid like the others and are never stored.  The
+// block index advances with a wrap instead of a division.
+template <int SZ, int ALPHA>
+__global__ __launch_bounds__(256) void prune_columns_fixed_kernel(const float2 *__restrict__ in,
+                                                                  float2 *__restrict__ out,
+                                                                  int64_t M, int32_t ncols,
+                                                                  const float *__restrict__ ztab) {
+    constexpr int J = 5 * SZ + 1;
+    constexpr int HALF = ALPHA * SZ / 2;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pol = blockIdx.z;
+    const int64_t Mb = M / ALPHA;                      // output rows
+    const int64_t j0 = (int64_t)blockIdx.y * J;
+    const int64_t j_end = min<int64_t>(j0 + J, Mb);
+    if (col >= ncols || j0 >= Mb) return;
+    const float2 *src = in + (size_t)pol * M * ncols + col;
+    float2 *dst = out + (size_t)pol * Mb * ncols + col;
+    float2 acc[SZ];
+#pragma unroll
+    for (int k = 0; k < SZ; ++k) acc[k] = make_float2(0.0f, 0.0f);
+    int64_t b = j0 - SZ / 2;
+    int64_t bw = b % Mb;                               // circular convolution
+    if (bw < 0) bw += Mb;
+    for (int it = 0; it < 6; ++it) {
+#pragma unroll
+        for (int t = 0; t < SZ; ++t) {
+            const float2 *row = src + (size_t)(bw * ALPHA) * ncols;
+            float2 x[ALPHA];
+#pragma unroll
+            for (int a = 0; a < ALPHA; ++a) x[a] = row[(size_t)a * ncols];
+#pragma unroll
+            for (int a = 0; a < ALPHA; ++a) {
+#pragma unroll
+                for (int s = 0; s < SZ; ++s) {
+                    const float w = ztab[ALPHA * (s - SZ / 2) + a + HALF];
+                    float2 &y = acc[((t - s - 1) % SZ + SZ) % SZ];
+                    y.x = fmaf(w, x[a].x, y.x);
+                    y.y = fmaf(w, x[a].y, y.y);
+                }
+            }
+            const int64_t jc = b - SZ / 2 + 1;         // complete output
+            if (jc >= j0 && jc < j_end) dst[(size_t)jc * ncols] = acc[t];
+            acc[t] = make_float2(0.0f, 0.0f);
+            ++b;
+            bw = (bw + 1 == Mb) ? 0 : bw + 1;
+        }
+    }
+}
+
 template <int SZ>
 void launch_prune(const float2 *in, float2 *out, int npol, int64_t M, int ncols, int alpha,
                   const float *ztab, hipStream_t stream) {
-    constexpr int J = 64;
     const int64_t Mb = M / alpha;
+    if (alpha == 2 || alpha == 4 || alpha == 8) {
+        constexpr int J = 5 * SZ + 1;
+        const dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)((Mb + J - 1) / J),
+                        (unsigned)npol);
+        if (alpha == 2)
+            hipLaunchKernelGGL((prune_columns_fixed_kernel<SZ, 2>), grid, dim3(256), 0, stream,
+                               in, out, M, ncols, ztab);
+        else if (alpha == 4)
+            hipLaunchKernelGGL((prune_columns_fixed_kernel<SZ, 4>), grid, dim3(256), 0, stream,
+                               in, out, M, ncols, ztab);
+        else
+            hipLaunchKernelGGL((prune_columns_fixed_kernel<SZ, 8>), grid, dim3(256), 0, stream,
+                               in, out, M, ncols, ztab);
+        return;
+    }
+    constexpr int J = 64;
     const dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)((Mb + J - 1) / J),
                     (unsigned)npol);
     hipLaunchKernelGGL(prune_columns_kernel<SZ>, grid, dim3(256), 0, stream, in, out, M, ncols,
