@@ -243,8 +243,9 @@ mg_status mg_server_submit(mg_server *s, const mg_grid_desc *g, const mg_kernel_
     if (nrec > 0 && !vis) return set_error(MG_EINVAL, "null vis");
     if (!grid) return set_error(MG_EINVAL, "null grid");
     if (nrec < 0) return set_error(MG_EINVAL, "negative nrec");
-    if (k->kind == MG_KERNEL_WSTACK && (k->nplanes < 1 || k->nplanes > 128))
-        return set_error(MG_EINVAL, "W-stacking layers must be in [1, 128]");
+    if (k->kind == MG_KERNEL_WSTACK &&
+        (k->nplanes < 1 || k->nplanes > 128 || (int64_t)k->nplanes * g->nv > 65535))
+        return set_error(MG_EINVAL, "W-stacking layers must be in [1, 128] with layers x nv <= 65535");
     if (k->kind == MG_KERNEL_WPROJ && (k->nplanes < 1 || k->nplanes > kMaxPlanes ||
                                        !k->plane_support || !k->plane_offset))
         return set_error(MG_EINVAL, "bad W-projection planes");

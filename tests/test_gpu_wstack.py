@@ -178,6 +178,15 @@ def test_served_wstack_jobs_match_the_oracle(torch_cuda, api):
         print(f"[wstack] served, {layers} layers: rel-L2 {err:.2e}", flush=True)
         assert err < TOL
     assert H.rel_l2(g_s.cpu().numpy(), ref_s) < TOL
+    # more stacked rows than the 16-bit cell halves hold: refused at submit
+    spec2 = api.GridSpec(16, 1024, 1, wl.beta, 1.0, 1.0)
+    bank2 = _bank(api, torch, wl, 65, dw)
+    u2 = torch.zeros(10, 3, dtype=torch.float64, device="cuda")
+    v2 = torch.zeros(10, 1, dtype=torch.complex64, device="cuda")
+    g2 = torch.zeros(1, 65, 1024, 16, dtype=torch.complex64, device="cuda")
+    with api.Server(1 << 30, max_slots=1, nstreams=1) as srv:
+        with pytest.raises(Exception, match="65535"):
+            srv.submit(spec2, bank2, u2, v2, g2)
 
 
 def test_image_small_workload(torch_cuda, api):
